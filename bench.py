@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Benchmark of the MSDA hot path on one MI355X.
+
+One step = the whole hot path over one batch: the forward kernel and the
+backward (grad_feat, grad_sampling_loc, grad_weights) on the 64-camera scene
+(64 cameras, 4 levels from a 256x448 image, C=256 in 8 groups, 900 anchors x
+13 keypoints), BF16 feature storage with FP32 arithmetic. Inputs are seeded
+synthetic tensors already resident in HBM when timing starts.
+
+Prints one JSON line: GSamples/s of forward+backward (one sample = one
+bilinear interpolation of all C channels at one (anchor, keypoint, camera,
+level)), the FP32-storage rate beside it, a roofline object for the dominant
+kernel (algorithmic bytes per launch / its event-timed duration, against the
+8 TB/s HBM peak) and the FP64 CPU oracle's rate on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cam64", choices=["cam64", "train16", "sparse4d"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage comparison")
+    ap.add_argument("--cpu-anchors", type=int, default=0,
+                    help="anchors in the oracle's timed sample (0 = all of them)")
+    return ap.parse_args()
+
+
+def bytes_per_sample(C, G, L, P, N, s):
+    """Algorithmic bytes one sample moves, per pass (the method's own traffic,
+    independent of the implementation): 4 corner rows of C elements of s bytes,
+    the sample's G weights, its share of the location (shared by L levels) and
+    of the anchor's output row (shared by P*N*L samples). The backward re-reads
+    the corners, scatters 4 corner contributions at the feature's precision,
+    reads weights and writes their gradient, reads the location and writes its
+    gradient, and reads grad_out."""
+    share_out = C * 4.0 / (P * N * L)
+    fwd = 4 * C * s + G * 4 + 8.0 / L + share_out
+    bwd = 4 * C * s + 4 * C * s + 2 * G * 4 + 2 * 8.0 / L + share_out
+    return fwd, bwd
+
+
+class HipEvents:
+    """hipEvent_t pairs through the HIP runtime torch has already loaded."""
+
+    def __init__(self):
+        self.hip = ctypes.CDLL("libamdhip64.so.7")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                 ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self):
+        e = ctypes.c_void_p()
+        if self.hip.hipEventCreate(ctypes.byref(e)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        return e
+
+    def elapsed_ms(self, a, b):
+        ms = ctypes.c_float()
+        if self.hip.hipEventElapsedTime(ctypes.byref(ms), a, b) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+    def destroy(self, e):
+        self.hip.hipEventDestroy(e)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("paper_2601_10819_amd/csrc/msda_kernels.hip", "paper_2601_10819_amd/csrc/msda_api.cpp"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, dtype: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        table = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    ent = table.get(f"{kernel}/{workload}/{dtype}")
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup):
+    """Time `steps` forward+backward steps; returns a dict of measurements."""
+    lib = ops._lib.load()
+    dev = "cuda"
+    feat = p.feat.to(feat_dtype).to(dev)
+    layout = ops.Layout(p.spatial_shapes, p.level_start_index, dev)
+    loc, w = p.sampling_loc.to(dev), p.weights.to(dev)
+    go = synth.grad_out_like(p, seed=1).to(dev)
+    out = torch.empty(p.batch, p.num_anchors, p.channels, device=dev)
+    ws_bytes = ops.backward_workspace_bytes(feat, layout, loc, w)
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev) if ws_bytes else None
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ops.forward(feat, layout, loc, w, out=out)
+        ops.backward(feat, layout, loc, w, go, workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+
+    ev = HipEvents()
+    pairs = [(ev.create(), ev.create(), ev.create(), ev.create()) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        f0, f1, b0, b1 = pairs[i]
+        ops._lib.check(lib.msda_set_kernel_events(f0, f1))
+        ops.forward(feat, layout, loc, w, out=out)
+        ops._lib.check(lib.msda_set_kernel_events(b0, b1))
+        ops.backward(feat, layout, loc, w, go, workspace=ws)
+        ops._lib.check(lib.msda_set_kernel_events(None, None))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fwd_ms = [ev.elapsed_ms(a, b) for a, b, _, _ in pairs]
+    bwd_ms = [ev.elapsed_ms(c, d) for _, _, c, d in pairs]
+    for pr in pairs:
+        for e in pr:
+            ev.destroy(e)
+    del stream
+    return {"total_s": t1 - t0, "fwd_kernel_ms": sum(fwd_ms) / steps,
+            "bwd_kernel_ms": sum(bwd_ms) / steps}
+
+
+def copy_bandwidth(torch, ops, nbytes=1 << 30, reps=10):
+    """Achievable streaming bandwidth (read + write) of the library's copy kernel."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    ops.stream_copy(dst, src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ops.stream_copy(dst, src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del src, dst
+    return 2 * nbytes / dt / 1e9
+
+
+def cpu_baseline(p, anchors):
+    """The FP64 oracle (as it stands) on the first `anchors` anchors of the
+    same workload, forward + full backward, BF16-widened features."""
+    import numpy as np
+    import torch
+    import oracle
+    oracle._load()
+    sub_loc = p.sampling_loc[:, :anchors].contiguous()
+    sub_w = p.weights[:, :anchors].contiguous()
+    feat = p.feat.to(torch.bfloat16).double().numpy()
+    go = np.random.default_rng(0).standard_normal((p.batch, anchors, p.channels))
+    t0 = time.perf_counter()
+    oracle.forward(feat, p.spatial_shapes, p.level_start_index, sub_loc, sub_w)
+    oracle.backward(feat, p.spatial_shapes, p.level_start_index, sub_loc, sub_w, go)
+    dt = time.perf_counter() - t0
+    samples = p.batch * anchors * p.num_points * p.num_cams * p.num_levels
+    return samples / dt / 1e9, dt, oracle.num_threads(), samples
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the MSDA path "
+              "here is single-GPU; camera sharding across GPUs is not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2601_10819_amd import ops, synth
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    ops._lib.load()
+
+    maker = {"cam64": synth.cam64, "train16": synth.train16,
+             "sparse4d": lambda: synth.sparse4d(seed=0)}[args.workload]
+    p = maker()
+    S = p.samples
+    print(f"# workload {p.name} {p.dims()} samples/step {S}", file=sys.stderr, flush=True)
+
+    bf = run_gpu(args, torch, ops, synth, p, torch.bfloat16, args.steps, args.warmup)
+    print(f"# bf16 done: {bf}", file=sys.stderr, flush=True)
+    ms_step = bf["total_s"] / args.steps * 1e3
+    value = S * args.steps / bf["total_s"] / 1e9
+
+    fp = None
+    if not args.no_fp32:
+        fp = run_gpu(args, torch, ops, synth, p, torch.float32, args.steps, args.warmup)
+        print(f"# fp32 done: {fp}", file=sys.stderr, flush=True)
+
+    C, G, L, P, N = p.channels, p.groups, p.num_levels, p.num_points, p.num_cams
+    fwd_b, bwd_b = bytes_per_sample(C, G, L, P, N, 2)
+    kern = "msda_bwd_kernel" if bf["bwd_kernel_ms"] >= bf["fwd_kernel_ms"] else "msda_fwd_kernel"
+    kms = bf["bwd_kernel_ms"] if kern == "msda_bwd_kernel" else bf["fwd_kernel_ms"]
+    kbytes = S * (bwd_b if kern == "msda_bwd_kernel" else fwd_b)
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    traffic = measured_traffic(kern, p.name, "bf16")
+
+    res = {
+        "metric": "MSDA fwd+bwd GSamples/s (64-camera scene, BF16 storage, FP32 math)",
+        "value": round(value, 4),
+        "unit": "GSamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": p.name, "batch": p.batch, "cameras": N, "levels": L,
+                   "level_shapes": [list(map(int, s)) for s in p.spatial_shapes[0].tolist()],
+                   "channels": C, "groups": G, "anchors": p.num_anchors, "keypoints": P,
+                   "samples_per_step": S},
+        "fwd_kernel_ms": round(bf["fwd_kernel_ms"], 4),
+        "bwd_kernel_ms": round(bf["bwd_kernel_ms"], 4),
+        "alg_hbm_frac_fwd_bwd": round(S * (fwd_b + bwd_b) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "alg_bytes_per_launch": int(kbytes)},
+    }
+    if fp is not None:
+        fp_ms = fp["total_s"] / args.steps * 1e3
+        res["fp32_ms_per_step"] = round(fp_ms, 4)
+        res["fp32_value"] = round(S * args.steps / fp["total_s"] / 1e9, 4)
+        res["bf16_speedup_vs_fp32"] = round(fp_ms / ms_step, 3)
+    res["copy_GBps"] = round(copy_bandwidth(torch, ops), 1)
+
+    if not args.no_cpu:
+        anchors = args.cpu_anchors or p.num_anchors
+        v, dt, cores, ns = cpu_baseline(p, anchors)
+        res["cpu_baseline"] = {"value": round(v, 6), "unit": "GSamples/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{p.name} anchors[0:{anchors}] ({ns} samples), FP64 "
+                                         f"forward + full backward, {dt:.1f} s"}
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * msda.h -- C ABI of the MI355X (gfx950) multi-scale deformable aggregation
+ * (MSDA) library, libmsda.so.
+ *
+ * The operator (paper Sec. 3.1 and Sec. 3.2; named and accelerated in
+ * Sec. 5.3): the keypoints of every 3D anchor are projected into every camera;
+ * at each projected point the camera's multi-level feature pyramid is sampled
+ * bilinearly, and the samples are summed with one weight per (keypoint,
+ * camera, level, channel group) into a single C-channel feature per anchor:
+ *
+ *   out[b,a,c] = sum_{p,n,l} weights[b,a,p,n,l,c/(C/G)] *
+ *                bilinear(feat[b, region(n,l)], u*W_nl - 0.5, v*H_nl - 0.5)[c]
+ *
+ * with (u, v) = sampling_loc[b,a,p,n], pixel centres at integer + 0.5, a
+ * neighbour outside the level contributing zero, and a sample skipped unless
+ * -1 < x < W and -1 < y < H.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layouts (row-major, contiguous, element strides implied):
+ *   feat               [B][R][C]          R rows per batch item, channels fastest;
+ *                                          FP32, BF16 or FP8-e4m3 (OCP e4m3fn)
+ *   spatial_shapes     [Ncam][L][2] int32 (H, W) of level l of camera n
+ *   level_start_index  [Ncam][L]   int32  first row of region (n, l) in a batch item
+ *   sampling_loc       [B][A][P][Ncam][2] FP32, (x, y) normalised so 0..1 spans the image
+ *   weights            [B][A][P][Ncam][L][G] FP32; channel c uses group c / (C/G)
+ *   out, grad_out      [B][A][C] FP32
+ *   grad_sampling_loc  like sampling_loc, grad_weights like weights (FP32)
+ *   grad_feat          like feat, in the feat dtype (FP32 or BF16)
+ * Pointers named "device" are HIP device memory; "host" pointers are read
+ * during the call only. The caller owns every buffer, including workspaces;
+ * the library never allocates, frees or synchronises on these calls, so they
+ * may be captured into a HIP graph. Outputs are overwritten, never
+ * accumulated into, and must not alias inputs. Out-of-range samples give exact
+ * zeros in every output. Work is enqueued on `stream` (a hipStream_t; NULL =
+ * the null stream) and the call returns before it completes.
+ *
+ * Errors: every argument is validated on the host before anything is
+ * enqueued; on failure nothing is launched, no output is touched, and the
+ * status says why (msda_last_error() has the message, thread-local, valid
+ * until the next call on the thread). A HIP launch error returns
+ * MSDA_ERR_HIP. Nothing aborts, nothing throws across the ABI. Device faults
+ * are reported by HIP asynchronously, at the caller's next synchronisation.
+ */
+#ifndef MSDA_H
+#define MSDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSDA_ABI_VERSION 1
+
+typedef enum msda_status {
+    MSDA_OK = 0,
+    MSDA_ERR_INVALID_ARGUMENT = 1, /* sizes, pointers or regions inconsistent      */
+    MSDA_ERR_UNSUPPORTED = 2,      /* valid request this build does not implement  */
+    MSDA_ERR_HIP = 3,              /* the HIP runtime reported an error            */
+    MSDA_ERR_WORKSPACE = 4         /* workspace missing, too small or misaligned   */
+} msda_status;
+
+typedef enum msda_dtype {
+    MSDA_F32 = 0,
+    MSDA_BF16 = 1,
+    MSDA_FP8_E4M3 = 2 /* OCP e4m3fn codes; value = decode(code) * level_scale[l] */
+} msda_dtype;
+
+/* msda_desc.flags */
+#define MSDA_DETERMINISTIC 1u /* backward: grad_feat reduced in a fixed order (no
+                                 float atomics); bitwise reproducible run to run */
+
+/* Launch shape. A zero field means "choose". */
+typedef struct msda_tile {
+    int32_t waves_per_anchor; /* wavefronts (64 lanes) sharing one anchor: 1, 2, 4, 8 */
+    int32_t chans_per_lane;   /* channels each lane owns: 4, 8 or 16                  */
+    int32_t anchors_per_block;/* reserved, must be 0 or 1                              */
+    int32_t reserved;
+} msda_tile;
+
+/* Sizes and options of one call. */
+typedef struct msda_desc {
+    int32_t batch;       /* B  >= 1                                              */
+    int32_t num_cams;    /* Ncam >= 1                                            */
+    int32_t num_levels;  /* L in 1..8                                            */
+    int32_t num_anchors; /* A >= 0 (0: nothing to do, outputs of size 0)         */
+    int32_t num_points;  /* P >= 1 keypoints per anchor                          */
+    int32_t channels;    /* C >= 1, C % groups == 0                              */
+    int32_t groups;      /* G >= 1                                               */
+    int32_t feat_dtype;  /* msda_dtype                                           */
+    int64_t rows;        /* R: rows of one batch item of feat                    */
+    /* host mirrors of spatial_shapes [Ncam][L][2] and level_start_index
+       [Ncam][L], used only to validate regions without reading the device */
+    const int32_t* host_spatial_shapes;
+    const int32_t* host_level_start_index;
+    const float* level_scale; /* device [L] FP32; FP8 only, else NULL        */
+    uint32_t flags;           /* MSDA_DETERMINISTIC ...                       */
+    const msda_tile* tile;    /* NULL = built-in choice                       */
+} msda_desc;
+
+/*
+ * Forward (paper Sec. 3.1/3.2): out = sum over keypoints, cameras and levels
+ * of weight * bilinear sample. All pointers device.
+ * Requirements: every region [start, start + H*W) lies in [0, R); H, W >= 1;
+ * R*C*sizeof(feat element) < 2^31 (one batch item is addressed with 32-bit
+ * offsets; larger inputs are split by the caller); feat 16-byte aligned.
+ * Returns INVALID_ARGUMENT / UNSUPPORTED as listed above, else OK.
+ */
+msda_status msda_forward(const void* feat, const int32_t* spatial_shapes,
+                         const int32_t* level_start_index, const float* sampling_loc,
+                         const float* weights, float* out, const msda_desc* desc,
+                         void* stream);
+
+/*
+ * Backward: gradients of <grad_out, out> with respect to feat, sampling_loc
+ * and weights (the analytic derivative of the forward; at an integer
+ * coordinate the right-hand derivative). Any of grad_feat,
+ * grad_sampling_loc, grad_weights may be NULL to skip it. grad_feat has the
+ * feat dtype; FP8 grad_feat is UNSUPPORTED. Accumulation is FP32; a BF16
+ * grad_feat is rounded once (to nearest even) from the FP32 sum.
+ * workspace: device, 256-byte aligned, at least
+ * msda_backward_workspace_size(desc) bytes (may be NULL when that is 0).
+ * Without MSDA_DETERMINISTIC, grad_feat is summed with float atomics: correct
+ * to rounding, but the last bits can vary run to run.
+ */
+msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
+                          const int32_t* level_start_index, const float* sampling_loc,
+                          const float* weights, const float* grad_out, void* grad_feat,
+                          float* grad_sampling_loc, float* grad_weights, void* workspace,
+                          size_t workspace_bytes, const msda_desc* desc, void* stream);
+
+/* Bytes of device workspace msda_backward needs for desc (0 if none). */
+size_t msda_backward_workspace_size(const msda_desc* desc);
+
+/*
+ * Per-level FP8 quantisation of an FP32 feat (the precision form's storage):
+ * scale_l = amax_l / 448 over every batch item, camera and channel of level l
+ * (1 when the level is all zero), code = round-to-nearest-even(clamp(x /
+ * scale_l, -448, 448)) in OCP e4m3fn. Rows in no region are written as 0.
+ * feat_f32 [B][R][C] device; codes [B][R][C] uint8 device; level_scale [L]
+ * FP32 device (written). workspace: device, >= msda_quantize_workspace_size.
+ */
+msda_status msda_quantize_fp8(const float* feat_f32, const int32_t* spatial_shapes,
+                              const int32_t* level_start_index, uint8_t* codes,
+                              float* level_scale, void* workspace, size_t workspace_bytes,
+                              const msda_desc* desc, void* stream);
+size_t msda_quantize_workspace_size(const msda_desc* desc);
+
+/*
+ * Streaming copy of `bytes` (multiple of 16) from src to dst, both device and
+ * 16-byte aligned: the achievable-bandwidth reference kernel used when
+ * reporting the fraction of HBM bandwidth the MSDA kernels reach.
+ */
+msda_status msda_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/*
+ * Benchmark instrumentation. While set on the calling thread, msda_forward
+ * and msda_backward record `start` (a hipEvent_t) on their stream just before
+ * their main MSDA kernel and `stop` just after it, so the kernel's own
+ * duration can be read with hipEventElapsedTime even when the call also
+ * launches helper kernels (zeroing, BF16 rounding). The events belong to the
+ * caller; NULL, NULL turns the hook off. Returns INVALID_ARGUMENT if exactly
+ * one of the two is NULL.
+ */
+msda_status msda_set_kernel_events(void* start, void* stop);
+
+const char* msda_last_error(void);
+int32_t msda_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSDA_H */

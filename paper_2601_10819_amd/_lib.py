@@ -1,0 +1,102 @@
+"""ctypes binding of libmsda.so (the C ABI declared in include/msda.h).
+
+Argument marshalling only: every step of the operator runs in the library's
+HIP kernels. Loading fails loudly when the library is missing; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmsda.so")
+
+MSDA_OK = 0
+MSDA_ERR_INVALID_ARGUMENT = 1
+MSDA_ERR_UNSUPPORTED = 2
+MSDA_ERR_HIP = 3
+MSDA_ERR_WORKSPACE = 4
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "UNSUPPORTED", 3: "HIP", 4: "WORKSPACE"}
+
+MSDA_F32 = 0
+MSDA_BF16 = 1
+MSDA_FP8_E4M3 = 2
+
+MSDA_DETERMINISTIC = 1
+
+ABI_VERSION = 1
+
+# Every symbol include/msda.h declares.
+EXPORTS = (
+    "msda_forward", "msda_backward", "msda_backward_workspace_size", "msda_quantize_fp8",
+    "msda_quantize_workspace_size", "msda_stream_copy", "msda_set_kernel_events",
+    "msda_last_error", "msda_abi_version",
+)
+
+
+class MsdaTile(ctypes.Structure):
+    _fields_ = [("waves_per_anchor", ctypes.c_int32), ("chans_per_lane", ctypes.c_int32),
+                ("anchors_per_block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class MsdaDesc(ctypes.Structure):
+    _fields_ = [
+        ("batch", ctypes.c_int32), ("num_cams", ctypes.c_int32), ("num_levels", ctypes.c_int32),
+        ("num_anchors", ctypes.c_int32), ("num_points", ctypes.c_int32),
+        ("channels", ctypes.c_int32), ("groups", ctypes.c_int32), ("feat_dtype", ctypes.c_int32),
+        ("rows", ctypes.c_int64),
+        ("host_spatial_shapes", ctypes.c_void_p), ("host_level_start_index", ctypes.c_void_p),
+        ("level_scale", ctypes.c_void_p), ("flags", ctypes.c_uint32),
+        ("tile", ctypes.POINTER(MsdaTile)),
+    ]
+
+
+class MSDAError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmsda.so and declare its signatures (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build the HIP library first "
+            "(python -m paper_2601_10819_amd.build)")
+    lib = ctypes.CDLL(path)
+    vp, sz, dp = ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(MsdaDesc)
+    lib.msda_forward.argtypes = [vp] * 6 + [dp, vp]
+    lib.msda_forward.restype = ctypes.c_int
+    lib.msda_backward.argtypes = [vp] * 10 + [sz, dp, vp]
+    lib.msda_backward.restype = ctypes.c_int
+    lib.msda_backward_workspace_size.argtypes = [dp]
+    lib.msda_backward_workspace_size.restype = sz
+    lib.msda_quantize_fp8.argtypes = [vp] * 6 + [sz, dp, vp]
+    lib.msda_quantize_fp8.restype = ctypes.c_int
+    lib.msda_quantize_workspace_size.argtypes = [dp]
+    lib.msda_quantize_workspace_size.restype = sz
+    lib.msda_stream_copy.argtypes = [vp, vp, sz, vp]
+    lib.msda_stream_copy.restype = ctypes.c_int
+    lib.msda_set_kernel_events.argtypes = [vp, vp]
+    lib.msda_set_kernel_events.restype = ctypes.c_int
+    lib.msda_last_error.argtypes = []
+    lib.msda_last_error.restype = ctypes.c_char_p
+    lib.msda_abi_version.argtypes = []
+    lib.msda_abi_version.restype = ctypes.c_int32
+    if lib.msda_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"libmsda ABI {lib.msda_abi_version()} != binding ABI {ABI_VERSION}")
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != MSDA_OK:
+        msg = load().msda_last_error()
+        raise MSDAError(status, msg.decode() if msg else "")

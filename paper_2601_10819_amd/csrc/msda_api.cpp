@@ -1,0 +1,346 @@
+// C-ABI layer of libmsda.so: host-side validation, launch-shape choice and
+// dispatch to the HIP kernels. Nothing here allocates, frees or synchronises.
+// The operator and the argument conventions are documented in include/msda.h.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+
+#include "../../include/msda.h"
+#include "msda_internal.h"
+
+namespace {
+
+thread_local std::string g_error;
+thread_local hipEvent_t g_ev_start = nullptr;
+thread_local hipEvent_t g_ev_stop = nullptr;
+
+// Record the benchmark hook's start/stop events around the main kernel.
+hipError_t mark(bool start, hipStream_t s) {
+    hipEvent_t e = start ? g_ev_start : g_ev_stop;
+    return e ? hipEventRecord(e, s) : hipSuccess;
+}
+
+msda_status fail(msda_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+
+msda_status ok() {
+    g_error.clear();
+    return MSDA_OK;
+}
+
+int elem_bytes(int32_t dtype) {
+    switch (dtype) {
+        case MSDA_F32: return 4;
+        case MSDA_BF16: return 2;
+        case MSDA_FP8_E4M3: return 1;
+        default: return 0;
+    }
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int log2i(int64_t v) {
+    int s = 0;
+    while ((int64_t(1) << s) < v) ++s;
+    return s;
+}
+
+// Channels per lane the kernels are built for, widest first (16-byte loads).
+const int* cpl_candidates(int32_t dtype) {
+    static const int f32[] = {4, 2, 1, 0};
+    static const int bf16[] = {8, 4, 2, 0};
+    static const int fp8[] = {16, 8, 4, 0};
+    switch (dtype) {
+        case MSDA_F32: return f32;
+        case MSDA_BF16: return bf16;
+        default: return fp8;
+    }
+}
+
+bool cpl_fits(int cpl, int32_t C, int32_t G) {
+    if (cpl <= 0 || C % cpl) return false;
+    const int64_t lps = C / cpl;
+    if (!is_pow2(lps) || lps > 64) return false;
+    const int32_t cpg = C / G;
+    return cpg % cpl == 0 && is_pow2(cpg / cpl);
+}
+
+bool cpl_is_candidate(int cpl, int32_t dtype) {
+    for (const int* c = cpl_candidates(dtype); *c; ++c)
+        if (*c == cpl) return true;
+    return false;
+}
+
+// Sizes, dtype and the (camera, level) regions, checked against the host
+// mirrors. Shared by the operator and the quantiser.
+msda_status check_regions(const msda_desc* d, int64_t* batch_bytes_out) {
+    if (!d) return fail(MSDA_ERR_INVALID_ARGUMENT, "desc is NULL");
+    if (d->batch < 1 || d->num_cams < 1 || d->num_levels < 1 || d->num_anchors < 0 ||
+        d->num_points < 1 || d->channels < 1 || d->groups < 1 || d->rows < 1)
+        return fail(MSDA_ERR_INVALID_ARGUMENT,
+                    "sizes must be positive (B=%d Ncam=%d L=%d A=%d P=%d C=%d G=%d R=%lld)",
+                    d->batch, d->num_cams, d->num_levels, d->num_anchors, d->num_points,
+                    d->channels, d->groups, (long long)d->rows);
+    if (d->num_levels > 8) return fail(MSDA_ERR_UNSUPPORTED, "at most 8 levels (L=%d)", d->num_levels);
+    if (d->channels % d->groups)
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "channels (%d) not divisible by groups (%d)",
+                    d->channels, d->groups);
+    const int eb = elem_bytes(d->feat_dtype);
+    if (!eb) return fail(MSDA_ERR_INVALID_ARGUMENT, "unknown feat_dtype %d", d->feat_dtype);
+    if (d->feat_dtype == MSDA_FP8_E4M3 && !d->level_scale)
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "FP8 features need level_scale");
+    if (!d->host_spatial_shapes || !d->host_level_start_index)
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "host mirrors of spatial_shapes/level_start_index are NULL");
+    const int64_t NL = (int64_t)d->num_cams * d->num_levels;
+    if (NL > 1024)
+        return fail(MSDA_ERR_UNSUPPORTED, "too many (camera, level) regions (%lld > 1024)",
+                    (long long)NL);
+    for (int64_t i = 0; i < NL; ++i) {
+        const int64_t H = d->host_spatial_shapes[2 * i], W = d->host_spatial_shapes[2 * i + 1];
+        const int64_t s0 = d->host_level_start_index[i];
+        if (H < 1 || W < 1 || H > 32768 || W > 32768)
+            return fail(MSDA_ERR_INVALID_ARGUMENT, "region %lld: H=%lld W=%lld out of [1, 32768]",
+                        (long long)i, (long long)H, (long long)W);
+        if (s0 < 0 || s0 + H * W > d->rows)
+            return fail(MSDA_ERR_INVALID_ARGUMENT,
+                        "region %lld: rows [%lld, %lld) outside [0, R=%lld)", (long long)i,
+                        (long long)s0, (long long)(s0 + H * W), (long long)d->rows);
+    }
+    const int64_t batch_bytes = d->rows * d->channels * (int64_t)eb;
+    if (batch_bytes > 0x7ffffff0LL)
+        return fail(MSDA_ERR_UNSUPPORTED, "one batch item of feat is %lld bytes (limit 2^31 - 16)",
+                    (long long)batch_bytes);
+    if ((int64_t)d->batch * d->num_anchors > 0x7fffffffLL)
+        return fail(MSDA_ERR_UNSUPPORTED, "batch * anchors exceeds 2^31 - 1");
+    *batch_bytes_out = batch_bytes;
+    return MSDA_OK;
+}
+
+// Validates everything and chooses the launch shape; fills `a` except pointers.
+msda_status prepare(const msda_desc* d, msda::OpArgs* a, int* cpl_out, int* waves_out) {
+    int64_t batch_bytes = 0;
+    msda_status st = check_regions(d, &batch_bytes);
+    if (st != MSDA_OK) return st;
+    int cpl = 0;
+    if (d->tile && d->tile->chans_per_lane) {
+        cpl = d->tile->chans_per_lane;
+        if (!cpl_is_candidate(cpl, d->feat_dtype) || !cpl_fits(cpl, d->channels, d->groups))
+            return fail(MSDA_ERR_UNSUPPORTED, "chans_per_lane=%d does not fit C=%d G=%d dtype=%d",
+                        cpl, d->channels, d->groups, d->feat_dtype);
+    } else {
+        for (const int* c = cpl_candidates(d->feat_dtype); *c; ++c)
+            if (cpl_fits(*c, d->channels, d->groups)) { cpl = *c; break; }
+        if (!cpl)
+            return fail(MSDA_ERR_UNSUPPORTED,
+                        "no lane layout for C=%d G=%d: need C/k a power of two <= 64 and "
+                        "C/G/k a power of two for k in the dtype's lane widths",
+                        d->channels, d->groups);
+    }
+    if (d->tile && d->tile->anchors_per_block > 1)
+        return fail(MSDA_ERR_UNSUPPORTED, "anchors_per_block > 1 is not implemented");
+
+    a->B = d->batch;
+    a->N = d->num_cams;
+    a->L = d->num_levels;
+    a->A = d->num_anchors;
+    a->P = d->num_points;
+    a->C = d->channels;
+    a->G = d->groups;
+    a->R = d->rows;
+    a->batch_bytes = (uint32_t)batch_bytes;
+    a->lps_shift = log2i(d->channels / cpl);
+    a->pairs_per_chunk = msda::max_pairs_per_chunk(d->num_levels, d->groups);
+
+    const int64_t npairs = (int64_t)d->num_points * d->num_cams;
+    const int64_t nchunks = (npairs + a->pairs_per_chunk - 1) / a->pairs_per_chunk;
+    int waves = 0;
+    if (d->tile && d->tile->waves_per_anchor) {
+        waves = d->tile->waves_per_anchor;
+        if (!is_pow2(waves) || waves > 8)
+            return fail(MSDA_ERR_UNSUPPORTED, "waves_per_anchor=%d not in {1,2,4,8}", waves);
+    } else {
+        // Aim for about 8 waves per SIMD across the chip (256 CUs x 4 SIMDs),
+        // but no more waves than the anchor has staging chunks.
+        const int64_t blocks = (int64_t)d->batch * d->num_anchors;
+        waves = 1;
+        while (waves < 8 && blocks * waves * 2 <= 8192 && waves * 2 <= nchunks) waves *= 2;
+    }
+    const size_t lds = msda::lds_bytes_for(*a, waves);
+    if (lds > 65536)
+        return fail(MSDA_ERR_UNSUPPORTED, "launch needs %zu bytes of LDS (limit 65536)", lds);
+    *cpl_out = cpl;
+    *waves_out = waves;
+    return MSDA_OK;
+}
+
+msda_status hip_fail(hipError_t e, const char* what) {
+    return fail(MSDA_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t n) { return ((uintptr_t)p % n) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int32_t msda_abi_version(void) { return MSDA_ABI_VERSION; }
+
+msda_status msda_set_kernel_events(void* start, void* stop) {
+    if ((start == nullptr) != (stop == nullptr))
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "give both events or neither");
+    g_ev_start = static_cast<hipEvent_t>(start);
+    g_ev_stop = static_cast<hipEvent_t>(stop);
+    return ok();
+}
+
+const char* msda_last_error(void) { return g_error.c_str(); }
+
+msda_status msda_forward(const void* feat, const int32_t* spatial_shapes,
+                         const int32_t* level_start_index, const float* sampling_loc,
+                         const float* weights, float* out, const msda_desc* desc, void* stream) {
+    msda::OpArgs a = {};
+    int cpl = 0, waves = 0;
+    msda_status st = prepare(desc, &a, &cpl, &waves);
+    if (st != MSDA_OK) return st;
+    if (!feat || !spatial_shapes || !level_start_index || !sampling_loc || !weights || !out)
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "a required device pointer is NULL");
+    if (!aligned(feat, 16)) return fail(MSDA_ERR_UNSUPPORTED, "feat must be 16-byte aligned");
+    if (a.A == 0) return ok();
+    a.feat = feat;
+    a.shapes = spatial_shapes;
+    a.starts = level_start_index;
+    a.loc = sampling_loc;
+    a.w = weights;
+    a.level_scale = desc->feat_dtype == MSDA_FP8_E4M3 ? desc->level_scale : nullptr;
+    a.out = out;
+    const hipStream_t s = (hipStream_t)stream;
+    hipError_t e = mark(true, s);
+    if (e == hipSuccess)
+        e = msda::launch_forward(a, desc->feat_dtype, cpl, waves, msda::lds_bytes_for(a, waves), s);
+    if (e == hipSuccess) e = mark(false, s);
+    if (e != hipSuccess) return hip_fail(e, "msda_forward launch");
+    return ok();
+}
+
+size_t msda_backward_workspace_size(const msda_desc* d) {
+    if (!d || d->batch < 1 || d->rows < 1 || d->channels < 1) return 0;
+    if (d->feat_dtype == MSDA_BF16)   // FP32 accumulator for grad_feat
+        return (size_t)d->batch * (size_t)d->rows * (size_t)d->channels * sizeof(float);
+    return 0;
+}
+
+msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
+                          const int32_t* level_start_index, const float* sampling_loc,
+                          const float* weights, const float* grad_out, void* grad_feat,
+                          float* grad_sampling_loc, float* grad_weights, void* workspace,
+                          size_t workspace_bytes, const msda_desc* desc, void* stream) {
+    msda::OpArgs a = {};
+    int cpl = 0, waves = 0;
+    msda_status st = prepare(desc, &a, &cpl, &waves);
+    if (st != MSDA_OK) return st;
+    if (!feat || !spatial_shapes || !level_start_index || !sampling_loc || !weights || !grad_out)
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "a required device pointer is NULL");
+    if (!aligned(feat, 16)) return fail(MSDA_ERR_UNSUPPORTED, "feat must be 16-byte aligned");
+    if (grad_feat && desc->feat_dtype == MSDA_FP8_E4M3)
+        return fail(MSDA_ERR_UNSUPPORTED, "grad_feat for FP8 features is not supported");
+    if (desc->feat_dtype == MSDA_FP8_E4M3)
+        return fail(MSDA_ERR_UNSUPPORTED, "the backward takes FP32 or BF16 features");
+    if (desc->flags & MSDA_DETERMINISTIC)
+        return fail(MSDA_ERR_UNSUPPORTED, "deterministic grad_feat is not available in this build");
+    const size_t need = grad_feat ? msda_backward_workspace_size(desc) : 0;
+    if (need) {
+        if (!workspace || workspace_bytes < need)
+            return fail(MSDA_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
+                        workspace ? workspace_bytes : (size_t)0);
+        if (!aligned(workspace, 256))
+            return fail(MSDA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    }
+    if (grad_feat && !aligned(grad_feat, 16))
+        return fail(MSDA_ERR_UNSUPPORTED, "grad_feat must be 16-byte aligned");
+
+    const hipStream_t s = (hipStream_t)stream;
+    const size_t gf_elems = (size_t)a.B * (size_t)a.R * (size_t)a.C;
+    float* acc = nullptr;
+    if (grad_feat) {
+        acc = desc->feat_dtype == MSDA_F32 ? static_cast<float*>(grad_feat)
+                                           : static_cast<float*>(workspace);
+        hipError_t e = msda::launch_fill_zero(acc, gf_elems * sizeof(float), s);
+        if (e != hipSuccess) return hip_fail(e, "zero grad_feat accumulator");
+    }
+    if (a.A > 0) {
+        a.feat = feat;
+        a.shapes = spatial_shapes;
+        a.starts = level_start_index;
+        a.loc = sampling_loc;
+        a.w = weights;
+        a.grad_out = grad_out;
+        a.gfeat_acc = acc;
+        a.grad_loc = grad_sampling_loc;
+        a.grad_w = grad_weights;
+        hipError_t e = mark(true, s);
+        if (e == hipSuccess)
+            e = msda::launch_backward(a, desc->feat_dtype, cpl, waves,
+                                      msda::lds_bytes_for(a, waves), s);
+        if (e == hipSuccess) e = mark(false, s);
+        if (e != hipSuccess) return hip_fail(e, "msda_backward launch");
+    }
+    if (grad_feat && desc->feat_dtype == MSDA_BF16) {
+        const hipError_t e =
+            msda::launch_f32_to_bf16(acc, static_cast<uint16_t*>(grad_feat), gf_elems, s);
+        if (e != hipSuccess) return hip_fail(e, "round grad_feat to bf16");
+    }
+    return ok();
+}
+
+size_t msda_quantize_workspace_size(const msda_desc* d) {
+    return d ? (size_t)(d->num_levels > 0 ? d->num_levels : 0) * sizeof(uint32_t) : 0;
+}
+
+msda_status msda_quantize_fp8(const float* feat_f32, const int32_t* spatial_shapes,
+                              const int32_t* level_start_index, uint8_t* codes,
+                              float* level_scale, void* workspace, size_t workspace_bytes,
+                              const msda_desc* desc, void* stream) {
+    if (!desc) return fail(MSDA_ERR_INVALID_ARGUMENT, "desc is NULL");
+    msda_desc d = *desc;
+    d.feat_dtype = MSDA_F32;            // the input is FP32
+    d.level_scale = nullptr;
+    int64_t batch_bytes = 0;
+    msda_status st = check_regions(&d, &batch_bytes);
+    if (st != MSDA_OK) return st;
+    if (!feat_f32 || !spatial_shapes || !level_start_index || !codes || !level_scale)
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "a required device pointer is NULL");
+    if (!workspace || workspace_bytes < msda_quantize_workspace_size(desc))
+        return fail(MSDA_ERR_WORKSPACE, "quantize workspace too small");
+    if (!aligned(workspace, 4)) return fail(MSDA_ERR_WORKSPACE, "workspace must be 4-byte aligned");
+    if (!aligned(codes, 4)) return fail(MSDA_ERR_INVALID_ARGUMENT, "codes must be 4-byte aligned");
+    const hipStream_t s = (hipStream_t)stream;
+    // rows in no region read as code 0
+    hipError_t e = msda::launch_fill_zero(codes, (size_t)d.batch * d.rows * d.channels, s);
+    if (e != hipSuccess) return hip_fail(e, "zero codes");
+    e = msda::launch_quantize_fp8(feat_f32, spatial_shapes, level_start_index, d.batch,
+                                  d.num_cams, d.num_levels, d.rows, d.channels, codes,
+                                  level_scale, static_cast<uint32_t*>(workspace), s);
+    if (e != hipSuccess) return hip_fail(e, "msda_quantize_fp8 launch");
+    return ok();
+}
+
+msda_status msda_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src) return fail(MSDA_ERR_INVALID_ARGUMENT, "NULL pointer");
+    if (bytes % 16 || !aligned(dst, 16) || !aligned(src, 16))
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "copy needs 16-byte aligned pointers and size");
+    const hipError_t e = msda::launch_stream_copy(dst, src, bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "msda_stream_copy launch");
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+"""PyTorch-facing entry points of the MSDA library.
+
+PyTorch supplies device memory and the current HIP stream; the computation is
+the library's (libmsda.so, via ctypes). The operator is multi-scale deformable
+aggregation (paper Sec. 3.1 / Sec. 3.2, accelerated in Sec. 5.3):
+
+    out[b, a, :] = sum over keypoints p, cameras n, levels l of
+                   weights[b, a, p, n, l, group] * bilinear(feat region (n, l), loc[b, a, p, n])
+
+Layouts are those of include/msda.h. ``Layout`` carries the per-(camera,
+level) geometry both on the device (read by the kernels) and on the host
+(validated by the library without a device read).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_DTYPES = {torch.float32: _lib.MSDA_F32, torch.bfloat16: _lib.MSDA_BF16,
+           torch.float8_e4m3fn: _lib.MSDA_FP8_E4M3, torch.uint8: _lib.MSDA_FP8_E4M3}
+
+
+class Layout:
+    """Geometry of the feature rows: spatial_shapes [Ncam, L, 2] (H, W) and
+    level_start_index [Ncam, L], kept on the host and on `device`."""
+
+    def __init__(self, spatial_shapes, level_start_index, device="cuda"):
+        hs = torch.as_tensor(spatial_shapes).detach().to("cpu", torch.int32).contiguous()
+        hl = torch.as_tensor(level_start_index).detach().to("cpu", torch.int32).contiguous()
+        if hs.dim() != 3 or hs.shape[2] != 2 or hl.shape != hs.shape[:2]:
+            raise ValueError(f"bad geometry shapes {tuple(hs.shape)} / {tuple(hl.shape)}")
+        self.host_shapes = hs.numpy().copy()
+        self.host_starts = hl.numpy().copy()
+        self.shapes = hs.to(device)
+        self.starts = hl.to(device)
+        self.num_cams, self.num_levels = int(hs.shape[0]), int(hs.shape[1])
+
+    @property
+    def rows_needed(self) -> int:
+        h, w = self.host_shapes[..., 0].astype(np.int64), self.host_shapes[..., 1].astype(np.int64)
+        return int((self.host_starts + h * w).max())
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need_cuda_contig(name, t, dtype=None):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+def make_desc(feat: torch.Tensor, layout: Layout, sampling_loc: torch.Tensor,
+              weights: torch.Tensor, level_scale: Optional[torch.Tensor] = None,
+              deterministic: bool = False, tile: Optional[dict] = None):
+    """Build the msda_desc for these tensors (shapes are checked here and,
+    authoritatively, by the library)."""
+    if feat.dim() != 3 or sampling_loc.dim() != 5 or weights.dim() != 6:
+        raise ValueError("feat [B,R,C], sampling_loc [B,A,P,Ncam,2], weights [B,A,P,Ncam,L,G]")
+    B, R, C = feat.shape
+    _, A, P, N, two = sampling_loc.shape
+    if two != 2 or sampling_loc.shape[0] != B or N != layout.num_cams:
+        raise ValueError(f"sampling_loc shape {tuple(sampling_loc.shape)} does not match")
+    if weights.shape[:5] != (B, A, P, N, layout.num_levels):
+        raise ValueError(f"weights shape {tuple(weights.shape)} does not match")
+    if feat.dtype not in _DTYPES:
+        raise ValueError(f"unsupported feat dtype {feat.dtype}")
+    d = _lib.MsdaDesc()
+    d.batch, d.num_cams, d.num_levels = B, N, layout.num_levels
+    d.num_anchors, d.num_points, d.channels = A, P, C
+    d.groups = weights.shape[5]
+    d.feat_dtype = _DTYPES[feat.dtype]
+    d.rows = R
+    d.host_spatial_shapes = layout.host_shapes.ctypes.data
+    d.host_level_start_index = layout.host_starts.ctypes.data
+    d.level_scale = level_scale.data_ptr() if level_scale is not None else None
+    d.flags = _lib.MSDA_DETERMINISTIC if deterministic else 0
+    keep = [layout]
+    if tile:
+        t = _lib.MsdaTile(int(tile.get("waves_per_anchor", 0)), int(tile.get("chans_per_lane", 0)),
+                          int(tile.get("anchors_per_block", 0)), 0)
+        keep.append(t)
+        d.tile = ctypes.pointer(t)
+    d._keep = keep        # host arrays must outlive the call
+    return d
+
+
+def forward(feat, layout: Layout, sampling_loc, weights, level_scale=None, tile=None,
+            out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """out [B, A, C] FP32 = MSDA(feat, loc, weights) on the current stream."""
+    lib = _lib.load()
+    _need_cuda_contig("feat", feat)
+    _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
+    _need_cuda_contig("weights", weights, torch.float32)
+    if level_scale is not None:
+        _need_cuda_contig("level_scale", level_scale, torch.float32)
+    d = make_desc(feat, layout, sampling_loc, weights, level_scale, tile=tile)
+    if out is None:
+        out = torch.empty(d.batch, d.num_anchors, d.channels, device=feat.device,
+                          dtype=torch.float32)
+    _lib.check(lib.msda_forward(_ptr(feat), _ptr(layout.shapes), _ptr(layout.starts),
+                                _ptr(sampling_loc), _ptr(weights), _ptr(out), ctypes.byref(d),
+                                _stream(stream)))
+    return out
+
+
+def backward_workspace_bytes(feat, layout, sampling_loc, weights, deterministic=False) -> int:
+    d = make_desc(feat, layout, sampling_loc, weights, deterministic=deterministic)
+    return int(_lib.load().msda_backward_workspace_size(ctypes.byref(d)))
+
+
+def backward(feat, layout: Layout, sampling_loc, weights, grad_out,
+             need_feat=True, need_loc=True, need_w=True, deterministic=False, tile=None,
+             workspace: Optional[torch.Tensor] = None, stream=None
+             ) -> Tuple[Optional[torch.Tensor], Optional[torch.Tensor], Optional[torch.Tensor]]:
+    """(grad_feat, grad_sampling_loc, grad_weights); an unrequested one is None."""
+    lib = _lib.load()
+    _need_cuda_contig("feat", feat)
+    _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
+    _need_cuda_contig("weights", weights, torch.float32)
+    _need_cuda_contig("grad_out", grad_out, torch.float32)
+    d = make_desc(feat, layout, sampling_loc, weights, deterministic=deterministic, tile=tile)
+    gf = torch.empty_like(feat) if need_feat else None
+    gl = torch.empty_like(sampling_loc) if need_loc else None
+    gw = torch.empty_like(weights) if need_w else None
+    ws_bytes = int(lib.msda_backward_workspace_size(ctypes.byref(d))) if need_feat else 0
+    if ws_bytes and (workspace is None or workspace.numel() * workspace.element_size() < ws_bytes):
+        workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=feat.device)
+    ws_ptr, ws_len = None, 0
+    if workspace is not None and ws_bytes:
+        base = workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        ws_ptr = ctypes.c_void_p(aligned)
+        ws_len = workspace.numel() * workspace.element_size() - (aligned - base)
+    _lib.check(lib.msda_backward(_ptr(feat), _ptr(layout.shapes), _ptr(layout.starts),
+                                 _ptr(sampling_loc), _ptr(weights), _ptr(grad_out), _ptr(gf),
+                                 _ptr(gl), _ptr(gw), ws_ptr, ws_len, ctypes.byref(d),
+                                 _stream(stream)))
+    return gf, gl, gw
+
+
+def quantize_fp8(feat_f32: torch.Tensor, layout: Layout, stream=None):
+    """Per-level FP8 e4m3 quantisation on the device: (codes uint8 [B,R,C],
+    level_scale float32 [L]) with scale_l = amax_l / 448."""
+    lib = _lib.load()
+    _need_cuda_contig("feat", feat_f32, torch.float32)
+    B, R, C = feat_f32.shape
+    d = _lib.MsdaDesc()
+    d.batch, d.num_cams, d.num_levels = B, layout.num_cams, layout.num_levels
+    d.num_anchors, d.num_points, d.channels, d.groups = 0, 1, C, 1
+    d.feat_dtype, d.rows = _lib.MSDA_F32, R
+    d.host_spatial_shapes = layout.host_shapes.ctypes.data
+    d.host_level_start_index = layout.host_starts.ctypes.data
+    codes = torch.empty(B, R, C, dtype=torch.uint8, device=feat_f32.device)
+    scales = torch.empty(layout.num_levels, dtype=torch.float32, device=feat_f32.device)
+    ws = torch.empty(max(16, int(lib.msda_quantize_workspace_size(ctypes.byref(d)))),
+                     dtype=torch.uint8, device=feat_f32.device)
+    _lib.check(lib.msda_quantize_fp8(_ptr(feat_f32), _ptr(layout.shapes), _ptr(layout.starts),
+                                     _ptr(codes), _ptr(scales), _ptr(ws), ws.numel(),
+                                     ctypes.byref(d), _stream(stream)))
+    return codes, scales
+
+
+def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
+    """Plain streaming copy kernel (the achievable-bandwidth reference)."""
+    lib = _lib.load()
+    n = src.numel() * src.element_size()
+    _lib.check(lib.msda_stream_copy(_ptr(dst), _ptr(src), n, _stream(stream)))
+
+
+class MSDAFunction(torch.autograd.Function):
+    """Differentiable MSDA: forward and backward are the library's kernels.
+    No gradient flows to the geometry or to the FP8 level scales."""
+
+    @staticmethod
+    def forward(ctx, feat, sampling_loc, weights, layout, level_scale, deterministic, tile):
+        out = forward(feat, layout, sampling_loc, weights, level_scale=level_scale, tile=tile)
+        ctx.save_for_backward(feat, sampling_loc, weights)
+        ctx.layout, ctx.deterministic, ctx.tile = layout, deterministic, tile
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        feat, loc, w = ctx.saved_tensors
+        nf, nl, nw = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
+        gf = gl = gw = None
+        if nf or nl or nw:
+            gf, gl, gw = backward(feat, ctx.layout, loc, w, grad_out.contiguous(),
+                                  need_feat=nf, need_loc=nl, need_w=nw,
+                                  deterministic=ctx.deterministic, tile=ctx.tile)
+        return gf, gl, gw, None, None, None, None
+
+
+def msda(feat, layout: Layout, sampling_loc, weights, level_scale=None, deterministic=False,
+         tile=None):
+    """Autograd-aware MSDA."""
+    return MSDAFunction.apply(feat, sampling_loc, weights, layout, level_scale, deterministic, tile)

@@ -1,0 +1,190 @@
+"""The C ABI: the library loads, exports every symbol include/msda.h declares,
+and rejects bad arguments on the host before anything is launched. These
+tests pass fake device addresses and only exercise failure paths (plus the
+empty A=0 case, which launches nothing), so they run without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2601_10819_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x7f0000000000           # 16-byte aligned stand-in for a device address
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "msda.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(msda_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = declared_symbols()
+    assert "msda_forward" in syms and "msda_backward" in syms
+    for s in syms:
+        assert hasattr(lib, s), f"libmsda.so does not export {s}"
+    assert set(syms) == set(_lib.EXPORTS)
+    assert lib.msda_abi_version() == _lib.ABI_VERSION
+
+
+class Geo:
+    def __init__(self, ncam=2, levels=((8, 12), (4, 6)), rows=None):
+        shapes, starts, r = [], [], 0
+        for _ in range(ncam):
+            for h, w in levels:
+                shapes.append((h, w))
+                starts.append(r)
+                r += h * w
+        self.shapes = np.array(shapes, dtype=np.int32).reshape(ncam, len(levels), 2)
+        self.starts = np.array(starts, dtype=np.int32).reshape(ncam, len(levels))
+        self.rows = r if rows is None else rows
+
+
+def desc(geo, B=1, A=4, P=3, C=32, G=4, dtype=_lib.MSDA_F32, scale=None, flags=0, tile=None):
+    d = _lib.MsdaDesc()
+    d.batch, d.num_cams, d.num_levels = B, geo.shapes.shape[0], geo.shapes.shape[1]
+    d.num_anchors, d.num_points, d.channels, d.groups = A, P, C, G
+    d.feat_dtype, d.rows = dtype, geo.rows
+    d.host_spatial_shapes = geo.shapes.ctypes.data
+    d.host_level_start_index = geo.starts.ctypes.data
+    d.level_scale = scale
+    d.flags = flags
+    if tile is not None:
+        d._t = _lib.MsdaTile(*tile)
+        d.tile = ctypes.pointer(d._t)
+    d._geo = geo
+    return d
+
+
+def fwd(lib, d, feat=FAKE, out=FAKE + 4096):
+    return lib.msda_forward(feat, FAKE, FAKE, FAKE, FAKE, out, ctypes.byref(d), None)
+
+
+def bwd(lib, d, grad_feat=FAKE + 8192, ws=None, ws_bytes=0, feat=FAKE):
+    return lib.msda_backward(feat, FAKE, FAKE, FAKE, FAKE, FAKE, grad_feat, FAKE, FAKE, ws,
+                             ws_bytes, ctypes.byref(d), None)
+
+
+def expect(lib, status, want, needle=None):
+    assert status == want, (status, lib.msda_last_error())
+    msg = lib.msda_last_error().decode()
+    assert msg, "a failure must leave a message"
+    if needle:
+        assert needle in msg, msg
+
+
+INV, UNS, WS = _lib.MSDA_ERR_INVALID_ARGUMENT, _lib.MSDA_ERR_UNSUPPORTED, _lib.MSDA_ERR_WORKSPACE
+
+
+def test_null_desc_and_pointers(lib):
+    expect(lib, lib.msda_forward(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None, None), INV, "desc")
+    d = desc(Geo())
+    expect(lib, fwd(lib, d, feat=None), INV, "NULL")
+    expect(lib, fwd(lib, d, out=None), INV, "NULL")
+    d.host_spatial_shapes = None
+    expect(lib, fwd(lib, d), INV, "host mirrors")
+
+
+@pytest.mark.parametrize("field,value", [("batch", 0), ("num_cams", 0), ("num_levels", 0),
+                                         ("num_anchors", -1), ("num_points", 0), ("channels", 0),
+                                         ("groups", 0), ("rows", 0), ("batch", -3)])
+def test_nonpositive_sizes(lib, field, value):
+    d = desc(Geo())
+    setattr(d, field, value)
+    expect(lib, fwd(lib, d), INV)
+
+
+def test_channels_not_divisible_by_groups(lib):
+    expect(lib, fwd(lib, desc(Geo(), C=30, G=4)), INV, "divisible")
+
+
+def test_region_outside_rows(lib):
+    g = Geo()
+    g.rows -= 1
+    expect(lib, fwd(lib, desc(g)), INV, "outside")
+    g = Geo()
+    g.starts[1, 0] = -5
+    expect(lib, fwd(lib, desc(g)), INV, "outside")
+
+
+def test_bad_level_shape(lib):
+    g = Geo()
+    g.shapes[0, 1, 1] = 0
+    expect(lib, fwd(lib, desc(g)), INV, "H=")
+    g = Geo()
+    g.shapes[1, 0, 0] = -2
+    expect(lib, fwd(lib, desc(g)), INV)
+
+
+def test_unknown_dtype_and_fp8_scale(lib):
+    expect(lib, fwd(lib, desc(Geo(), dtype=7)), INV, "dtype")
+    expect(lib, fwd(lib, desc(Geo(), dtype=_lib.MSDA_FP8_E4M3, C=64)), INV, "level_scale")
+
+
+def test_unsupported_requests(lib):
+    expect(lib, fwd(lib, desc(Geo(), C=96, G=3)), UNS, "lane layout")
+    expect(lib, fwd(lib, desc(Geo(levels=tuple((2, 2) for _ in range(9))))), UNS, "levels")
+    expect(lib, fwd(lib, desc(Geo()), feat=FAKE + 4), UNS, "aligned")
+    expect(lib, fwd(lib, desc(Geo(), tile=(3, 0, 0, 0))), UNS, "waves_per_anchor")
+    expect(lib, fwd(lib, desc(Geo(), tile=(0, 16, 0, 0))), UNS, "chans_per_lane")
+    expect(lib, fwd(lib, desc(Geo(), tile=(0, 0, 2, 0))), UNS, "anchors_per_block")
+    # one batch item beyond 2^31 bytes of features
+    g = Geo(ncam=1, levels=((4096, 4096),))
+    expect(lib, fwd(lib, desc(g, C=64, G=4)), UNS, "bytes")
+
+
+def test_backward_validation(lib):
+    d = desc(Geo(), dtype=_lib.MSDA_FP8_E4M3, C=64, scale=FAKE)
+    expect(lib, bwd(lib, d), UNS, "FP8")
+    d = desc(Geo(), dtype=_lib.MSDA_BF16, C=64)
+    need = lib.msda_backward_workspace_size(ctypes.byref(d))
+    assert need == 1 * Geo().rows * 64 * 4
+    expect(lib, bwd(lib, d), WS, "workspace")
+    expect(lib, bwd(lib, d, ws=FAKE + (1 << 20), ws_bytes=need - 4), WS)
+    expect(lib, bwd(lib, d, ws=(FAKE + (1 << 20)) + 8, ws_bytes=need + 64), WS, "aligned")
+    d = desc(Geo())
+    assert lib.msda_backward_workspace_size(ctypes.byref(d)) == 0
+
+
+def test_empty_anchor_set_is_ok_without_launch(lib):
+    d = desc(Geo(), A=0)
+    assert fwd(lib, d) == _lib.MSDA_OK
+    assert lib.msda_last_error().decode() == ""
+
+
+def test_stream_copy_validation(lib):
+    expect(lib, lib.msda_stream_copy(None, FAKE, 16, None), INV)
+    expect(lib, lib.msda_stream_copy(FAKE, FAKE, 17, None), INV, "aligned")
+    expect(lib, lib.msda_stream_copy(FAKE + 4, FAKE, 16, None), INV, "aligned")
+
+
+def test_quantize_validation(lib):
+    d = desc(Geo(), C=64)
+    ws = lib.msda_quantize_workspace_size(ctypes.byref(d))
+    assert ws == 2 * 4
+    expect(lib, lib.msda_quantize_fp8(FAKE, FAKE, FAKE, FAKE, FAKE, None, 0, ctypes.byref(d), None),
+           WS)
+    g = Geo()
+    g.rows -= 3
+    expect(lib, lib.msda_quantize_fp8(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 64,
+                                      ctypes.byref(desc(g, C=64)), None), INV, "outside")
+
+
+def test_python_binding_fails_loudly_without_library(tmp_path):
+    import importlib
+    mod = importlib.import_module("paper_2601_10819_amd._lib")
+    saved = mod._lib
+    try:
+        mod._lib = None
+        with pytest.raises(RuntimeError, match="missing"):
+            mod.load(str(tmp_path / "nope.so"))
+    finally:
+        mod._lib = saved

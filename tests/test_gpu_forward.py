@@ -1,0 +1,154 @@
+"""Forward parity of the HIP kernels against the FP64 oracle (FP32 storage),
+over every lane layout and wave split, ragged shapes and edge cases."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import (FWD_F32_MAXREL, FWD_F32_TOL, anchor_subset, assert_close, host,
+                     oracle_forward_subset, to_device)
+from paper_2601_10819_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_2601_10819_amd import ops as o
+    o._lib.load()
+    return o
+
+
+def run_fwd(ops, p, dtype=torch.float32, tile=None):
+    feat, layout, loc, w = to_device(p, dtype)
+    out = ops.forward(feat, layout, loc, w, tile=tile)
+    torch.cuda.synchronize()
+    return host(out)
+
+
+@pytest.mark.parametrize("maker", [synth.tiny, lambda: synth.sparse4d(seed=0)],
+                         ids=["tiny_2cam_c64", "sparse4d_6cam"])
+def test_forward_matches_oracle(ops, oracle_mod, maker):
+    p = maker()
+    print(f"case {p.name} {p.dims()}", flush=True)
+    got = run_fwd(ops, p)
+    ref = oracle_mod.forward(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                             p.weights)
+    assert_close(got, ref, FWD_F32_TOL, FWD_F32_MAXREL, p.name)
+
+
+LAYOUTS = [
+    # (C, G, chans_per_lane, waves_per_anchor)
+    (256, 8, 4, 1), (256, 8, 4, 2), (256, 8, 4, 8), (128, 8, 2, 4), (64, 8, 1, 2),
+    (64, 4, 4, 1), (64, 4, 2, 2), (32, 4, 4, 4), (16, 2, 4, 1), (8, 1, 1, 8), (4, 1, 4, 2),
+]
+
+
+@pytest.mark.parametrize("C,G,cpl,waves", LAYOUTS)
+def test_forward_lane_layouts(ops, oracle_mod, C, G, cpl, waves):
+    """Ragged shapes (odd H/W, 3 levels, 5 keypoints, 7 cameras) under every
+    channels-per-lane / waves split the F32 kernel is built for."""
+    p = synth.small(seed=C + waves, B=2, cams=7, levels=((11, 13), (6, 7), (3, 3)), C=C, G=G,
+                    A=37, P=5)
+    print(f"case C={C} G={G} cpl={cpl} waves={waves}", flush=True)
+    got = run_fwd(ops, p, tile={"chans_per_lane": cpl, "waves_per_anchor": waves})
+    ref = oracle_mod.forward(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                             p.weights)
+    assert_close(got, ref, FWD_F32_TOL, FWD_F32_MAXREL, f"C={C} cpl={cpl} waves={waves}")
+
+
+def test_forward_edge_cases(ops, oracle_mod):
+    # every sample out of range -> exact zeros
+    p = synth.small(seed=3, A=9, P=4)
+    p.sampling_loc[..., 0] = 1.5
+    assert np.all(run_fwd(ops, p) == 0.0)
+    # one level, one camera, one keypoint, one channel group
+    p = synth.small(seed=4, cams=1, levels=((5, 3),), C=8, G=1, A=3, P=1)
+    ref = oracle_mod.forward(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc, p.weights)
+    assert_close(run_fwd(ops, p), ref, FWD_F32_TOL, FWD_F32_MAXREL, "single")
+    # 1x1 levels (every in-range sample touches the only pixel)
+    p = synth.small(seed=5, cams=2, levels=((1, 1), (1, 2)), C=16, G=2, A=5, P=3)
+    ref = oracle_mod.forward(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc, p.weights)
+    assert_close(run_fwd(ops, p), ref, FWD_F32_TOL, FWD_F32_MAXREL, "1x1")
+    # 8 levels (two blocks of four in the kernel)
+    p = synth.small(seed=6, cams=2, levels=tuple((9 - i, 10 - i) for i in range(8)), C=32, G=4,
+                    A=6, P=2)
+    ref = oracle_mod.forward(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc, p.weights)
+    assert_close(run_fwd(ops, p), ref, FWD_F32_TOL, FWD_F32_MAXREL, "8 levels")
+
+
+def test_forward_empty_anchor_set(ops):
+    p = synth.small(seed=1, A=1)
+    feat, layout, loc, w = to_device(p)
+    out = ops.forward(feat, layout, loc[:, :0].contiguous(), w[:, :0].contiguous())
+    torch.cuda.synchronize()
+    assert out.shape == (1, 0, p.channels)
+
+
+def test_forward_pixel_centres_exact(ops):
+    """u = (i + 0.5) / W with power-of-two W hits pixel i exactly: the output
+    equals weight * feature bit for bit (one nonzero weight per anchor)."""
+    gen = torch.Generator().manual_seed(11)
+    levels = [(16, 32), (8, 16)]
+    shapes, starts, R = synth.layout([levels] * 3)
+    B, A, P, N, L, G, C = 1, 40, 1, 3, 2, 4, 64
+    feat = torch.randn(B, R, C, generator=gen)
+    ix = torch.randint(0, 32, (B, A, P, N), generator=gen)
+    iy = torch.randint(0, 16, (B, A, P, N), generator=gen)
+    loc = torch.stack([(ix + 0.5) / 32, (iy + 0.5) / 16], dim=-1).float().contiguous()
+    w = torch.zeros(B, A, P, N, L, G)
+    w[:, :, 0, 1, 0, :] = 1.0
+    p = synth.Problem("centres", feat, shapes, starts, loc, w)
+    got = run_fwd(ops, p)
+    rows = starts[1, 0].item() + iy[0, :, 0, 1] * 32 + ix[0, :, 0, 1]
+    assert np.array_equal(got[0], feat[0, rows].double().numpy())
+
+
+def test_forward_max_batch_item(ops, oracle_mod):
+    """A batch item just under the 2^31-byte addressing limit, with samples in
+    its last rows: 32-bit offsets stay exact up to the limit."""
+    C, G = 256, 8
+    # 2 cameras x one 1024 x 1023 level: R*C*4 = 2,145,386,496 bytes < 2^31 - 16
+    levels = [(1024, 1023)]
+    shapes, starts, R = synth.layout([levels] * 2)
+    assert R * C * 4 < 2 ** 31 - 16
+    gen = torch.Generator().manual_seed(2)
+    A, P = 16, 4
+    feat = torch.empty(1, R, C, device="cuda")
+    feat.normal_(generator=torch.Generator(device="cuda").manual_seed(3))
+    loc = torch.rand(1, A, P, 2, 2, generator=gen) * 0.05 + 0.95   # bottom-right corner
+    w = torch.rand(1, A, P, 2, 1, G, generator=gen)
+    layout = ops.Layout(shapes, starts)
+    out = ops.forward(feat, layout, loc.cuda(), w.cuda())
+    torch.cuda.synchronize()
+    # oracle on the rows actually touched: the last 60 rows x 60 cols of each camera
+    rows = []
+    for n in range(2):
+        s0 = int(starts[n, 0])
+        for y in range(1024 - 60, 1024):
+            rows.append(s0 + y * 1023 + 1023 - 60 + np.arange(60))
+    rows = np.unique(np.concatenate(rows))
+    sub = feat[0, torch.from_numpy(rows).cuda()].double().cpu().numpy()
+    full = np.zeros((1, R, C))
+    full[0, rows] = sub
+    del feat
+    ref = oracle_mod.forward(full, shapes, starts, loc, w)
+    assert_close(host(out), ref, FWD_F32_TOL, FWD_F32_MAXREL, "max batch item")
+
+
+@pytest.mark.parametrize("which", ["train16", "cam64"])
+def test_forward_full_size_sampled(ops, oracle_mod, which):
+    """Full-size workloads in the benchmark's launch configuration (default
+    tile), FP32 storage; the oracle evaluates a seeded subset of anchors."""
+    p = synth.train16() if which == "train16" else synth.cam64()
+    print(f"case {p.name} {p.dims()}", flush=True)
+    got = run_fwd(ops, p)
+    idx = anchor_subset(p, 48, seed=1)
+    ref = oracle_forward_subset(oracle_mod, p.feat, p, idx)
+    assert_close(got[:, idx], ref, FWD_F32_TOL, FWD_F32_MAXREL, p.name)
+    assert np.isfinite(got).all()

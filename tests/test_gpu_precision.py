@@ -1,0 +1,143 @@
+"""Precision forms: BF16 and FP8-e4m3 feature storage with FP32 arithmetic.
+
+Each is measured two ways against the FP64 oracle: the kernel error (oracle
+run on the stored values, widened exactly) must meet the FP32 bar, and the
+total error (oracle run on the original FP32 features) is reported, with the
+BF16 bar of 1e-2 of the output RMS."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import (BF16_TOL, FWD_F32_MAXREL, FWD_F32_TOL, GRAD_F32_TOL, anchor_subset,
+                     assert_close, host, normwise, oracle_backward_subset,
+                     oracle_forward_subset, to_device)
+from paper_2601_10819_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_2601_10819_amd import ops as o
+    o._lib.load()
+    return o
+
+
+def bf16_widened(p):
+    return p.feat.to(torch.bfloat16).double()
+
+
+@pytest.mark.parametrize("which", ["sparse4d", "train16", "cam64"])
+def test_bf16_forward(ops, oracle_mod, which):
+    p = {"sparse4d": lambda: synth.sparse4d(seed=0), "train16": synth.train16,
+         "cam64": synth.cam64}[which]()
+    feat, layout, loc, w = to_device(p, torch.bfloat16)
+    got = host(ops.forward(feat, layout, loc, w))
+    idx = anchor_subset(p, 64, seed=3)
+    ref_kernel = oracle_forward_subset(oracle_mod, bf16_widened(p), p, idx)
+    ref_total = oracle_forward_subset(oracle_mod, p.feat, p, idx)
+    assert_close(got[:, idx], ref_kernel, FWD_F32_TOL, FWD_F32_MAXREL, f"{which} bf16 kernel")
+    total = normwise(got[:, idx], ref_total)
+    print(f"{which} bf16 forward total error {total:.3e}", flush=True)
+    assert total <= BF16_TOL
+
+
+@pytest.mark.parametrize("which", ["sparse4d", "train16"])
+def test_bf16_backward(ops, oracle_mod, which):
+    p = synth.sparse4d(seed=0) if which == "sparse4d" else synth.train16()
+    go = synth.grad_out_like(p, seed=7)
+    feat, layout, loc, w = to_device(p, torch.bfloat16)
+    gf, gl, gw = ops.backward(feat, layout, loc, w, go.cuda())
+    torch.cuda.synchronize()
+    assert gf.dtype == torch.bfloat16
+    idx = anchor_subset(p, 48, seed=4)
+    rgl_k, rgw_k = oracle_backward_subset(oracle_mod, bf16_widened(p), p, idx, go)
+    rgl_t, rgw_t = oracle_backward_subset(oracle_mod, p.feat, p, idx, go)
+    assert_close(host(gl)[:, idx], rgl_k, GRAD_F32_TOL, None, f"{which} bf16 grad_loc kernel")
+    assert_close(host(gw)[:, idx], rgw_k, GRAD_F32_TOL, None, f"{which} bf16 grad_w kernel")
+    assert normwise(host(gl)[:, idx], rgl_t) <= BF16_TOL
+    assert normwise(host(gw)[:, idx], rgw_t) <= BF16_TOL
+    if which == "sparse4d":
+        rgf, _, _ = oracle_mod.backward(bf16_widened(p), p.spatial_shapes, p.level_start_index,
+                                        p.sampling_loc, p.weights, go, need_loc=False,
+                                        need_w=False)
+        # grad_feat is rounded once to BF16: error bounded by the BF16 bar,
+        # and the rounding is to nearest (within half a BF16 ulp of FP32 sum)
+        err = normwise(host(gf), rgf)
+        print(f"{which} bf16 grad_feat error {err:.3e}", flush=True)
+        assert err <= BF16_TOL
+        rounded = torch.from_numpy(rgf).float().to(torch.bfloat16).double().numpy()
+        assert normwise(host(gf), rounded) <= 5e-3
+
+
+def test_fp8_quantiser_bit_exact(ops, oracle_mod):
+    p = synth.sparse4d(seed=1, anchors=8)
+    layout = ops.Layout(p.spatial_shapes, p.level_start_index)
+    codes, scales = ops.quantize_fp8(p.feat.cuda(), layout)
+    torch.cuda.synchronize()
+    rcodes, rscales = oracle_mod.quantize_fp8_per_level(p.feat, p.spatial_shapes,
+                                                         p.level_start_index)
+    assert np.array_equal(scales.cpu().numpy(), rscales)
+    assert np.array_equal(codes.cpu().numpy(), rcodes)
+
+
+def test_fp8_decode_all_codes(ops, oracle_mod):
+    """Every e4m3 code through the forward kernel at exact pixel centres
+    (one channel group per code byte): out = decode(code) * scale exactly."""
+    codes = np.array([c for c in range(256) if c not in (0x7F, 0xFF)], dtype=np.uint8)
+    C, G = 64, 4
+    ncode = len(codes)                            # 254 codes -> 4 rows x 64 channels
+    rows_needed = (ncode + C - 1) // C
+    levels = [(1, 4)]
+    shapes, starts, R = synth.layout([levels])
+    assert R >= rows_needed
+    table = np.zeros((1, R, C), dtype=np.uint8)
+    table.reshape(-1)[:ncode] = codes
+    A = R
+    loc = torch.zeros(1, A, 1, 1, 2)
+    loc[0, :, 0, 0, 0] = (torch.arange(A) + 0.5) / 4
+    loc[0, :, 0, 0, 1] = 0.5
+    w = torch.ones(1, A, 1, 1, 1, G)
+    scale = torch.tensor([0.5], dtype=torch.float32)
+    layout = ops.Layout(shapes, starts)
+    out = ops.forward(torch.from_numpy(table).cuda(), layout, loc.cuda(), w.cuda(),
+                      level_scale=scale.cuda())
+    torch.cuda.synchronize()
+    got = out.cpu().double().numpy().reshape(-1)[:ncode]
+    want = oracle_mod.decode_e4m3(codes) * 0.5
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("which", ["sparse4d", "cam64"])
+def test_fp8_forward(ops, oracle_mod, which):
+    p = synth.sparse4d(seed=0) if which == "sparse4d" else synth.cam64()
+    layout = ops.Layout(p.spatial_shapes, p.level_start_index)
+    codes, scales = ops.quantize_fp8(p.feat.cuda(), layout)
+    loc, w = p.sampling_loc.cuda(), p.weights.cuda()
+    got = host(ops.forward(codes, layout, loc, w, level_scale=scales))
+    idx = anchor_subset(p, 48, seed=5)
+    deq = oracle_mod.dequantize_fp8(codes.cpu().numpy(), scales.cpu().numpy(), p.spatial_shapes,
+                                    p.level_start_index)
+    ref_kernel = oracle_forward_subset(oracle_mod, deq, p, idx)
+    assert_close(got[:, idx], ref_kernel, FWD_F32_TOL, FWD_F32_MAXREL, f"{which} fp8 kernel")
+    ref_total = oracle_forward_subset(oracle_mod, p.feat, p, idx)
+    total = normwise(got[:, idx], ref_total)
+    print(f"{which} fp8 forward total error {total:.3e}", flush=True)
+    # e4m3 keeps 3 mantissa bits: a few percent per element, averaged by the
+    # aggregation; a loose sanity bound (the number itself is reported)
+    assert total <= 0.1
+
+
+def test_fp8_backward_rejected(ops):
+    p = synth.small(seed=1, C=64, G=4)
+    layout = ops.Layout(p.spatial_shapes, p.level_start_index)
+    codes, scales = ops.quantize_fp8(p.feat.cuda(), layout)
+    with pytest.raises(ops._lib.MSDAError, match="UNSUPPORTED"):
+        ops.backward(codes, layout, p.sampling_loc.cuda(), p.weights.cuda(),
+                     torch.zeros(1, p.num_anchors, 64, device="cuda"))
