@@ -104,7 +104,9 @@ def measured_traffic(kernel: str, workload: str, dtype: str):
 
 
 def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup):
-    """Time `steps` forward+backward steps; returns a dict of measurements."""
+    """Time `steps` forward+backward steps. Every kernel the library launches
+    is bracketed by HIP events on its stream (the library's benchmark hook),
+    so per-kernel average durations come from the timed region itself."""
     lib = ops._lib.load()
     dev = "cuda"
     feat = p.feat.to(feat_dtype).to(dev)
@@ -114,7 +116,6 @@ def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup):
     out = torch.empty(p.batch, p.num_anchors, p.channels, device=dev)
     ws_bytes = ops.backward_workspace_bytes(feat, layout, loc, w)
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev) if ws_bytes else None
-    stream = torch.cuda.current_stream()
 
     def step():
         ops.forward(feat, layout, loc, w, out=out)
@@ -125,26 +126,34 @@ def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup):
     torch.cuda.synchronize()
 
     ev = HipEvents()
-    pairs = [(ev.create(), ev.create(), ev.create(), ev.create()) for _ in range(steps)]
+    cap = 32                                       # kernels recorded per step
+    arrays = []
+    for _ in range(steps):
+        arr = (ctypes.c_void_p * (2 * cap))()
+        for i in range(2 * cap):
+            arr[i] = ev.create()
+        arrays.append(arr)
+    names = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        f0, f1, b0, b1 = pairs[i]
-        ops._lib.check(lib.msda_set_kernel_events(f0, f1))
-        ops.forward(feat, layout, loc, w, out=out)
-        ops._lib.check(lib.msda_set_kernel_events(b0, b1))
-        ops.backward(feat, layout, loc, w, go, workspace=ws)
-        ops._lib.check(lib.msda_set_kernel_events(None, None))
+        ops._lib.check(lib.msda_set_kernel_events(arrays[i], cap))
+        step()
+        k = lib.msda_recorded_kernels()
+        names.append([lib.msda_recorded_kernel_name(j).decode() for j in range(k)])
+        ops._lib.check(lib.msda_set_kernel_events(None, 0))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    fwd_ms = [ev.elapsed_ms(a, b) for a, b, _, _ in pairs]
-    bwd_ms = [ev.elapsed_ms(c, d) for _, _, c, d in pairs]
-    for pr in pairs:
-        for e in pr:
+    per_kernel = {}
+    for arr, nm in zip(arrays, names):
+        for j, name in enumerate(nm):
+            per_kernel.setdefault(name, []).append(ev.elapsed_ms(arr[2 * j], arr[2 * j + 1]))
+    for arr in arrays:
+        for e in arr:
             ev.destroy(e)
-    del stream
-    return {"total_s": t1 - t0, "fwd_kernel_ms": sum(fwd_ms) / steps,
-            "bwd_kernel_ms": sum(bwd_ms) / steps}
+    # average duration of one launch, and launches per step
+    kern = {n: {"ms": sum(v) / len(v), "per_step": len(v) / steps} for n, v in per_kernel.items()}
+    return {"total_s": t1 - t0, "kernels": kern}
 
 
 def copy_bandwidth(torch, ops, nbytes=1 << 30, reps=10):
@@ -162,9 +171,10 @@ def copy_bandwidth(torch, ops, nbytes=1 << 30, reps=10):
     return 2 * nbytes / dt / 1e9
 
 
-def cpu_baseline(p, anchors):
+def cpu_baseline(p, anchors, min_seconds=10.0, max_reps=20):
     """The FP64 oracle (as it stands) on the first `anchors` anchors of the
-    same workload, forward + full backward, BF16-widened features."""
+    same workload, forward + full backward on BF16-widened features, repeated
+    until about `min_seconds` of CPU time have been measured."""
     import numpy as np
     import torch
     import oracle
@@ -173,12 +183,15 @@ def cpu_baseline(p, anchors):
     sub_w = p.weights[:, :anchors].contiguous()
     feat = p.feat.to(torch.bfloat16).double().numpy()
     go = np.random.default_rng(0).standard_normal((p.batch, anchors, p.channels))
-    t0 = time.perf_counter()
-    oracle.forward(feat, p.spatial_shapes, p.level_start_index, sub_loc, sub_w)
-    oracle.backward(feat, p.spatial_shapes, p.level_start_index, sub_loc, sub_w, go)
-    dt = time.perf_counter() - t0
+    reps, dt = 0, 0.0
+    while reps < max_reps and (reps == 0 or dt < min_seconds):
+        t0 = time.perf_counter()
+        oracle.forward(feat, p.spatial_shapes, p.level_start_index, sub_loc, sub_w)
+        oracle.backward(feat, p.spatial_shapes, p.level_start_index, sub_loc, sub_w, go)
+        dt += time.perf_counter() - t0
+        reps += 1
     samples = p.batch * anchors * p.num_points * p.num_cams * p.num_levels
-    return samples / dt / 1e9, dt, oracle.num_threads(), samples
+    return samples * reps / dt / 1e9, dt, oracle.num_threads(), samples, reps
 
 
 def main():
@@ -212,10 +225,19 @@ def main():
 
     C, G, L, P, N = p.channels, p.groups, p.num_levels, p.num_points, p.num_cams
     fwd_b, bwd_b = bytes_per_sample(C, G, L, P, N, 2)
-    kern = "msda_bwd_kernel" if bf["bwd_kernel_ms"] >= bf["fwd_kernel_ms"] else "msda_fwd_kernel"
-    kms = bf["bwd_kernel_ms"] if kern == "msda_bwd_kernel" else bf["fwd_kernel_ms"]
-    kbytes = S * (bwd_b if kern == "msda_bwd_kernel" else fwd_b)
-    achieved = kbytes / (kms * 1e-3) / 1e9
+    # roofline of the dominant kernel (largest time per step); its algorithmic
+    # bytes are the pass's per-sample bytes times the samples of one launch
+    ks = bf["kernels"]
+    kern = max(ks, key=lambda n: ks[n]["ms"] * ks[n]["per_step"])
+    kms = ks[kern]["ms"]
+    alg_per_sample = {"msda_fwd_kernel": fwd_b,
+                      # the backward's gather kernel: re-gather, weights + grad_w,
+                      # loc + grad_loc, grad_out; the grad_feat scatter bytes are
+                      # charged to the row-reduction kernel
+                      "msda_bwd_kernel": bwd_b - 4 * C * 2,
+                      "gfeat_reduce_kernel": 4 * C * 2}.get(kern)
+    kbytes = S * alg_per_sample if alg_per_sample else None
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kbytes else None
     traffic = measured_traffic(kern, p.name, "bf16")
 
     res = {
@@ -235,27 +257,30 @@ def main():
                    "level_shapes": [list(map(int, s)) for s in p.spatial_shapes[0].tolist()],
                    "channels": C, "groups": G, "anchors": p.num_anchors, "keypoints": P,
                    "samples_per_step": S},
-        "fwd_kernel_ms": round(bf["fwd_kernel_ms"], 4),
-        "bwd_kernel_ms": round(bf["bwd_kernel_ms"], 4),
+        "kernels_ms": {n: round(v["ms"], 4) for n, v in ks.items()},
         "alg_hbm_frac_fwd_bwd": round(S * (fwd_b + bwd_b) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "alg_bytes_per_launch": int(kbytes)},
+        "roofline": {"bound": "hbm", "kernel": kern,
+                     "achieved": round(achieved, 1) if achieved else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                     "traffic": traffic, "alg_bytes_per_launch": int(kbytes) if kbytes else None,
+                     "avg_launch_ms": round(kms, 4)},
     }
     if fp is not None:
         fp_ms = fp["total_s"] / args.steps * 1e3
         res["fp32_ms_per_step"] = round(fp_ms, 4)
         res["fp32_value"] = round(S * args.steps / fp["total_s"] / 1e9, 4)
         res["bf16_speedup_vs_fp32"] = round(fp_ms / ms_step, 3)
+        res["fp32_kernels_ms"] = {n: round(v["ms"], 4) for n, v in fp["kernels"].items()}
     res["copy_GBps"] = round(copy_bandwidth(torch, ops), 1)
 
     if not args.no_cpu:
         anchors = args.cpu_anchors or p.num_anchors
-        v, dt, cores, ns = cpu_baseline(p, anchors)
+        v, dt, cores, ns, reps = cpu_baseline(p, anchors)
         res["cpu_baseline"] = {"value": round(v, 6), "unit": "GSamples/s", "cores": cores,
                                "kind": "oracle",
                                "sample": f"{p.name} anchors[0:{anchors}] ({ns} samples), FP64 "
-                                         f"forward + full backward, {dt:.1f} s"}
+                                         f"forward + full backward, {reps} runs in {dt:.1f} s"}
     print(json.dumps(res), flush=True)
 
 

@@ -69,15 +69,24 @@ typedef enum msda_dtype {
 } msda_dtype;
 
 /* msda_desc.flags */
-#define MSDA_DETERMINISTIC 1u /* backward: grad_feat reduced in a fixed order (no
-                                 float atomics); bitwise reproducible run to run */
+#define MSDA_DETERMINISTIC 1u /* backward: grad_feat must be summed in a fixed order
+                                 (bitwise reproducible run to run); rejects
+                                 MSDA_SCATTER_ATOMIC */
+
+/* msda_tile.scatter: how the backward forms grad_feat */
+#define MSDA_SCATTER_AUTO 0   /* the library's choice (currently SORTED)                */
+#define MSDA_SCATTER_SORTED 1 /* records sorted by feature row, then one pass per row
+                                 summing in sample order: deterministic, no atomics   */
+#define MSDA_SCATTER_ATOMIC 2 /* FP32 float atomics into an accumulator: run-to-run
+                                 differences in the last bits                        */
 
 /* Launch shape. A zero field means "choose". */
 typedef struct msda_tile {
     int32_t waves_per_anchor; /* wavefronts (64 lanes) sharing one anchor: 1, 2, 4, 8 */
-    int32_t chans_per_lane;   /* channels each lane owns: 4, 8 or 16                  */
+    int32_t chans_per_lane;   /* channels each lane owns: 1, 2, 4 (FP32), 2, 4, 8
+                                 (BF16), 4, 8, 16 (FP8)                              */
     int32_t anchors_per_block;/* reserved, must be 0 or 1                              */
-    int32_t reserved;
+    int32_t scatter;          /* MSDA_SCATTER_* (backward only)                        */
 } msda_tile;
 
 /* Sizes and options of one call. */
@@ -85,7 +94,7 @@ typedef struct msda_desc {
     int32_t batch;       /* B  >= 1                                              */
     int32_t num_cams;    /* Ncam >= 1                                            */
     int32_t num_levels;  /* L in 1..8                                            */
-    int32_t num_anchors; /* A >= 0 (0: nothing to do, outputs of size 0)         */
+    int32_t num_anchors; /* A >= 0 (0: arrays sized by A are empty and may be NULL) */
     int32_t num_points;  /* P >= 1 keypoints per anchor                          */
     int32_t channels;    /* C >= 1, C % groups == 0                              */
     int32_t groups;      /* G >= 1                                               */
@@ -120,10 +129,14 @@ msda_status msda_forward(const void* feat, const int32_t* spatial_shapes,
  * grad_sampling_loc, grad_weights may be NULL to skip it. grad_feat has the
  * feat dtype; FP8 grad_feat is UNSUPPORTED. Accumulation is FP32; a BF16
  * grad_feat is rounded once (to nearest even) from the FP32 sum.
+ * grad_feat is formed as msda_tile.scatter says: by default every (sample,
+ * corner) contribution is recorded, the records are sorted by feature row
+ * (a stable radix sort) and each row is summed in sample order and written
+ * once -- bitwise reproducible; MSDA_SCATTER_ATOMIC instead adds them with
+ * FP32 atomics (correct to rounding, last bits vary run to run).
  * workspace: device, 256-byte aligned, at least
  * msda_backward_workspace_size(desc) bytes (may be NULL when that is 0).
- * Without MSDA_DETERMINISTIC, grad_feat is summed with float atomics: correct
- * to rounding, but the last bits can vary run to run.
+ * Limits of the sorted form: B*R < 2^31 and 4*B*A*P*Ncam*L < 2^32.
  */
 msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
                           const int32_t* level_start_index, const float* sampling_loc,
@@ -131,7 +144,9 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
                           float* grad_sampling_loc, float* grad_weights, void* workspace,
                           size_t workspace_bytes, const msda_desc* desc, void* stream);
 
-/* Bytes of device workspace msda_backward needs for desc (0 if none). */
+/* Bytes of device workspace msda_backward needs for desc (0 if none): about
+ * 20 bytes per (sample, corner) for the sorted form; B*R*C*4 for the atomic
+ * form with BF16 features. */
 size_t msda_backward_workspace_size(const msda_desc* desc);
 
 /*
@@ -156,15 +171,18 @@ size_t msda_quantize_workspace_size(const msda_desc* desc);
 msda_status msda_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
 
 /*
- * Benchmark instrumentation. While set on the calling thread, msda_forward
- * and msda_backward record `start` (a hipEvent_t) on their stream just before
- * their main MSDA kernel and `stop` just after it, so the kernel's own
- * duration can be read with hipEventElapsedTime even when the call also
- * launches helper kernels (zeroing, BF16 rounding). The events belong to the
- * caller; NULL, NULL turns the hook off. Returns INVALID_ARGUMENT if exactly
- * one of the two is NULL.
+ * Benchmark instrumentation. `events` is an array of 2 * max_kernels
+ * hipEvent_t owned by the caller. While it is set on the calling thread, the
+ * i-th kernel the library launches (counting from this call, i <
+ * max_kernels) is bracketed by events[2i] and events[2i+1], recorded on its
+ * stream, so each kernel's own duration can be read with
+ * hipEventElapsedTime. msda_recorded_kernels() returns how many were
+ * recorded so far and msda_recorded_kernel_name(i) the name of the i-th.
+ * events == NULL turns the hook off. Not for use during graph capture.
  */
-msda_status msda_set_kernel_events(void* start, void* stop);
+msda_status msda_set_kernel_events(void* const* events, int32_t max_kernels);
+int32_t msda_recorded_kernels(void);
+const char* msda_recorded_kernel_name(int32_t i);
 
 const char* msda_last_error(void);
 int32_t msda_abi_version(void);

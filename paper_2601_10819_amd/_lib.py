@@ -31,13 +31,17 @@ ABI_VERSION = 1
 EXPORTS = (
     "msda_forward", "msda_backward", "msda_backward_workspace_size", "msda_quantize_fp8",
     "msda_quantize_workspace_size", "msda_stream_copy", "msda_set_kernel_events",
-    "msda_last_error", "msda_abi_version",
+    "msda_recorded_kernels", "msda_recorded_kernel_name", "msda_last_error", "msda_abi_version",
 )
+
+MSDA_SCATTER_AUTO = 0
+MSDA_SCATTER_SORTED = 1
+MSDA_SCATTER_ATOMIC = 2
 
 
 class MsdaTile(ctypes.Structure):
     _fields_ = [("waves_per_anchor", ctypes.c_int32), ("chans_per_lane", ctypes.c_int32),
-                ("anchors_per_block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("anchors_per_block", ctypes.c_int32), ("scatter", ctypes.c_int32)]
 
 
 class MsdaDesc(ctypes.Structure):
@@ -84,8 +88,12 @@ def load(path: str = LIB_PATH):
     lib.msda_quantize_workspace_size.restype = sz
     lib.msda_stream_copy.argtypes = [vp, vp, sz, vp]
     lib.msda_stream_copy.restype = ctypes.c_int
-    lib.msda_set_kernel_events.argtypes = [vp, vp]
+    lib.msda_set_kernel_events.argtypes = [vp, ctypes.c_int32]
     lib.msda_set_kernel_events.restype = ctypes.c_int
+    lib.msda_recorded_kernels.argtypes = []
+    lib.msda_recorded_kernels.restype = ctypes.c_int32
+    lib.msda_recorded_kernel_name.argtypes = [ctypes.c_int32]
+    lib.msda_recorded_kernel_name.restype = ctypes.c_char_p
     lib.msda_last_error.argtypes = []
     lib.msda_last_error.restype = ctypes.c_char_p
     lib.msda_abi_version.argtypes = []

@@ -12,8 +12,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmsda.so")
-SOURCES = [os.path.join(CSRC, "msda_kernels.hip"), os.path.join(CSRC, "msda_api.cpp")]
-HEADERS = [os.path.join(CSRC, "msda_internal.h"), os.path.join(ROOT, "include", "msda.h")]
+SOURCES = [os.path.join(CSRC, f) for f in
+           ("msda_fwd.hip", "msda_bwd.hip", "msda_sort.hip", "msda_util.hip", "msda_api.cpp")]
+HEADERS = [os.path.join(CSRC, "msda_internal.h"), os.path.join(CSRC, "msda_common.h"),
+           os.path.join(ROOT, "include", "msda.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -14,14 +14,11 @@
 namespace {
 
 thread_local std::string g_error;
-thread_local hipEvent_t g_ev_start = nullptr;
-thread_local hipEvent_t g_ev_stop = nullptr;
-
-// Record the benchmark hook's start/stop events around the main kernel.
-hipError_t mark(bool start, hipStream_t s) {
-    hipEvent_t e = start ? g_ev_start : g_ev_stop;
-    return e ? hipEventRecord(e, s) : hipSuccess;
-}
+// Benchmark hook state (msda_set_kernel_events).
+thread_local void* const* g_events = nullptr;
+thread_local int32_t g_event_cap = 0;
+thread_local int32_t g_event_used = 0;
+thread_local const char* g_event_names[256];
 
 msda_status fail(msda_status st, const char* fmt, ...) {
     char buf[512];
@@ -189,18 +186,82 @@ msda_status hip_fail(hipError_t e, const char* what) {
 
 bool aligned(const void* p, size_t n) { return ((uintptr_t)p % n) == 0; }
 
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace of the sorted grad_feat form: record keys (x2 for the sort),
+// values (x2), corner weights, row offsets and the sort's histogram scratch.
+struct SortedWs {
+    size_t keys_a, keys_b, vals_a, vals_b, cw, off, scratch, total;
+};
+
+SortedWs sorted_layout(uint64_t nrec, uint64_t nrows) {
+    SortedWs w;
+    const size_t rec = align256(nrec * 4);
+    w.keys_a = 0;
+    w.keys_b = w.keys_a + rec;
+    w.vals_a = w.keys_b + rec;
+    w.vals_b = w.vals_a + rec;
+    w.cw = w.vals_b + rec;
+    w.off = w.cw + rec;
+    w.scratch = w.off + align256((nrows + 1) * 4);
+    w.total = w.scratch + align256(msda::sort_scratch_words((uint32_t)nrec) * 4);
+    return w;
+}
+
+int scatter_mode(const msda_desc* d) {
+    const int m = d->tile ? d->tile->scatter : MSDA_SCATTER_AUTO;
+    return m == MSDA_SCATTER_AUTO ? MSDA_SCATTER_SORTED : m;
+}
+
+uint64_t num_records(const msda_desc* d) {
+    return 4ull * (uint64_t)d->batch * (uint64_t)d->num_anchors * (uint64_t)d->num_points *
+           (uint64_t)d->num_cams * (uint64_t)d->num_levels;
+}
+
+// s / d for s < 2^30 as (s * m) >> shift (round-up multiplier).
+void divmagic(uint32_t d, uint64_t* m, int* shift) {
+    int l = 0;
+    while ((1ull << l) < d) ++l;
+    const int k = 32 + l;
+    *m = ((1ull << k) + d - 1) / d;
+    *shift = k;
+}
+
 }  // namespace
+
+namespace msda {
+
+void mark_begin(const char* kernel, hipStream_t s) {
+    if (!g_events || g_event_used >= g_event_cap) return;
+    g_event_names[g_event_used] = kernel;
+    hipEventRecord(static_cast<hipEvent_t>(g_events[2 * g_event_used]), s);
+}
+
+void mark_end(hipStream_t s) {
+    if (!g_events || g_event_used >= g_event_cap) return;
+    hipEventRecord(static_cast<hipEvent_t>(g_events[2 * g_event_used + 1]), s);
+    ++g_event_used;
+}
+
+}  // namespace msda
 
 extern "C" {
 
 int32_t msda_abi_version(void) { return MSDA_ABI_VERSION; }
 
-msda_status msda_set_kernel_events(void* start, void* stop) {
-    if ((start == nullptr) != (stop == nullptr))
-        return fail(MSDA_ERR_INVALID_ARGUMENT, "give both events or neither");
-    g_ev_start = static_cast<hipEvent_t>(start);
-    g_ev_stop = static_cast<hipEvent_t>(stop);
+msda_status msda_set_kernel_events(void* const* events, int32_t max_kernels) {
+    if (events && (max_kernels < 1 || max_kernels > 256))
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "max_kernels must be in [1, 256]");
+    g_events = events;
+    g_event_cap = events ? max_kernels : 0;
+    g_event_used = 0;
     return ok();
+}
+
+int32_t msda_recorded_kernels(void) { return g_event_used; }
+
+const char* msda_recorded_kernel_name(int32_t i) {
+    return (i >= 0 && i < g_event_used) ? g_event_names[i] : "";
 }
 
 const char* msda_last_error(void) { return g_error.c_str(); }
@@ -212,7 +273,9 @@ msda_status msda_forward(const void* feat, const int32_t* spatial_shapes,
     int cpl = 0, waves = 0;
     msda_status st = prepare(desc, &a, &cpl, &waves);
     if (st != MSDA_OK) return st;
-    if (!feat || !spatial_shapes || !level_start_index || !sampling_loc || !weights || !out)
+    // sampling_loc, weights and out hold zero elements when A == 0 and may be NULL then
+    if (!feat || !spatial_shapes || !level_start_index ||
+        (a.A > 0 && (!sampling_loc || !weights || !out)))
         return fail(MSDA_ERR_INVALID_ARGUMENT, "a required device pointer is NULL");
     if (!aligned(feat, 16)) return fail(MSDA_ERR_UNSUPPORTED, "feat must be 16-byte aligned");
     if (a.A == 0) return ok();
@@ -223,20 +286,20 @@ msda_status msda_forward(const void* feat, const int32_t* spatial_shapes,
     a.w = weights;
     a.level_scale = desc->feat_dtype == MSDA_FP8_E4M3 ? desc->level_scale : nullptr;
     a.out = out;
-    const hipStream_t s = (hipStream_t)stream;
-    hipError_t e = mark(true, s);
-    if (e == hipSuccess)
-        e = msda::launch_forward(a, desc->feat_dtype, cpl, waves, msda::lds_bytes_for(a, waves), s);
-    if (e == hipSuccess) e = mark(false, s);
+    const hipError_t e = msda::launch_forward(a, desc->feat_dtype, cpl, waves,
+                                              msda::lds_bytes_for(a, waves), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "msda_forward launch");
     return ok();
 }
 
 size_t msda_backward_workspace_size(const msda_desc* d) {
-    if (!d || d->batch < 1 || d->rows < 1 || d->channels < 1) return 0;
-    if (d->feat_dtype == MSDA_BF16)   // FP32 accumulator for grad_feat
-        return (size_t)d->batch * (size_t)d->rows * (size_t)d->channels * sizeof(float);
-    return 0;
+    if (!d || d->batch < 1 || d->rows < 1 || d->channels < 1 || d->num_anchors < 0) return 0;
+    if (scatter_mode(d) == MSDA_SCATTER_ATOMIC) {
+        if (d->feat_dtype == MSDA_BF16)   // FP32 accumulator for grad_feat
+            return (size_t)d->batch * (size_t)d->rows * (size_t)d->channels * sizeof(float);
+        return 0;
+    }
+    return sorted_layout(num_records(d), (uint64_t)d->batch * (uint64_t)d->rows).total;
 }
 
 msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
@@ -248,15 +311,35 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
     int cpl = 0, waves = 0;
     msda_status st = prepare(desc, &a, &cpl, &waves);
     if (st != MSDA_OK) return st;
-    if (!feat || !spatial_shapes || !level_start_index || !sampling_loc || !weights || !grad_out)
+    // sampling_loc, weights and grad_out hold zero elements when A == 0 and may be NULL then
+    if (!feat || !spatial_shapes || !level_start_index ||
+        (a.A > 0 && (!sampling_loc || !weights || !grad_out)))
         return fail(MSDA_ERR_INVALID_ARGUMENT, "a required device pointer is NULL");
     if (!aligned(feat, 16)) return fail(MSDA_ERR_UNSUPPORTED, "feat must be 16-byte aligned");
-    if (grad_feat && desc->feat_dtype == MSDA_FP8_E4M3)
-        return fail(MSDA_ERR_UNSUPPORTED, "grad_feat for FP8 features is not supported");
     if (desc->feat_dtype == MSDA_FP8_E4M3)
-        return fail(MSDA_ERR_UNSUPPORTED, "the backward takes FP32 or BF16 features");
-    if (desc->flags & MSDA_DETERMINISTIC)
-        return fail(MSDA_ERR_UNSUPPORTED, "deterministic grad_feat is not available in this build");
+        return fail(MSDA_ERR_UNSUPPORTED, "the backward takes FP32 or BF16 features (not FP8)");
+    const int mode = scatter_mode(desc);
+    if (mode != MSDA_SCATTER_SORTED && mode != MSDA_SCATTER_ATOMIC)
+        return fail(MSDA_ERR_UNSUPPORTED, "unknown scatter mode %d", mode);
+    if ((desc->flags & MSDA_DETERMINISTIC) && mode == MSDA_SCATTER_ATOMIC)
+        return fail(MSDA_ERR_UNSUPPORTED, "MSDA_DETERMINISTIC excludes MSDA_SCATTER_ATOMIC");
+    const uint64_t nrec = num_records(desc);
+    const uint64_t nrows = (uint64_t)a.B * (uint64_t)a.R;
+    // the reduction's lane layout: FP32 accumulators, 4/2/1 channels per lane
+    int rcpl = 0;
+    for (int c : {4, 2, 1})
+        if (cpl_fits(c, a.C, a.G)) { rcpl = c; break; }
+    if (grad_feat && mode == MSDA_SCATTER_SORTED) {
+        if (nrows >= 0x7fffffffull)
+            return fail(MSDA_ERR_UNSUPPORTED, "B*R = %llu rows exceeds 2^31 - 1",
+                        (unsigned long long)nrows);
+        if (nrec >= 0xffffffffull)
+            return fail(MSDA_ERR_UNSUPPORTED, "4*B*A*P*Ncam*L = %llu records exceeds 2^32 - 1",
+                        (unsigned long long)nrec);
+        if (!rcpl) return fail(MSDA_ERR_UNSUPPORTED, "no reduction lane layout for C=%d G=%d", a.C, a.G);
+        if (rcpl == 4 && !aligned(grad_out, 16))
+            return fail(MSDA_ERR_UNSUPPORTED, "grad_out must be 16-byte aligned");
+    }
     const size_t need = grad_feat ? msda_backward_workspace_size(desc) : 0;
     if (need) {
         if (!workspace || workspace_bytes < need)
@@ -269,36 +352,71 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
         return fail(MSDA_ERR_UNSUPPORTED, "grad_feat must be 16-byte aligned");
 
     const hipStream_t s = (hipStream_t)stream;
-    const size_t gf_elems = (size_t)a.B * (size_t)a.R * (size_t)a.C;
-    float* acc = nullptr;
-    if (grad_feat) {
-        acc = desc->feat_dtype == MSDA_F32 ? static_cast<float*>(grad_feat)
-                                           : static_cast<float*>(workspace);
-        hipError_t e = msda::launch_fill_zero(acc, gf_elems * sizeof(float), s);
-        if (e != hipSuccess) return hip_fail(e, "zero grad_feat accumulator");
-    }
-    if (a.A > 0) {
-        a.feat = feat;
-        a.shapes = spatial_shapes;
-        a.starts = level_start_index;
-        a.loc = sampling_loc;
-        a.w = weights;
-        a.grad_out = grad_out;
+    const size_t gf_elems = (size_t)nrows * (size_t)a.C;
+    char* ws = static_cast<char*>(workspace);
+    hipError_t e = hipSuccess;
+    a.feat = feat;
+    a.shapes = spatial_shapes;
+    a.starts = level_start_index;
+    a.loc = sampling_loc;
+    a.w = weights;
+    a.grad_out = grad_out;
+    a.grad_loc = grad_sampling_loc;
+    a.grad_w = grad_weights;
+
+    if (grad_feat && mode == MSDA_SCATTER_ATOMIC) {
+        float* acc = desc->feat_dtype == MSDA_F32 ? static_cast<float*>(grad_feat)
+                                                  : reinterpret_cast<float*>(ws);
+        if ((e = msda::launch_fill_zero(acc, gf_elems * sizeof(float), s)) != hipSuccess)
+            return hip_fail(e, "zero grad_feat accumulator");
         a.gfeat_acc = acc;
-        a.grad_loc = grad_sampling_loc;
-        a.grad_w = grad_weights;
-        hipError_t e = mark(true, s);
-        if (e == hipSuccess)
-            e = msda::launch_backward(a, desc->feat_dtype, cpl, waves,
-                                      msda::lds_bytes_for(a, waves), s);
-        if (e == hipSuccess) e = mark(false, s);
-        if (e != hipSuccess) return hip_fail(e, "msda_backward launch");
+        if (a.A > 0 &&
+            (e = msda::launch_backward(a, desc->feat_dtype, cpl, waves,
+                                       msda::lds_bytes_for(a, waves), s)) != hipSuccess)
+            return hip_fail(e, "msda_backward launch");
+        if (desc->feat_dtype == MSDA_BF16 &&
+            (e = msda::launch_f32_to_bf16(acc, static_cast<uint16_t*>(grad_feat), gf_elems, s)) !=
+                hipSuccess)
+            return hip_fail(e, "round grad_feat to bf16");
+        return ok();
     }
-    if (grad_feat && desc->feat_dtype == MSDA_BF16) {
-        const hipError_t e =
-            msda::launch_f32_to_bf16(acc, static_cast<uint16_t*>(grad_feat), gf_elems, s);
-        if (e != hipSuccess) return hip_fail(e, "round grad_feat to bf16");
+
+    SortedWs L = {};
+    if (grad_feat) {
+        L = sorted_layout(nrec, nrows);
+        a.rec_key = reinterpret_cast<uint32_t*>(ws + L.keys_a);
+        a.rec_cw = reinterpret_cast<float*>(ws + L.cw);
     }
+    if (a.A > 0 && (grad_feat || grad_sampling_loc || grad_weights) &&
+        (e = msda::launch_backward(a, desc->feat_dtype, cpl, waves, msda::lds_bytes_for(a, waves),
+                                   s)) != hipSuccess)
+        return hip_fail(e, "msda_backward launch");
+    if (!grad_feat) return ok();
+
+    uint32_t* sorted = nullptr;
+    uint32_t* off = reinterpret_cast<uint32_t*>(ws + L.off);
+    e = msda::launch_sort_records(reinterpret_cast<uint32_t*>(ws + L.keys_a),
+                                  reinterpret_cast<uint32_t*>(ws + L.keys_b),
+                                  reinterpret_cast<uint32_t*>(ws + L.vals_a),
+                                  reinterpret_cast<uint32_t*>(ws + L.vals_b), (uint32_t)nrec,
+                                  (uint32_t)nrows, reinterpret_cast<uint32_t*>(ws + L.scratch),
+                                  off, &sorted, s);
+    if (e != hipSuccess) return hip_fail(e, "sort grad_feat records");
+    msda::ReduceArgs r = {};
+    r.vals = sorted;
+    r.off = off;
+    r.rec_cw = a.rec_cw;
+    r.w = weights;
+    r.grad_out = grad_out;
+    r.grad_feat = grad_feat;
+    r.nrows = (uint32_t)nrows;
+    r.nrec = (uint32_t)nrec;
+    r.C = a.C;
+    r.G = a.G;
+    r.lps_shift = log2i(a.C / rcpl);
+    divmagic((uint32_t)a.P * (uint32_t)a.N * (uint32_t)a.L, &r.magic, &r.magic_shift);
+    if ((e = msda::launch_gfeat_reduce(r, desc->feat_dtype, rcpl, s)) != hipSuccess)
+        return hip_fail(e, "grad_feat row reduction");
     return ok();
 }
 

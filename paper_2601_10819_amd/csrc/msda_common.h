@@ -1,0 +1,228 @@
+// Device-side building blocks shared by the MSDA kernels for gfx950:
+// buffer resources and lane-width loads, storage widening, sample geometry,
+// and the per-wave LDS staging of locations and weights.
+//
+// The operator (paper Sec. 3.1 / Sec. 3.2; named in Sec. 5.3) samples every
+// camera's feature pyramid bilinearly at each projected keypoint and sums the
+// samples with per-(keypoint, camera, level, group) weights. It is a gather
+// with low arithmetic intensity (Sec. 5.3), so the kernels are organised
+// around memory access, not matrix cores:
+//
+//  * Each lane owns CPL consecutive channels; a sample occupies C/CPL lanes
+//    ("lanes per sample", a power of two <= 64) and a 64-lane wave works on
+//    64/(C/CPL) samples at once. Corner rows are read with 4/8/16-byte buffer
+//    loads, so the 4 corner gathers of a sample are channel-contiguous.
+//  * Feature reads go through a buffer resource spanning one batch item. A
+//    corner outside its level gets an offset past the end of the resource and
+//    the hardware returns 0 without touching memory: zero padding costs no
+//    branch, and no computed index can read outside the tensor.
+//  * The coordinate t = u*W - 0.5 is assembled from the exact product u*W
+//    (an fma recovers the rounding error of the multiply), so floor(t) and the
+//    bilinear fraction are exact to ~1e-7 px instead of half an FP32 ulp of t.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "msda_internal.h"
+
+namespace msda {
+
+typedef uint32_t u32;
+typedef uint64_t u64;
+typedef u32 u32x2 __attribute__((ext_vector_type(2)));
+typedef u32 u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+// Offset used for a corner outside its level: beyond every resource (whose
+// size is < 2^31), so a buffer load returns zeros.
+constexpr u32 kOOB = 0x80000000u;
+
+// Word 3 of a raw (untyped, stride 0) buffer resource on gfx9-family GPUs.
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, u32 bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             kRsrcWord3);
+}
+
+// ---------------------------------------------------------------- storage types
+
+struct TF32 { static constexpr int kBytes = 4; };
+struct TBF16 { static constexpr int kBytes = 2; };
+struct TFP8 { static constexpr int kBytes = 1; };
+
+template <class FT, int CPL>
+struct Row {
+    static constexpr int kBytes = FT::kBytes * CPL;   // 4, 8 or 16
+    static constexpr int kWords = kBytes / 4;
+    static_assert(kBytes == 4 || kBytes == 8 || kBytes == 16, "unsupported lane width");
+};
+
+template <int WORDS>
+__device__ __forceinline__ void load_words(rsrc_t r, u32 off, u32* d) {
+    if constexpr (WORDS == 4) {
+        u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+    } else if constexpr (WORDS == 2) {
+        u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        d[0] = v.x; d[1] = v.y;
+    } else {
+        d[0] = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+    }
+}
+
+// Widen CPL stored channels (packed in `w`) to FP32.
+template <class FT, int CPL>
+__device__ __forceinline__ void widen(const u32* w, float* f) {
+    if constexpr (FT::kBytes == 4) {
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) f[i] = __uint_as_float(w[i]);
+    } else if constexpr (FT::kBytes == 2) {
+        // bfloat16 is the top half of an FP32: widening is a shift.
+#pragma unroll
+        for (int i = 0; i < CPL / 2; ++i) {
+            f[2 * i] = __uint_as_float(w[i] << 16);
+            f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+        }
+    } else {
+        // OCP e4m3 to FP32 with the hardware converter, two codes at a time.
+#pragma unroll
+        for (int i = 0; i < CPL / 4; ++i) {
+            f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], false);
+            f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], true);
+            f[4 * i] = lo.x; f[4 * i + 1] = lo.y; f[4 * i + 2] = hi.x; f[4 * i + 3] = hi.y;
+        }
+    }
+}
+
+// FP32 -> bfloat16, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    const u32 b = __float_as_uint(x);
+    if ((b & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((b >> 16) | 0x40u);
+    return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+}
+
+// ---------------------------------------------------------------- geometry
+
+// One (camera, level) region: its size, first row, and the FP8 level scale
+// (1 for other storage types).
+struct Geo { int H, W, start; float scale; };
+
+__device__ __forceinline__ void stage_geometry(Geo* geo, const OpArgs& a) {
+    const int NL = a.N * a.L;
+    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
+        Geo g;
+        g.H = a.shapes[2 * i];
+        g.W = a.shapes[2 * i + 1];
+        g.start = a.starts[i];
+        g.scale = a.level_scale ? a.level_scale[i % a.L] : 1.f;
+        geo[i] = g;
+    }
+}
+
+// Integer part and fraction of t = u*n - 0.5 along one axis of a level with n
+// pixels, and whether -1 < t < n. u*n is split exactly into p + e, the floor
+// is taken of p, and the fraction is assembled from exact pieces, so only the
+// final add rounds.
+struct Axis { int i0; float l; bool ok; };
+
+__device__ __forceinline__ Axis axis_of(float u, int n) {
+    // The split only works if each operation is rounded as written: a fused
+    // u*n - fp would already contain e, which is then added a second time.
+#pragma clang fp contract(off)
+    const float fn = (float)n;
+    const float p = u * fn;
+    const float e = fmaf(u, fn, -p);            // u*n == p + e exactly
+    const float fp = floorf(p);
+    const float f = ((p - fp) - 0.5f) + e;      // t - fp, in about [-0.5, 0.5)
+    const float flo = f < 0.f ? -1.f : 0.f;
+    float l = f - flo;
+    float i0f = fp + flo;
+    if (l >= 1.f) { l = 0.f; i0f += 1.f; }      // f a hair below 0: t is an integer
+    i0f = fminf(fmaxf(i0f, -4.f), fn + 4.f);    // keeps the int conversion defined; NaN -> -4
+    Axis a;
+    a.i0 = (int)i0f;
+    a.ok = (a.i0 >= 0 || (a.i0 == -1 && l > 0.f)) && a.i0 < n;
+    a.l = a.ok ? l : 0.f;
+    return a;
+}
+
+// The 4 corners of one sample, in the order (y0,x0), (y0,x0+1), (y0+1,x0),
+// (y0+1,x0+1): byte offsets (kOOB when outside), bilinear weights (0 when
+// outside) and rows within the batch item (-1 when outside).
+struct Corners {
+    u32 off[4];
+    float cw[4];
+    float lx, ly;
+    int row[4];
+    bool valid;
+};
+
+__device__ __forceinline__ Corners corners_of(float u, float v, const Geo& g, u32 row_bytes,
+                                              u32 lane_off) {
+    const Axis ax = axis_of(u, g.W);
+    const Axis ay = axis_of(v, g.H);
+    Corners c;
+    c.valid = ax.ok && ay.ok;
+    c.lx = c.valid ? ax.l : 0.f;
+    c.ly = c.valid ? ay.l : 0.f;
+    const float hx = 1.f - c.lx, hy = 1.f - c.ly;
+    const bool in_x0 = ax.i0 >= 0, in_x1 = ax.i0 + 1 < g.W;
+    const bool in_y0 = ay.i0 >= 0, in_y1 = ay.i0 + 1 < g.H;
+    const bool in[4] = {c.valid && in_y0 && in_x0, c.valid && in_y0 && in_x1,
+                        c.valid && in_y1 && in_x0, c.valid && in_y1 && in_x1};
+    const float wt[4] = {hy * hx, hy * c.lx, c.ly * hx, c.ly * c.lx};
+    const int base = g.start + ay.i0 * g.W + ax.i0;
+    const int rows[4] = {base, base + 1, base + g.W, base + g.W + 1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        c.row[k] = in[k] ? rows[k] : -1;
+        c.off[k] = in[k] ? (u32)rows[k] * row_bytes + lane_off : kOOB;
+        c.cw[k] = in[k] ? wt[k] : 0.f;
+    }
+    return c;
+}
+
+// ---------------------------------------------------------------- lanes and LDS
+
+__device__ __forceinline__ float xor_shuffle(float v, int mask) {
+    return __shfl_xor(v, mask, 64);
+}
+
+// Per-lane registers' worth of weights staged per wave step.
+constexpr int kStageWords = 8;
+
+// Copy one chunk of nj pairs' weights (nj*LG floats) and locations (nj*2)
+// into this wave's LDS slot; both are contiguous in global memory.
+__device__ __forceinline__ void stage_chunk(float* sw, float* sl, const float* gw,
+                                            const float* gl, int nj, int LG, int lane) {
+    const int nw = nj * LG;
+#pragma unroll
+    for (int t = 0; t < kStageWords; ++t) {
+        const int i = t * 64 + lane;
+        if (i < nw) sw[i] = gw[i];
+    }
+    if (lane < 2 * nj) sl[lane] = gl[lane];
+    // LDS accesses of one wave are performed in program order; the fences
+    // keep the compiler from moving the reads that follow above the writes.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Ends a chunk: the next stage_chunk may overwrite the slot.
+__device__ __forceinline__ void end_chunk() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Quotient of n < 2^30 by the divisor whose magic is (m, shift): exact
+// (Granlund-Montgomery with a round-up multiplier, see divmagic()).
+__device__ __forceinline__ u32 fast_div(u32 n, u64 m, int shift) {
+    return (u32)(((u64)n * m) >> shift);
+}
+
+}  // namespace msda

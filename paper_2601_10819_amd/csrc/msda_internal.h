@@ -1,5 +1,6 @@
 // Internal interface between the C-ABI layer (msda_api.cpp) and the HIP
-// kernels (msda_kernels.hip). Not installed; not part of the public ABI.
+// kernels (msda_fwd.hip, msda_bwd.hip, msda_sort.hip, msda_util.hip). Not
+// installed; not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,7 +19,9 @@ struct OpArgs {
     const float* level_scale;     // [L] (FP8) or nullptr
     const float* grad_out;        // [B][A][C] (backward)
     float* out;                   // [B][A][C] (forward)
-    float* gfeat_acc;             // FP32 [B][R][C] accumulator for grad_feat, or nullptr
+    float* gfeat_acc;             // atomic grad_feat: FP32 [B][R][C] accumulator, or nullptr
+    uint32_t* rec_key;            // sorted grad_feat: [4*S] row keys, or nullptr
+    float* rec_cw;                // sorted grad_feat: [4*S] corner weights
     float* grad_loc;              // or nullptr
     float* grad_w;                // or nullptr
     int32_t B, N, L, A, P, C, G;
@@ -28,6 +31,22 @@ struct OpArgs {
     int32_t pairs_per_chunk;      // (keypoint, camera) pairs staged per wave step
 };
 
+// The per-row grad_feat reduction over sorted records.
+struct ReduceArgs {
+    const uint32_t* vals;         // record indices (4*sample + corner), sorted by row
+    const uint32_t* off;          // [nrows + 1] first record of each row
+    const float* rec_cw;          // [4*S] corner weights
+    const float* w;               // weights, [S][G]
+    const float* grad_out;        // [B*A][C]
+    void* grad_feat;              // [nrows][C], FP32 or BF16
+    uint32_t nrows;               // B * R
+    uint32_t nrec;                // records: 4 * B * A * P * N * L
+    int32_t C, G;
+    int32_t lps_shift;            // log2(C / chans_per_lane)
+    uint64_t magic;               // sample -> anchor: s / (P*N*L) == (s * magic) >> magic_shift
+    int32_t magic_shift;
+};
+
 enum FeatType { kF32 = 0, kBF16 = 1, kFP8 = 2 };
 
 // Launchers return hipSuccess or the launch error. They enqueue only.
@@ -35,6 +54,16 @@ hipError_t launch_forward(const OpArgs& a, int dtype, int cpl, int waves, size_t
                           hipStream_t s);
 hipError_t launch_backward(const OpArgs& a, int dtype, int cpl, int waves, size_t lds_bytes,
                            hipStream_t s);
+hipError_t launch_gfeat_reduce(const ReduceArgs& r, int out_dtype, int cpl, hipStream_t s);
+// Stable sort of the n record keys (keys_a, values = indices) by key in
+// [0, nrows]; *sorted_vals receives the sorted indices (in vals_a or vals_b)
+// and off[0..nrows] the segment starts. scratch: sort_scratch_words(n) words.
+hipError_t launch_sort_records(uint32_t* keys_a, uint32_t* keys_b, uint32_t* vals_a,
+                               uint32_t* vals_b, uint32_t n, uint32_t nrows, uint32_t* scratch,
+                               uint32_t* off, uint32_t** sorted_vals, hipStream_t s);
+size_t sort_scratch_words(uint32_t n);
+int sort_passes(uint32_t max_key);
+
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, size_t n, hipStream_t s);
 hipError_t launch_quantize_fp8(const float* x, const int32_t* shapes, const int32_t* starts,
@@ -43,8 +72,14 @@ hipError_t launch_quantize_fp8(const float* x, const int32_t* shapes, const int3
                                hipStream_t s);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
-// Per-sample LDS bytes: geometry table + per-wave staging / reduction area.
+// LDS bytes of a forward/backward launch: geometry table + per-wave staging
+// (or the cross-wave reduction area, whichever is larger).
 size_t lds_bytes_for(const OpArgs& a, int waves);
 int max_pairs_per_chunk(int L, int G);
+
+// Benchmark instrumentation (msda_set_kernel_events): called around every
+// kernel launch; records the caller's events when enabled, else does nothing.
+void mark_begin(const char* kernel, hipStream_t s);
+void mark_end(hipStream_t s);
 
 }  // namespace msda

@@ -92,7 +92,7 @@ def make_desc(feat: torch.Tensor, layout: Layout, sampling_loc: torch.Tensor,
     keep = [layout]
     if tile:
         t = _lib.MsdaTile(int(tile.get("waves_per_anchor", 0)), int(tile.get("chans_per_lane", 0)),
-                          int(tile.get("anchors_per_block", 0)), 0)
+                          int(tile.get("anchors_per_block", 0)), int(tile.get("scatter", 0)))
         keep.append(t)
         d.tile = ctypes.pointer(t)
     d._keep = keep        # host arrays must outlive the call
@@ -118,14 +118,15 @@ def forward(feat, layout: Layout, sampling_loc, weights, level_scale=None, tile=
     return out
 
 
-def backward_workspace_bytes(feat, layout, sampling_loc, weights, deterministic=False) -> int:
-    d = make_desc(feat, layout, sampling_loc, weights, deterministic=deterministic)
+def backward_workspace_bytes(feat, layout, sampling_loc, weights, deterministic=False,
+                             tile=None) -> int:
+    d = make_desc(feat, layout, sampling_loc, weights, deterministic=deterministic, tile=tile)
     return int(_lib.load().msda_backward_workspace_size(ctypes.byref(d)))
 
 
 def backward(feat, layout: Layout, sampling_loc, weights, grad_out,
              need_feat=True, need_loc=True, need_w=True, deterministic=False, tile=None,
-             workspace: Optional[torch.Tensor] = None, stream=None
+             workspace: Optional[torch.Tensor] = None, level_scale=None, stream=None
              ) -> Tuple[Optional[torch.Tensor], Optional[torch.Tensor], Optional[torch.Tensor]]:
     """(grad_feat, grad_sampling_loc, grad_weights); an unrequested one is None."""
     lib = _lib.load()
@@ -133,7 +134,8 @@ def backward(feat, layout: Layout, sampling_loc, weights, grad_out,
     _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
     _need_cuda_contig("weights", weights, torch.float32)
     _need_cuda_contig("grad_out", grad_out, torch.float32)
-    d = make_desc(feat, layout, sampling_loc, weights, deterministic=deterministic, tile=tile)
+    d = make_desc(feat, layout, sampling_loc, weights, level_scale, deterministic=deterministic,
+                  tile=tile)
     gf = torch.empty_like(feat) if need_feat else None
     gl = torch.empty_like(sampling_loc) if need_loc else None
     gw = torch.empty_like(weights) if need_w else None
@@ -191,6 +193,7 @@ class MSDAFunction(torch.autograd.Function):
         out = forward(feat, layout, sampling_loc, weights, level_scale=level_scale, tile=tile)
         ctx.save_for_backward(feat, sampling_loc, weights)
         ctx.layout, ctx.deterministic, ctx.tile = layout, deterministic, tile
+        ctx.level_scale = level_scale
         return out
 
     @staticmethod
@@ -201,7 +204,8 @@ class MSDAFunction(torch.autograd.Function):
         if nf or nl or nw:
             gf, gl, gw = backward(feat, ctx.layout, loc, w, grad_out.contiguous(),
                                   need_feat=nf, need_loc=nl, need_w=nw,
-                                  deterministic=ctx.deterministic, tile=ctx.tile)
+                                  deterministic=ctx.deterministic, tile=ctx.tile,
+                                  level_scale=ctx.level_scale)
         return gf, gl, gw, None, None, None, None
 
 

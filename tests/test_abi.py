@@ -144,14 +144,32 @@ def test_unsupported_requests(lib):
 def test_backward_validation(lib):
     d = desc(Geo(), dtype=_lib.MSDA_FP8_E4M3, C=64, scale=FAKE)
     expect(lib, bwd(lib, d), UNS, "FP8")
+    # sorted grad_feat (the default): workspace for 4 records per sample
     d = desc(Geo(), dtype=_lib.MSDA_BF16, C=64)
     need = lib.msda_backward_workspace_size(ctypes.byref(d))
-    assert need == 1 * Geo().rows * 64 * 4
+    nrec = 4 * 1 * 4 * 3 * 2 * 2
+    assert need >= 5 * 4 * nrec + 4 * (Geo().rows + 1)
     expect(lib, bwd(lib, d), WS, "workspace")
     expect(lib, bwd(lib, d, ws=FAKE + (1 << 20), ws_bytes=need - 4), WS)
     expect(lib, bwd(lib, d, ws=(FAKE + (1 << 20)) + 8, ws_bytes=need + 64), WS, "aligned")
-    d = desc(Geo())
+    # no grad_feat: no workspace needed, so none is checked
+    # atomic grad_feat: FP32 needs none, BF16 an FP32 accumulator
+    d = desc(Geo(), tile=(0, 0, 0, _lib.MSDA_SCATTER_ATOMIC))
     assert lib.msda_backward_workspace_size(ctypes.byref(d)) == 0
+    d = desc(Geo(), dtype=_lib.MSDA_BF16, C=64, tile=(0, 0, 0, _lib.MSDA_SCATTER_ATOMIC))
+    assert lib.msda_backward_workspace_size(ctypes.byref(d)) == Geo().rows * 64 * 4
+    # deterministic excludes the atomic form; unknown forms are rejected
+    d = desc(Geo(), flags=_lib.MSDA_DETERMINISTIC, tile=(0, 0, 0, _lib.MSDA_SCATTER_ATOMIC))
+    expect(lib, bwd(lib, d), UNS, "DETERMINISTIC")
+    d = desc(Geo(), tile=(0, 0, 0, 7))
+    expect(lib, bwd(lib, d, ws=FAKE + (1 << 20), ws_bytes=1 << 30), UNS, "scatter")
+
+
+def test_kernel_event_hook_validation(lib):
+    expect(lib, lib.msda_set_kernel_events(FAKE, 0), INV, "max_kernels")
+    assert lib.msda_set_kernel_events(None, 0) == _lib.MSDA_OK
+    assert lib.msda_recorded_kernels() == 0
+    assert lib.msda_recorded_kernel_name(0) == b""
 
 
 def test_empty_anchor_set_is_ok_without_launch(lib):

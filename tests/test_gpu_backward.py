@@ -5,8 +5,8 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import (GRAD_F32_MAXREL, GRAD_F32_TOL, anchor_subset, assert_close, host,
-                     oracle_backward_subset, to_device)
+from helpers import (BF16_TOL, GRAD_F32_MAXREL, GRAD_F32_TOL, anchor_subset, assert_close,
+                     host, oracle_backward_subset, to_device)
 from paper_2601_10819_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -159,3 +159,48 @@ def test_autograd_function(ops, oracle_mod):
     feat2 = feat.detach().requires_grad_(True)
     ops.msda(feat2, layout, loc2, w.detach()).sum().backward()
     assert feat2.grad is not None and loc2.grad is None
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16], ids=["f32", "bf16"])
+def test_sorted_grad_feat_is_bitwise_reproducible(ops, oracle_mod, dtype):
+    """The default (sorted) grad_feat sums each row in sample order: repeated
+    calls and different launch shapes give identical bits, and both it and
+    the float-atomic form match the oracle."""
+    p = synth.sparse4d(seed=3, anchors=300)
+    go = synth.grad_out_like(p, seed=8).cuda()
+    feat, layout, loc, w = to_device(p, dtype)
+    runs = []
+    for tile in [None, {"waves_per_anchor": 1}, {"waves_per_anchor": 8},
+                 {"waves_per_anchor": 2, "chans_per_lane": 4}, None]:
+        gf, _, _ = ops.backward(feat, layout, loc, w, go, need_loc=False, need_w=False,
+                                tile=tile, deterministic=True)
+        runs.append(gf)
+    torch.cuda.synchronize()
+    for r in runs[1:]:
+        assert torch.equal(r, runs[0])
+    ref_feat = p.feat.to(dtype).double()
+    rgf, _, _ = oracle_mod.backward(ref_feat, p.spatial_shapes, p.level_start_index,
+                                    p.sampling_loc, p.weights, go.cpu(), need_loc=False,
+                                    need_w=False)
+    tol = GRAD_F32_TOL if dtype == torch.float32 else BF16_TOL
+    assert_close(host(runs[0]), rgf, tol, None, "sorted grad_feat")
+    ga, _, _ = ops.backward(feat, layout, loc, w, go, need_loc=False, need_w=False,
+                            tile={"scatter": 2})
+    torch.cuda.synchronize()
+    assert_close(host(ga), rgf, tol, None, "atomic grad_feat")
+
+
+def test_sorted_grad_feat_hot_pixels(ops, oracle_mod):
+    """Every sample of every anchor on the same few pixels: segments of
+    thousands of records per row."""
+    p = synth.small(seed=12, cams=2, levels=((6, 8), (3, 4)), C=64, G=4, A=150, P=13)
+    gen = torch.Generator().manual_seed(4)
+    # 3 distinct points shared by all anchors and keypoints
+    pts = torch.tensor([[0.31, 0.42], [0.55, 0.61], [0.8, 0.2]])
+    choice = torch.randint(0, 3, p.sampling_loc.shape[:-1], generator=gen)
+    p.sampling_loc.copy_(pts[choice])
+    go = synth.grad_out_like(p, seed=9)
+    gf, gl, gw = run_bwd(ops, p, go)
+    ref = oracle_mod.backward(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                              p.weights, go)
+    check_all((gf, gl, gw), ref, "hot pixels")

@@ -88,6 +88,11 @@ def test_forward_empty_anchor_set(ops):
     out = ops.forward(feat, layout, loc[:, :0].contiguous(), w[:, :0].contiguous())
     torch.cuda.synchronize()
     assert out.shape == (1, 0, p.channels)
+    # the backward of an empty anchor set still writes grad_feat (all zero)
+    gf, gl, gw = ops.backward(feat, layout, loc[:, :0].contiguous(), w[:, :0].contiguous(),
+                              torch.zeros(1, 0, p.channels, device="cuda"))
+    torch.cuda.synchronize()
+    assert torch.all(gf == 0) and gl.numel() == 0 and gw.numel() == 0
 
 
 def test_forward_pixel_centres_exact(ops):

@@ -140,4 +140,4 @@ def test_fp8_backward_rejected(ops):
     codes, scales = ops.quantize_fp8(p.feat.cuda(), layout)
     with pytest.raises(ops._lib.MSDAError, match="UNSUPPORTED"):
         ops.backward(codes, layout, p.sampling_loc.cuda(), p.weights.cuda(),
-                     torch.zeros(1, p.num_anchors, 64, device="cuda"))
+                     torch.zeros(1, p.num_anchors, 64, device="cuda"), level_scale=scales)
