@@ -6,7 +6,10 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/msda.h"
 #include "msda_internal.h"
@@ -189,23 +192,79 @@ bool aligned(const void* p, size_t n) { return ((uintptr_t)p % n) == 0; }
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Workspace of the sorted grad_feat form: record keys (x2 for the sort),
-// values (x2), corner weights, row offsets and the sort's histogram scratch.
+// values (x2), fractions, per-cell offsets, region tables and the sort's
+// histogram scratch.
 struct SortedWs {
-    size_t keys_a, keys_b, vals_a, vals_b, cw, off, scratch, total;
+    size_t keys_a, keys_b, vals_a, vals_b, frac, off, cell_start, tile_start, tile_region,
+        scratch, total;
 };
 
-SortedWs sorted_layout(uint64_t nrec, uint64_t nrows) {
+SortedWs sorted_layout(uint64_t nrec, uint64_t ncells, uint64_t nregions) {
     SortedWs w;
     const size_t rec = align256(nrec * 4);
     w.keys_a = 0;
     w.keys_b = w.keys_a + rec;
     w.vals_a = w.keys_b + rec;
     w.vals_b = w.vals_a + rec;
-    w.cw = w.vals_b + rec;
-    w.off = w.cw + rec;
-    w.scratch = w.off + align256((nrows + 1) * 4);
+    w.frac = w.vals_b + rec;
+    w.off = w.frac + align256(nrec * 8);
+    w.cell_start = w.off + align256((ncells + 1) * 4);
+    w.tile_start = w.cell_start + align256(nregions * 4);
+    w.tile_region = w.tile_start + align256((nregions + 1) * 4);
+    w.scratch = w.tile_region + align256(nregions * 4);
     w.total = w.scratch + align256(msda::sort_scratch_words((uint32_t)nrec) * 4);
     return w;
+}
+
+// Cells and 4x4 tiles of one batch item (from the host mirror of the shapes).
+void cells_and_tiles(const msda_desc* d, uint64_t* cells, uint64_t* tiles) {
+    *cells = *tiles = 0;
+    const int64_t NL = (int64_t)d->num_cams * d->num_levels;
+    for (int64_t i = 0; i < NL; ++i) {
+        const uint64_t H = d->host_spatial_shapes[2 * i], W = d->host_spatial_shapes[2 * i + 1];
+        *cells += (H + 1) * (W + 1);
+        *tiles += ((H + msda::kTileH - 1) / msda::kTileH) * ((W + msda::kTileW - 1) / msda::kTileW);
+    }
+}
+
+// Tiles (of one batch item, in slot order: coarse levels first) of the levels
+// whose regions are at most 1/16 of the largest region's area -- the levels
+// where a pixel collects 16x or more the samples of the finest one.
+uint32_t heavy_tiles(const msda_desc* d) {
+    const int N = d->num_cams, L = d->num_levels;
+    int64_t max_area = 0;
+    for (int i = 0; i < N * L; ++i)
+        max_area = std::max<int64_t>(max_area, (int64_t)d->host_spatial_shapes[2 * i] *
+                                                   d->host_spatial_shapes[2 * i + 1]);
+    uint32_t tiles = 0;
+    for (int o = 0; o < N * L; ++o) {            // slot o -> level L-1-o/N, camera o%N
+        const int l = L - 1 - o / N, n = o % N, r = n * L + l;
+        const int64_t H = d->host_spatial_shapes[2 * r], W = d->host_spatial_shapes[2 * r + 1];
+        if (H * W * 16 > max_area) break;
+        tiles += (uint32_t)(((H + msda::kTileH - 1) / msda::kTileH) *
+                            ((W + msda::kTileW - 1) / msda::kTileW));
+    }
+    return tiles;
+}
+
+// 1 if the regions are pairwise disjoint; *cover = they tile [0, R) exactly.
+bool regions_disjoint(const msda_desc* d, bool* cover) {
+    const int64_t NL = (int64_t)d->num_cams * d->num_levels;
+    std::vector<std::pair<int64_t, int64_t>> iv;
+    iv.reserve(NL);
+    for (int64_t i = 0; i < NL; ++i)
+        iv.emplace_back(d->host_level_start_index[i],
+                        d->host_level_start_index[i] + (int64_t)d->host_spatial_shapes[2 * i] *
+                                                           d->host_spatial_shapes[2 * i + 1]);
+    std::sort(iv.begin(), iv.end());
+    int64_t end = 0, covered = 0;
+    for (const auto& p : iv) {
+        if (p.first < end) return false;
+        covered += p.second - p.first;
+        end = p.second;
+    }
+    *cover = covered == d->rows;
+    return true;
 }
 
 int scatter_mode(const msda_desc* d) {
@@ -213,8 +272,8 @@ int scatter_mode(const msda_desc* d) {
     return m == MSDA_SCATTER_AUTO ? MSDA_SCATTER_SORTED : m;
 }
 
-uint64_t num_records(const msda_desc* d) {
-    return 4ull * (uint64_t)d->batch * (uint64_t)d->num_anchors * (uint64_t)d->num_points *
+uint64_t num_samples(const msda_desc* d) {
+    return (uint64_t)d->batch * (uint64_t)d->num_anchors * (uint64_t)d->num_points *
            (uint64_t)d->num_cams * (uint64_t)d->num_levels;
 }
 
@@ -299,7 +358,11 @@ size_t msda_backward_workspace_size(const msda_desc* d) {
             return (size_t)d->batch * (size_t)d->rows * (size_t)d->channels * sizeof(float);
         return 0;
     }
-    return sorted_layout(num_records(d), (uint64_t)d->batch * (uint64_t)d->rows).total;
+    if (!d->host_spatial_shapes || d->num_cams < 1 || d->num_levels < 1) return 0;
+    uint64_t cells, tiles;
+    cells_and_tiles(d, &cells, &tiles);
+    return sorted_layout(num_samples(d), cells * (uint64_t)d->batch,
+                         (uint64_t)d->num_cams * d->num_levels).total;
 }
 
 msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
@@ -323,20 +386,28 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
         return fail(MSDA_ERR_UNSUPPORTED, "unknown scatter mode %d", mode);
     if ((desc->flags & MSDA_DETERMINISTIC) && mode == MSDA_SCATTER_ATOMIC)
         return fail(MSDA_ERR_UNSUPPORTED, "MSDA_DETERMINISTIC excludes MSDA_SCATTER_ATOMIC");
-    const uint64_t nrec = num_records(desc);
-    const uint64_t nrows = (uint64_t)a.B * (uint64_t)a.R;
+    const uint64_t nrec = num_samples(desc);
+    uint64_t cells = 0, tiles = 0;
+    cells_and_tiles(desc, &cells, &tiles);
+    const uint64_t ncells = cells * (uint64_t)a.B;
     // the reduction's lane layout: FP32 accumulators, 4/2/1 channels per lane
     int rcpl = 0;
     for (int c : {4, 2, 1})
         if (cpl_fits(c, a.C, a.G)) { rcpl = c; break; }
+    bool cover = true;
     if (grad_feat && mode == MSDA_SCATTER_SORTED) {
-        if (nrows >= 0x7fffffffull)
-            return fail(MSDA_ERR_UNSUPPORTED, "B*R = %llu rows exceeds 2^31 - 1",
-                        (unsigned long long)nrows);
-        if (nrec >= 0xffffffffull)
-            return fail(MSDA_ERR_UNSUPPORTED, "4*B*A*P*Ncam*L = %llu records exceeds 2^32 - 1",
+        if (!regions_disjoint(desc, &cover))
+            return fail(MSDA_ERR_UNSUPPORTED,
+                        "sorted grad_feat needs disjoint regions (use MSDA_SCATTER_ATOMIC)");
+        if (ncells >= 0x7fffffffull)
+            return fail(MSDA_ERR_UNSUPPORTED, "B * cells = %llu exceeds 2^31 - 1",
+                        (unsigned long long)ncells);
+        if (nrec >= (1ull << 30))
+            return fail(MSDA_ERR_UNSUPPORTED, "B*A*P*Ncam*L = %llu samples exceeds 2^30",
                         (unsigned long long)nrec);
         if (!rcpl) return fail(MSDA_ERR_UNSUPPORTED, "no reduction lane layout for C=%d G=%d", a.C, a.G);
+        if (a.G > 64)
+            return fail(MSDA_ERR_UNSUPPORTED, "sorted grad_feat supports G <= 64 (G=%d)", a.G);
         if (rcpl == 4 && !aligned(grad_out, 16))
             return fail(MSDA_ERR_UNSUPPORTED, "grad_out must be 16-byte aligned");
     }
@@ -352,7 +423,8 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
         return fail(MSDA_ERR_UNSUPPORTED, "grad_feat must be 16-byte aligned");
 
     const hipStream_t s = (hipStream_t)stream;
-    const size_t gf_elems = (size_t)nrows * (size_t)a.C;
+    const size_t gf_elems = (size_t)a.B * (size_t)a.R * (size_t)a.C;
+    const size_t gf_bytes = gf_elems * (desc->feat_dtype == MSDA_F32 ? 4 : 2);
     char* ws = static_cast<char*>(workspace);
     hipError_t e = hipSuccess;
     a.feat = feat;
@@ -381,11 +453,23 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
         return ok();
     }
 
-    SortedWs L = {};
+    SortedWs W = {};
+    uint32_t *cell_start = nullptr, *tile_start = nullptr, *tile_region = nullptr;
     if (grad_feat) {
-        L = sorted_layout(nrec, nrows);
-        a.rec_key = reinterpret_cast<uint32_t*>(ws + L.keys_a);
-        a.rec_cw = reinterpret_cast<float*>(ws + L.cw);
+        W = sorted_layout(nrec, ncells, (uint64_t)a.N * a.L);
+        cell_start = reinterpret_cast<uint32_t*>(ws + W.cell_start);
+        tile_start = reinterpret_cast<uint32_t*>(ws + W.tile_start);
+        tile_region = reinterpret_cast<uint32_t*>(ws + W.tile_region);
+        if ((e = msda::launch_region_tables(spatial_shapes, a.N, a.L, cell_start, tile_start,
+                                            tile_region, s)) != hipSuccess)
+            return hip_fail(e, "region tables");
+        a.rec_key = reinterpret_cast<uint32_t*>(ws + W.keys_a);
+        a.rec_frac = reinterpret_cast<float2*>(ws + W.frac);
+        a.cell_start = cell_start;
+        a.cells_per_item = (uint32_t)cells;
+        // rows outside every region are not visited by a tile
+        if (!cover && (e = msda::launch_fill_zero(grad_feat, gf_bytes, s)) != hipSuccess)
+            return hip_fail(e, "zero grad_feat");
     }
     if (a.A > 0 && (grad_feat || grad_sampling_loc || grad_weights) &&
         (e = msda::launch_backward(a, desc->feat_dtype, cpl, waves, msda::lds_bytes_for(a, waves),
@@ -394,29 +478,49 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
     if (!grad_feat) return ok();
 
     uint32_t* sorted = nullptr;
-    uint32_t* off = reinterpret_cast<uint32_t*>(ws + L.off);
-    e = msda::launch_sort_records(reinterpret_cast<uint32_t*>(ws + L.keys_a),
-                                  reinterpret_cast<uint32_t*>(ws + L.keys_b),
-                                  reinterpret_cast<uint32_t*>(ws + L.vals_a),
-                                  reinterpret_cast<uint32_t*>(ws + L.vals_b), (uint32_t)nrec,
-                                  (uint32_t)nrows, reinterpret_cast<uint32_t*>(ws + L.scratch),
+    uint32_t* off = reinterpret_cast<uint32_t*>(ws + W.off);
+    e = msda::launch_sort_records(reinterpret_cast<uint32_t*>(ws + W.keys_a),
+                                  reinterpret_cast<uint32_t*>(ws + W.keys_b),
+                                  reinterpret_cast<uint32_t*>(ws + W.vals_a),
+                                  reinterpret_cast<uint32_t*>(ws + W.vals_b), (uint32_t)nrec,
+                                  (uint32_t)ncells, reinterpret_cast<uint32_t*>(ws + W.scratch),
                                   off, &sorted, s);
     if (e != hipSuccess) return hip_fail(e, "sort grad_feat records");
-    msda::ReduceArgs r = {};
-    r.vals = sorted;
-    r.off = off;
-    r.rec_cw = a.rec_cw;
-    r.w = weights;
-    r.grad_out = grad_out;
-    r.grad_feat = grad_feat;
-    r.nrows = (uint32_t)nrows;
-    r.nrec = (uint32_t)nrec;
-    r.C = a.C;
-    r.G = a.G;
-    r.lps_shift = log2i(a.C / rcpl);
-    divmagic((uint32_t)a.P * (uint32_t)a.N * (uint32_t)a.L, &r.magic, &r.magic_shift);
-    if ((e = msda::launch_gfeat_reduce(r, desc->feat_dtype, rcpl, s)) != hipSuccess)
-        return hip_fail(e, "grad_feat row reduction");
+    msda::TileArgs t = {};
+    t.vals = sorted ? sorted : reinterpret_cast<uint32_t*>(ws + W.vals_a);
+    t.off = off;
+    t.frac = a.rec_frac;
+    t.w = weights;
+    t.grad_out = grad_out;
+    t.grad_feat = grad_feat;
+    t.shapes = spatial_shapes;
+    t.starts = level_start_index;
+    t.cell_start = cell_start;
+    t.tile_start = tile_start;
+    t.tile_region = tile_region;
+    t.tiles_per_item = (uint32_t)tiles;
+    t.cells_per_item = (uint32_t)cells;
+    t.nrec = (uint32_t)(nrec > 0 ? nrec : 1);
+    t.NL = a.N * a.L;
+    t.B = a.B;
+    t.C = a.C;
+    t.G = a.G;
+    t.R = a.R;
+    t.lps_shift = log2i(a.C / rcpl);
+    divmagic((uint32_t)a.P * (uint32_t)a.N * (uint32_t)a.L, &t.magic, &t.magic_shift);
+    // Tiles of coarse levels collect many more samples per pixel: they come
+    // first in slot order and get 4 waves each (partial sums added as a
+    // tree); the rest get one wave each.
+    const uint32_t heavy = heavy_tiles(desc);
+    const uint32_t split[3] = {0u, heavy, (uint32_t)tiles};
+    for (int part = 0; part < 2; ++part) {
+        t.tile_begin = split[part];
+        t.tile_end = split[part + 1];
+        t.waves = part == 0 ? 4 : 1;
+        if (t.tile_end > t.tile_begin &&
+            (e = msda::launch_gfeat_tiles(t, desc->feat_dtype, rcpl, s)) != hipSuccess)
+            return hip_fail(e, "grad_feat tile reduction");
+    }
     return ok();
 }
 

@@ -9,17 +9,25 @@
 //   grad_loc   = sum over levels of W (H) * w * (d/dx (d/dy) of the bilinear
 //                blend of d), reduced over the sample's lanes once per
 //                (keypoint, camera) pair.
-// For grad_feat it either emits one record per (sample, corner) -- the row
-// touched and the corner weight, at a fixed position 4*sample + corner --
-// for the sorted per-row reduction below (deterministic, no float atomics),
-// or adds w * cw * grad_out to an FP32 accumulator with float atomics.
+// For grad_feat it either emits one record per sample -- the bilinear cell
+// the sample falls in (its top-left neighbour, (y0+1, x0+1) in an
+// (H+1) x (W+1) grid per region) and its fractions (lx, ly) -- for the
+// sorted, tiled reduction below (deterministic, no float atomics), or adds
+// w * cw * grad_out to an FP32 accumulator with float atomics.
 //
-// gfeat_reduce_kernel: after the records are sorted by row (msda_sort.hip),
-// one group of lanes per feature row sums cw * w[g] * grad_out[anchor] over
-// the row's records in sample order and writes the row once, in FP32 or
-// BF16 (rounded to nearest even), zeros for rows no sample touches.
+// gfeat_tile_kernel: after the records are sorted by cell (msda_sort.hip),
+// each 4x4 tile of pixels of a region visits the 5x5 cells whose samples
+// touch it, in a fixed order, and adds w * cw * grad_out[anchor] of each
+// sample's corners that fall in the tile to register accumulators; each
+// sample's grad_out row is read once per tile it touches (about 1.6 times
+// on average) instead of once per corner. The tile's records are split
+// between its waves and the partial sums added in a fixed order, so
+// grad_feat is bitwise reproducible; every pixel is written once, in FP32
+// or BF16 (rounded to nearest even), zeros where no sample lands.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "msda_common.h"
 
@@ -66,8 +74,8 @@ __global__ void __launch_bounds__(512) msda_bwd_kernel(OpArgs a) {
     float* gwout = a.grad_w ? a.grad_w + (size_t)ba * npairs * LG : nullptr;
     float* glout = a.grad_loc ? a.grad_loc + (size_t)ba * npairs * 2 : nullptr;
     const bool need_vals = gwout || glout;
-    const u32 row_base = (u32)b * (u32)a.R;        // first global row of this batch item
-    const u32 no_row = (u32)a.B * (u32)a.R;        // key of a corner outside its level
+    const u32 cell_base = (u32)b * a.cells_per_item;  // first cell of this batch item
+    const u32 no_cell = (u32)a.B * a.cells_per_item;  // key of a sample outside its level
 
     const int nchunks = (npairs + J - 1) / J;
     for (int k = wave; k < nchunks; k += nwaves) {
@@ -84,17 +92,14 @@ __global__ void __launch_bounds__(512) msda_bwd_kernel(OpArgs a) {
                 const Geo gm = geo[n * a.L + l];
                 const Corners cr = corners_of(u, v, gm, row_bytes, lane_off);
                 const float wl = wj[l * a.G];
-                if (a.rec_key) {
-                    // records of this sample's 4 corners, written by its first lanes
-                    const u32 s4 = ((u32)(ba * npairs + j) * (u32)a.L + (u32)l) * 4u;
-                    for (int q = sl_lane; q < 4; q += lps) {
-                        const int row = q == 0 ? cr.row[0] : q == 1 ? cr.row[1]
-                                      : q == 2 ? cr.row[2] : cr.row[3];
-                        const float cw = q == 0 ? cr.cw[0] : q == 1 ? cr.cw[1]
-                                       : q == 2 ? cr.cw[2] : cr.cw[3];
-                        a.rec_key[s4 + q] = row >= 0 ? row_base + (u32)row : no_row;
-                        a.rec_cw[s4 + q] = cw;
-                    }
+                if (a.rec_key && sl_lane == 0) {
+                    // the sample's record: its bilinear cell and fractions
+                    const u32 sidx = (u32)(ba * npairs + j) * (u32)a.L + (u32)l;
+                    a.rec_key[sidx] = cr.valid ? cell_base + gm.cstart +
+                                                     (u32)(cr.y0 + 1) * (u32)(gm.W + 1) +
+                                                     (u32)(cr.x0 + 1)
+                                               : no_cell;
+                    a.rec_frac[sidx] = make_float2(cr.lx, cr.ly);
                 }
                 if (gacc) {
 #pragma unroll
@@ -117,15 +122,15 @@ __global__ void __launch_bounds__(512) msda_bwd_kernel(OpArgs a) {
                 for (int c = 0; c < 4; ++c) {
                     float f[CPL];
                     widen<FT, CPL>(raw[c], f);
-                    float s = 0.f;
+                    float sum = 0.f;
 #pragma unroll
-                    for (int i = 0; i < CPL; ++i) s = fmaf(go[i], f[i], s);
-                    d[c] = s;
+                    for (int i = 0; i < CPL; ++i) sum = fmaf(go[i], f[i], sum);
+                    d[c] = sum;
                 }
                 if (gwout) {
                     float t = cr.cw[0] * d[0] + cr.cw[1] * d[1] + cr.cw[2] * d[2] +
                               cr.cw[3] * d[3];
-                    for (int s = 1; s < lpg; s <<= 1) t += xor_shuffle(t, s);
+                    for (int sft = 1; sft < lpg; sft <<= 1) t += xor_shuffle(t, sft);
                     if ((lane & (lpg - 1)) == 0) gwout[(size_t)j * LG + l * a.G + g] = t;
                 }
                 // d val / dx = hy (F01 - F00) + ly (F11 - F10); x = u W - 0.5
@@ -145,6 +150,18 @@ __global__ void __launch_bounds__(512) msda_bwd_kernel(OpArgs a) {
             }
         }
         end_chunk();
+    }
+}
+
+template <int I>
+using int_c = std::integral_constant<int, I>;
+
+// f(int_c<0>{}), ..., f(int_c<N-1>{}): a loop whose index is a compile-time constant.
+template <int N, int I = 0, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (I < N) {
+        f(int_c<I>{});
+        static_for<N, I + 1>(f);
     }
 }
 
@@ -182,52 +199,290 @@ __device__ __forceinline__ void load_go(const float* p, float* v) {
     }
 }
 
-template <class OT, int CPL>
-__global__ void __launch_bounds__(256) gfeat_reduce_kernel(ReduceArgs r) {
-    const int lane = threadIdx.x & 63;
-    const int lps = 1 << r.lps_shift;
-    const u32 row = blockIdx.x * (blockDim.x >> r.lps_shift) + (threadIdx.x >> r.lps_shift);
-    if (row >= r.nrows) return;
-    const int c0 = (lane & (lps - 1)) * CPL;
-    const int g = c0 / (r.C / r.G);
-    // offsets and indices are checked so that an inconsistent sort could only
-    // give wrong sums, never an access outside the workspace
-    const u32 e1 = min(r.off[row + 1], r.nrec);
-    const u32 e0 = min(r.off[row], e1);
-    float acc[CPL];
+// Tables of the tiled reduction for one batch item, from the shapes: the
+// first cell of each region (regions in order, (H+1)(W+1) cells each) and,
+// over processing slots (coarse levels first: slot o = (L-1-l)*N + n), the
+// first tile and the region of each slot. One block of 256 threads; N*L <=
+// 1024 regions, 4 per thread.
+__global__ void __launch_bounds__(256) region_tables_kernel(const int32_t* shapes, int N, int L,
+                                                            u32* cell_start, u32* tile_start,
+                                                            u32* tile_region) {
+    __shared__ u32 lds4[4];
+    const int NL = N * L;
+    u32 cells[4], tiles[4], sum_c = 0, sum_t = 0;
 #pragma unroll
-    for (int i = 0; i < CPL; ++i) acc[i] = 0.f;
-    u32 e = e0;
-    // four records at a time: their loads are issued before the sums
-    for (; e + 4 <= e1; e += 4) {
-        u32 idx[4];
-        float coef[4], gv[4][CPL];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) idx[q] = min(r.vals[e + q], r.nrec - 1);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const u32 s = idx[q] >> 2;
-            coef[q] = r.rec_cw[idx[q]] * r.w[(size_t)s * r.G + g];
-            const u32 anchor = fast_div(s, r.magic, r.magic_shift);
-            load_go<CPL>(r.grad_out + (size_t)anchor * r.C + c0, gv[q]);
+    for (int k = 0; k < 4; ++k) {
+        const int i = 4 * threadIdx.x + k;
+        cells[k] = tiles[k] = 0u;
+        if (i < NL) {
+            const u32 H = (u32)shapes[2 * i], W = (u32)shapes[2 * i + 1];
+            cells[k] = (H + 1) * (W + 1);
+            const int o = i;                     // slot o -> region r
+            const int r = (o % N) * L + (L - 1 - o / N);
+            const u32 Hr = (u32)shapes[2 * r], Wr = (u32)shapes[2 * r + 1];
+            tiles[k] = ((Hr + kTileH - 1) / kTileH) * ((Wr + kTileW - 1) / kTileW);
         }
+        sum_c += cells[k];
+        sum_t += tiles[k];
+    }
+    u32 total_c, total_t;
+    u32 run_c = block_inclusive_scan(sum_c, lds4, &total_c) - sum_c;
+    u32 run_t = block_inclusive_scan(sum_t, lds4, &total_t) - sum_t;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+    for (int k = 0; k < 4; ++k) {
+        const int i = 4 * threadIdx.x + k;
+        if (i < NL) {
+            cell_start[i] = run_c;
+            tile_start[i] = run_t;
+            tile_region[i] = (u32)((i % N) * L + (L - 1 - i / N));
+        }
+        run_c += cells[k];
+        run_t += tiles[k];
+    }
+    if (threadIdx.x == 0) tile_start[NL] = total_t;
+}
+
+// One sample's corners that fall in the tile, added to the accumulators.
+// The sample's cell sits at tile offset (DY, DX), so the corner -> pixel map
+// is static: corners land on (DY-1, DX-1), (DY-1, DX), (DY, DX-1), (DY, DX).
+template <int DY, int DX, int TH, int TW, int CPL>
+__device__ __forceinline__ void add_sample(float (&acc)[TH][TW][CPL], float fx, float fy,
+                                           float wv, const float* gv) {
+    const float hx = 1.f - fx, hy = 1.f - fy;
+    const float k00 = hy * hx * wv, k01 = hy * fx * wv;
+    const float k10 = fy * hx * wv, k11 = fy * fx * wv;
+    if constexpr (DY >= 1 && DX >= 1) {
 #pragma unroll
-            for (int i = 0; i < CPL; ++i) acc[i] = fmaf(coef[q], gv[q][i], acc[i]);
+        for (int i = 0; i < CPL; ++i) acc[DY - 1][DX - 1][i] = fmaf(k00, gv[i], acc[DY - 1][DX - 1][i]);
+    }
+    if constexpr (DY >= 1 && DX < TW) {
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) acc[DY - 1][DX][i] = fmaf(k01, gv[i], acc[DY - 1][DX][i]);
+    }
+    if constexpr (DY < TH && DX >= 1) {
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) acc[DY][DX - 1][i] = fmaf(k10, gv[i], acc[DY][DX - 1][i]);
+    }
+    if constexpr (DY < TH && DX < TW) {
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) acc[DY][DX][i] = fmaf(k11, gv[i], acc[DY][DX][i]);
+    }
+}
+
+// Dispatch on the cell position pos = DY * 5 + DX of a 4x4 tile's 5x5 cells
+// (uniform within the lane group) to the static accumulation: a switch, which
+// the compiler lowers to a jump table.
+template <int CPL>
+__device__ __forceinline__ void add_sample_at(int pos, float (&acc)[4][4][CPL], float fx,
+                                              float fy, float wv, const float* gv) {
+#define MSDA_CELL_CASE(P) \
+    case P: add_sample<(P) / 5, (P) % 5, 4, 4, CPL>(acc, fx, fy, wv, gv); break;
+    switch (pos) {
+        MSDA_CELL_CASE(0) MSDA_CELL_CASE(1) MSDA_CELL_CASE(2) MSDA_CELL_CASE(3) MSDA_CELL_CASE(4)
+        MSDA_CELL_CASE(5) MSDA_CELL_CASE(6) MSDA_CELL_CASE(7) MSDA_CELL_CASE(8) MSDA_CELL_CASE(9)
+        MSDA_CELL_CASE(10) MSDA_CELL_CASE(11) MSDA_CELL_CASE(12) MSDA_CELL_CASE(13)
+        MSDA_CELL_CASE(14) MSDA_CELL_CASE(15) MSDA_CELL_CASE(16) MSDA_CELL_CASE(17)
+        MSDA_CELL_CASE(18) MSDA_CELL_CASE(19) MSDA_CELL_CASE(20) MSDA_CELL_CASE(21)
+        MSDA_CELL_CASE(22) MSDA_CELL_CASE(23) MSDA_CELL_CASE(24)
+        default: break;
+    }
+#undef MSDA_CELL_CASE
+}
+
+// Cell boundaries of a tile's TH+1 cell rows, (TW+2) per row.
+constexpr int kBndPerGroup = (kTileH + 1) * (kTileW + 2);
+
+// LDS bytes of the boundary slots: one per lane group of every wave.
+__host__ __device__ inline size_t bnd_lds_bytes(const TileArgs& t) {
+    const size_t groups = (size_t)t.waves * (size_t)(64 >> t.lps_shift);
+    return (groups * kBndPerGroup * 4 + 15) & ~(size_t)15;
+}
+
+// Records handled per group of grad_out loads in flight.
+constexpr int kGoBatch = 8;
+
+template <class OT, int CPL, bool WHOLE_WAVE>
+__global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
+    static_assert(kTileH == 4 && kTileW == 4, "the cell dispatch is written for 4x4 tiles");
+    // LDS: per lane group its tile's cell boundaries; per wave a record table
+    // (64 entries of G weights, lx, ly, anchor, cell position); after the
+    // records, the waves' partial sums reuse the record tables' space.
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int TH = kTileH, TW = kTileW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lps = WHOLE_WAVE ? 64 : 1 << t.lps_shift;
+    const int spw = WHOLE_WAVE ? 1 : 64 >> t.lps_shift;
+    const int grp = WHOLE_WAVE ? 0 : lane >> t.lps_shift;
+    const int sl = WHOLE_WAVE ? lane : lane & (lps - 1);   // lane within its tile's group
+    const int stride = t.G + 4;                     // floats per record-table entry
+    u32* bnd_lds = reinterpret_cast<u32*>(smem_raw);
+    float* work = reinterpret_cast<float*>(smem_raw + bnd_lds_bytes(t));
+    float* tab = work + (size_t)wave * 64 * stride + (size_t)(lane - sl) * stride;
+
+    // tiles of one block: spw consecutive ids, one per lane group; ids run
+    // over processing slots (within [tile_begin, tile_end)) first, batch
+    // items second
+    const u32 span = t.tile_end - t.tile_begin;
+    const u32 gt = blockIdx.x * (u32)spw + (u32)grp;
+    const bool active = gt < span * (u32)t.B;
+    const u32 tt = t.tile_begin + (active ? gt / (u32)t.B : 0u);
+    const int b = active ? (int)(gt % (u32)t.B) : 0;
+    int lo = 0, hi = t.NL - 1;                      // last slot with tile_start <= tt
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t.tile_start[mid] <= tt) lo = mid; else hi = mid - 1;
+    }
+    const int r = (int)t.tile_region[lo];
+    const int H = t.shapes[2 * r], W = t.shapes[2 * r + 1];
+    const u32 lt = tt - t.tile_start[lo];
+    const u32 tpr = (u32)(W + TW - 1) / TW;
+    const int ty = (int)(lt / tpr) * TH, tx = (int)(lt % tpr) * TW;
+    const int c0 = sl * CPL;
+    const int g = c0 / (t.C / t.G);
+    const u32 cbase = (u32)b * t.cells_per_item + t.cell_start[r];
+
+    // The tile's cells are TH+1 rows of TW+1 consecutive cells; each row's
+    // records are one contiguous range of the sorted order. The group stores
+    // the (TH+1) x (TW+2) cell boundaries of those rows in its LDS slot.
+    constexpr int NB = kBndPerGroup;
+    u32* bslot = bnd_lds + ((size_t)wave * spw + (size_t)grp) * NB;
+    for (int k = sl; k < NB; k += lps) {
+        const int dy = k / (TW + 2), dx = k % (TW + 2);
+        u32 v = 0u;
+        if (active && ty + dy <= H) {
+            // cells past W+1 clamp to the row's end
+            const u32 cell = cbase + (u32)(ty + dy) * (u32)(W + 1) + (u32)min(tx + dx, W + 1);
+            v = min(t.off[cell], t.nrec);
+        }
+        bslot[k] = v;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    u32 rs[TH + 1], rn[TH + 1];                     // row range start and length
+    u32 total = 0;
+#pragma unroll
+    for (int dy = 0; dy <= TH; ++dy) {
+        const u32 a0 = bslot[dy * (TW + 2)];
+        const u32 a1 = bslot[dy * (TW + 2) + TW + 1];
+        rs[dy] = a0;
+        rn[dy] = active && ty + dy <= H && a1 > a0 ? a1 - a0 : 0u;
+        total += rn[dy];
+    }
+
+    float acc[TH][TW][CPL];
+#pragma unroll
+    for (int py = 0; py < TH; ++py)
+#pragma unroll
+        for (int px = 0; px < TW; ++px)
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) acc[py][px][i] = 0.f;
+
+    // The tile's records as one flat list, in chunks of lps; chunk k goes to
+    // wave k % waves. Each lane of the group fills one table entry (all the
+    // chunk's loads in flight together), then the group walks the chunk.
+    for (u32 base = (u32)(wave * lps); base < total; base += (u32)(t.waves * lps)) {
+        const int n = (int)min((u32)lps, total - base);
+        if (sl < n) {
+            // flat index -> (row dy, sorted position e) -> cell position dx
+            u32 f = base + (u32)sl;
+            int dy = 0;
+#pragma unroll
+            for (int k = 0; k < TH; ++k)
+                if (dy == k && f >= rn[k]) { f -= rn[k]; dy = k + 1; }
+            u32 e = rs[0] + f;
+#pragma unroll
+            for (int k = 1; k <= TH; ++k)
+                if (dy == k) e = rs[k] + f;
+            int dx = 0;
+#pragma unroll
+            for (int k = 1; k <= TW; ++k)
+                if (e >= bslot[dy * (TW + 2) + k]) dx = k;
+            const u32 s = min(t.vals[e], t.nrec - 1u);
+            const float2 fr = t.frac[s];
+            float* ent = tab + sl * stride;
+            const float* ws = t.w + (size_t)s * t.G;
+            for (int k = 0; k < t.G; ++k) ent[k] = ws[k];
+            ent[t.G] = fr.x;
+            ent[t.G + 1] = fr.y;
+            ent[t.G + 2] = __uint_as_float(fast_div(s, t.magic, t.magic_shift));
+            ent[t.G + 3] = __int_as_float(dy * (TW + 1) + dx);
+        }
+        // LDS accesses of one wave are performed in order; keep the compiler
+        // from hoisting the reads above the writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int q = 0;
+        for (; q + kGoBatch <= n; q += kGoBatch) {
+            float gv[kGoBatch][CPL];
+#pragma unroll
+            for (int k = 0; k < kGoBatch; ++k) {
+                const float* ent = tab + (q + k) * stride;
+                load_go<CPL>(t.grad_out + (size_t)__float_as_uint(ent[t.G + 2]) * t.C + c0, gv[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < kGoBatch; ++k) {
+                const float* ent = tab + (q + k) * stride;
+                add_sample_at<CPL>(__float_as_int(ent[t.G + 3]), acc, ent[t.G], ent[t.G + 1],
+                                   ent[g], gv[k]);
+            }
+        }
+        for (; q < n; ++q) {
+            const float* ent = tab + q * stride;
+            float gv[CPL];
+            load_go<CPL>(t.grad_out + (size_t)__float_as_uint(ent[t.G + 2]) * t.C + c0, gv);
+            add_sample_at<CPL>(__float_as_int(ent[t.G + 3]), acc, ent[t.G], ent[t.G + 1], ent[g],
+                               gv);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // partial sums of the waves, added pairwise in a fixed tree order:
+    // wave w += wave w + h for h = waves/2, waves/4, ..., 1
+    if (t.waves > 1) {
+        constexpr int E = TH * TW * CPL;
+        float* part = work;
+        __syncthreads();                             // record tables are dead from here on
+        for (int h = t.waves >> 1; h >= 1; h >>= 1) {
+            if (wave >= h && wave < 2 * h) {
+#pragma unroll
+                for (int py = 0; py < TH; ++py)
+#pragma unroll
+                    for (int px = 0; px < TW; ++px)
+#pragma unroll
+                        for (int i = 0; i < CPL; ++i)
+                            part[((wave - h) * E + (py * TW + px) * CPL + i) * 64 + lane] =
+                                acc[py][px][i];
+            }
+            __syncthreads();
+            if (wave < h) {
+#pragma unroll
+                for (int py = 0; py < TH; ++py)
+#pragma unroll
+                    for (int px = 0; px < TW; ++px)
+#pragma unroll
+                        for (int i = 0; i < CPL; ++i)
+                            acc[py][px][i] += part[(wave * E + (py * TW + px) * CPL + i) * 64 + lane];
+            }
+            __syncthreads();
         }
     }
-    for (; e < e1; ++e) {
-        const u32 idx = min(r.vals[e], r.nrec - 1);
-        const u32 s = idx >> 2;
-        const float coef = r.rec_cw[idx] * r.w[(size_t)s * r.G + g];
-        const u32 anchor = fast_div(s, r.magic, r.magic_shift);
-        float gv[CPL];
-        load_go<CPL>(r.grad_out + (size_t)anchor * r.C + c0, gv);
+    if (wave != 0 || !active) return;
+    const int start = t.starts[r];
 #pragma unroll
-        for (int i = 0; i < CPL; ++i) acc[i] = fmaf(coef, gv[i], acc[i]);
+    for (int py = 0; py < TH; ++py) {
+#pragma unroll
+        for (int px = 0; px < TW; ++px) {
+            const int y = ty + py, x = tx + px;
+            if (y < H && x < W) {
+                const size_t row = (size_t)b * (size_t)t.R + (size_t)(start + y * W + x);
+                store_row<OT, CPL>(t.grad_feat, row * (size_t)t.C + (size_t)c0, acc[py][px]);
+            }
+        }
     }
-    store_row<OT, CPL>(r.grad_feat, (size_t)row * r.C + c0, acc);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -255,26 +510,44 @@ hipError_t launch_backward(const OpArgs& a, int dtype, int cpl, int waves, size_
 }
 
 template <class OT, int CPL>
-static hipError_t reduce_launch(const ReduceArgs& r, hipStream_t s) {
-    const u32 rows_per_block = 256u >> r.lps_shift;
-    const u32 blocks = (r.nrows + rows_per_block - 1) / rows_per_block;
+static hipError_t tile_launch(const TileArgs& t, hipStream_t s) {
+    const u32 spw = 64u >> t.lps_shift;
+    const u32 ntiles = (t.tile_end - t.tile_begin) * (u32)t.B;
+    const u32 blocks = (ntiles + spw - 1) / spw;
     if (blocks == 0) return hipSuccess;
-    mark_begin("gfeat_reduce_kernel", s);
-    hipLaunchKernelGGL((gfeat_reduce_kernel<OT, CPL>), dim3(blocks), dim3(256), 0, s, r);
+    const size_t part = t.waves > 1 ? (size_t)(t.waves / 2) * kTileH * kTileW * CPL * 64 * 4 : 0;
+    const size_t tables = (size_t)t.waves * 64 * (t.G + 4) * sizeof(float);
+    const size_t lds = bnd_lds_bytes(t) + (part > tables ? part : tables);
+    mark_begin(t.waves > 1 ? "gfeat_tile_kernel_coarse" : "gfeat_tile_kernel", s);
+    if (t.lps_shift == 6)
+        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL, true>), dim3(blocks), dim3(64 * t.waves),
+                           lds, s, t);
+    else
+        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL, false>), dim3(blocks), dim3(64 * t.waves),
+                           lds, s, t);
     mark_end(s);
     return hipGetLastError();
 }
 
-hipError_t launch_gfeat_reduce(const ReduceArgs& r, int out_dtype, int cpl, hipStream_t s) {
+hipError_t launch_gfeat_tiles(const TileArgs& t, int out_dtype, int cpl, hipStream_t s) {
     switch (out_dtype * 100 + cpl) {
-        case kF32 * 100 + 1: return reduce_launch<TF32, 1>(r, s);
-        case kF32 * 100 + 2: return reduce_launch<TF32, 2>(r, s);
-        case kF32 * 100 + 4: return reduce_launch<TF32, 4>(r, s);
-        case kBF16 * 100 + 1: return reduce_launch<TBF16, 1>(r, s);
-        case kBF16 * 100 + 2: return reduce_launch<TBF16, 2>(r, s);
-        case kBF16 * 100 + 4: return reduce_launch<TBF16, 4>(r, s);
+        case kF32 * 100 + 1: return tile_launch<TF32, 1>(t, s);
+        case kF32 * 100 + 2: return tile_launch<TF32, 2>(t, s);
+        case kF32 * 100 + 4: return tile_launch<TF32, 4>(t, s);
+        case kBF16 * 100 + 1: return tile_launch<TBF16, 1>(t, s);
+        case kBF16 * 100 + 2: return tile_launch<TBF16, 2>(t, s);
+        case kBF16 * 100 + 4: return tile_launch<TBF16, 4>(t, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_region_tables(const int32_t* shapes, int32_t N, int32_t L, u32* cell_start,
+                                u32* tile_start, u32* tile_region, hipStream_t s) {
+    mark_begin("region_tables", s);
+    hipLaunchKernelGGL(region_tables_kernel, dim3(1), dim3(256), 0, s, shapes, N, L, cell_start,
+                       tile_start, tile_region);
+    mark_end(s);
+    return hipGetLastError();
 }
 
 }  // namespace msda

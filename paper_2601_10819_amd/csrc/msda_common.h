@@ -106,9 +106,10 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 
 // ---------------------------------------------------------------- geometry
 
-// One (camera, level) region: its size, first row, and the FP8 level scale
-// (1 for other storage types).
-struct Geo { int H, W, start; float scale; };
+// One (camera, level) region: its size, first row, first bilinear cell (for
+// the sorted grad_feat records; 0 when unused) and the FP8 level scale (1
+// for other storage types).
+struct Geo { int H, W, start; float scale; u32 cstart, pad0, pad1, pad2; };
 
 __device__ __forceinline__ void stage_geometry(Geo* geo, const OpArgs& a) {
     const int NL = a.N * a.L;
@@ -118,6 +119,8 @@ __device__ __forceinline__ void stage_geometry(Geo* geo, const OpArgs& a) {
         g.W = a.shapes[2 * i + 1];
         g.start = a.starts[i];
         g.scale = a.level_scale ? a.level_scale[i % a.L] : 1.f;
+        g.cstart = a.cell_start ? a.cell_start[i] : 0u;
+        g.pad0 = g.pad1 = g.pad2 = 0u;
         geo[i] = g;
     }
 }
@@ -157,6 +160,7 @@ struct Corners {
     float cw[4];
     float lx, ly;
     int row[4];
+    int x0, y0;     // top-left neighbour (meaningful when valid)
     bool valid;
 };
 
@@ -166,6 +170,8 @@ __device__ __forceinline__ Corners corners_of(float u, float v, const Geo& g, u3
     const Axis ay = axis_of(v, g.H);
     Corners c;
     c.valid = ax.ok && ay.ok;
+    c.x0 = ax.i0;
+    c.y0 = ay.i0;
     c.lx = c.valid ? ax.l : 0.f;
     c.ly = c.valid ? ay.l : 0.f;
     const float hx = 1.f - c.lx, hy = 1.f - c.ly;
@@ -217,6 +223,24 @@ __device__ __forceinline__ void end_chunk() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Inclusive scan across the 256 threads of a block (4 waves); returns the
+// thread's inclusive sum and the block total in *total.
+__device__ __forceinline__ u32 block_inclusive_scan(u32 v, u32* lds4, u32* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const u32 t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    if (lane == 63) lds4[wave] = v;
+    __syncthreads();
+    u32 before = 0;
+    for (int w = 0; w < wave; ++w) before += lds4[w];
+    *total = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+    __syncthreads();
+    return v + before;
 }
 
 // Quotient of n < 2^30 by the divisor whose magic is (m, shift): exact

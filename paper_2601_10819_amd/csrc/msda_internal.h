@@ -20,8 +20,10 @@ struct OpArgs {
     const float* grad_out;        // [B][A][C] (backward)
     float* out;                   // [B][A][C] (forward)
     float* gfeat_acc;             // atomic grad_feat: FP32 [B][R][C] accumulator, or nullptr
-    uint32_t* rec_key;            // sorted grad_feat: [4*S] row keys, or nullptr
-    float* rec_cw;                // sorted grad_feat: [4*S] corner weights
+    uint32_t* rec_key;            // sorted grad_feat: [S] bilinear-cell keys, or nullptr
+    float2* rec_frac;             // sorted grad_feat: [S] (lx, ly) bilinear fractions
+    const uint32_t* cell_start;   // [N*L] first cell of each region (sorted grad_feat)
+    uint32_t cells_per_item;      // cells of one batch item: sum of (H+1)(W+1)
     float* grad_loc;              // or nullptr
     float* grad_w;                // or nullptr
     int32_t B, N, L, A, P, C, G;
@@ -31,18 +33,31 @@ struct OpArgs {
     int32_t pairs_per_chunk;      // (keypoint, camera) pairs staged per wave step
 };
 
-// The per-row grad_feat reduction over sorted records.
-struct ReduceArgs {
-    const uint32_t* vals;         // record indices (4*sample + corner), sorted by row
-    const uint32_t* off;          // [nrows + 1] first record of each row
-    const float* rec_cw;          // [4*S] corner weights
+// The tiled grad_feat reduction over records sorted by bilinear cell.
+// Tiles are kTileH x kTileW pixels of one region; processing slot o covers
+// region tile_region[o], regions ordered coarse levels first.
+constexpr int kTileH = 4, kTileW = 4;
+
+struct TileArgs {
+    const uint32_t* vals;         // sample indices, sorted by cell (stable)
+    const uint32_t* off;          // [B * cells_per_item + 1] first record of each cell
+    const float2* frac;           // [S] (lx, ly)
     const float* w;               // weights, [S][G]
     const float* grad_out;        // [B*A][C]
-    void* grad_feat;              // [nrows][C], FP32 or BF16
-    uint32_t nrows;               // B * R
-    uint32_t nrec;                // records: 4 * B * A * P * N * L
-    int32_t C, G;
+    void* grad_feat;              // [B][R][C], FP32 or BF16
+    const int32_t* shapes;        // [N*L][2]
+    const int32_t* starts;        // [N*L]
+    const uint32_t* cell_start;   // [N*L]
+    const uint32_t* tile_start;   // [N*L + 1], by processing slot
+    const uint32_t* tile_region;  // [N*L], region of each processing slot
+    uint32_t tiles_per_item;
+    uint32_t tile_begin, tile_end;  // this launch's tiles of each batch item (slot order)
+    uint32_t cells_per_item;
+    uint32_t nrec;                // S (records, one per sample)
+    int32_t NL, B, C, G;
+    int64_t R;
     int32_t lps_shift;            // log2(C / chans_per_lane)
+    int32_t waves;                // waves sharing each tile's records (1, 2 or 4)
     uint64_t magic;               // sample -> anchor: s / (P*N*L) == (s * magic) >> magic_shift
     int32_t magic_shift;
 };
@@ -54,7 +69,10 @@ hipError_t launch_forward(const OpArgs& a, int dtype, int cpl, int waves, size_t
                           hipStream_t s);
 hipError_t launch_backward(const OpArgs& a, int dtype, int cpl, int waves, size_t lds_bytes,
                            hipStream_t s);
-hipError_t launch_gfeat_reduce(const ReduceArgs& r, int out_dtype, int cpl, hipStream_t s);
+hipError_t launch_gfeat_tiles(const TileArgs& t, int out_dtype, int cpl, hipStream_t s);
+// cell_start[N*L], tile_start[N*L + 1] and tile_region[N*L] from the shapes.
+hipError_t launch_region_tables(const int32_t* shapes, int32_t N, int32_t L, uint32_t* cell_start,
+                                uint32_t* tile_start, uint32_t* tile_region, hipStream_t s);
 // Stable sort of the n record keys (keys_a, values = indices) by key in
 // [0, nrows]; *sorted_vals receives the sorted indices (in vals_a or vals_b)
 // and off[0..nrows] the segment starts. scratch: sort_scratch_words(n) words.

@@ -41,23 +41,6 @@ radix_hist_kernel(const u32* __restrict__ keys, u32 n, int shift, u32* __restric
     table[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];   // digit-major
 }
 
-// Inclusive scan across the 256 threads of a block; returns the block total.
-__device__ __forceinline__ u32 block_inclusive_scan(u32 v, u32* lds4, u32* total) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const u32 t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
-    if (lane == 63) lds4[wave] = v;
-    __syncthreads();
-    u32 before = 0;
-    for (int w = 0; w < wave; ++w) before += lds4[w];
-    *total = lds4[0] + lds4[1] + lds4[2] + lds4[3];
-    __syncthreads();
-    return v + before;
-}
-
 // Scan, phase 1: per-tile sums.
 __global__ void __launch_bounds__(256) scan_reduce_kernel(const u32* __restrict__ x, u32 n,
                                                           u32* __restrict__ partial) {

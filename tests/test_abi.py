@@ -144,11 +144,13 @@ def test_unsupported_requests(lib):
 def test_backward_validation(lib):
     d = desc(Geo(), dtype=_lib.MSDA_FP8_E4M3, C=64, scale=FAKE)
     expect(lib, bwd(lib, d), UNS, "FP8")
-    # sorted grad_feat (the default): workspace for 4 records per sample
+    # sorted grad_feat (the default): keys, values (twice each), fractions
+    # (8 bytes) per sample and one offset per bilinear cell
     d = desc(Geo(), dtype=_lib.MSDA_BF16, C=64)
     need = lib.msda_backward_workspace_size(ctypes.byref(d))
-    nrec = 4 * 1 * 4 * 3 * 2 * 2
-    assert need >= 5 * 4 * nrec + 4 * (Geo().rows + 1)
+    nsamp = 1 * 4 * 3 * 2 * 2
+    ncells = 2 * ((8 + 1) * (12 + 1) + (4 + 1) * (6 + 1))
+    assert need >= 4 * 4 * nsamp + 8 * nsamp + 4 * (ncells + 1)
     expect(lib, bwd(lib, d), WS, "workspace")
     expect(lib, bwd(lib, d, ws=FAKE + (1 << 20), ws_bytes=need - 4), WS)
     expect(lib, bwd(lib, d, ws=(FAKE + (1 << 20)) + 8, ws_bytes=need + 64), WS, "aligned")
