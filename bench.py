@@ -83,9 +83,12 @@ class HipEvents:
 
 
 def kernel_source_hash():
+    """Hash of the library sources (the counters are void once they change)."""
     h = hashlib.sha256()
-    for f in ("paper_2601_10819_amd/csrc/msda_kernels.hip", "paper_2601_10819_amd/csrc/msda_api.cpp"):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+    csrc = os.path.join(ROOT, "paper_2601_10819_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(f.encode())
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
