@@ -164,6 +164,72 @@ msda_status msda_quantize_fp8(const float* feat_f32, const int32_t* spatial_shap
 size_t msda_quantize_workspace_size(const msda_desc* desc);
 
 /*
+ * Batched form: several scenes of uneven size in one persistent launch per
+ * pass (the scenes of a multi-camera deployment processed together). Each
+ * scene is one batch item with its own cameras, feature geometry and
+ * anchors; levels, keypoints, channels, groups and the feature dtype are
+ * shared. The results are those of msda_forward / msda_backward called on
+ * each scene with B = 1 (bitwise for the forward with the same launch shape,
+ * and for the default sorted grad_feat).
+ */
+typedef struct msda_scene {
+    const void* feat;                 /* [R][C] in the batch's feat dtype               */
+    const int32_t* spatial_shapes;    /* [Ncam][L][2] (H, W)                             */
+    const int32_t* level_start_index; /* [Ncam][L]                                       */
+    const float* sampling_loc;        /* [A][P][Ncam][2]                                 */
+    const float* weights;             /* [A][P][Ncam][L][G]                              */
+    float* out;                       /* [A][C]  forward output                          */
+    const float* grad_out;            /* [A][C]  backward input                          */
+    void* grad_feat;                  /* [R][C]  backward output (feat dtype), or NULL   */
+    float* grad_sampling_loc;         /* backward output, or NULL                        */
+    float* grad_weights;              /* backward output, or NULL                        */
+    int64_t rows;                     /* R                                               */
+    int32_t num_cams;                 /* Ncam >= 1                                       */
+    int32_t num_anchors;              /* A >= 0                                          */
+} msda_scene;
+
+typedef struct msda_batch {
+    int32_t num_scenes;               /* 1 .. 256                                        */
+    int32_t num_levels;               /* L, shared                                       */
+    int32_t num_points;               /* P, shared                                       */
+    int32_t channels;                 /* C, shared                                       */
+    int32_t groups;                   /* G, shared                                       */
+    int32_t feat_dtype;               /* msda_dtype, shared                              */
+    const msda_scene* scenes;         /* device copy of the scene table                  */
+    const msda_scene* host_scenes;    /* host copy of the same table (validation)        */
+    const int32_t* const* host_spatial_shapes;     /* per scene, host mirror            */
+    const int32_t* const* host_level_start_index;  /* per scene, host mirror            */
+    const float* level_scale;         /* device [L], FP8 only                            */
+    uint32_t flags;                   /* MSDA_DETERMINISTIC ...                          */
+    const msda_tile* tile;            /* NULL = built-in choice                          */
+} msda_batch;
+
+/* Workspace bytes of msda_forward_batched (backward == 0) or
+ * msda_backward_batched (backward != 0); 0 on invalid input. */
+size_t msda_batched_workspace_size(const msda_batch* batch, int32_t backward);
+
+/*
+ * Forward of every scene of the batch in one persistent launch (workgroups
+ * stride over all anchors of all scenes). workspace: device, 256-byte
+ * aligned, >= msda_batched_workspace_size(batch, 0). Validation as for
+ * msda_forward, per scene; in addition at most 4096 (camera, level) regions
+ * over all scenes.
+ */
+msda_status msda_forward_batched(const msda_batch* batch, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+
+/*
+ * Backward of every scene: one persistent gather launch for all anchors of
+ * all scenes, one sort of all scenes' grad_feat records, one tiled
+ * reduction over all scenes' pixels (two launches: coarse, fine). A
+ * gradient pointer must be NULL in every scene or in none. Only the sorted
+ * grad_feat form is available here. workspace: >=
+ * msda_batched_workspace_size(batch, 1).
+ */
+msda_status msda_backward_batched(const msda_batch* batch, void* workspace,
+                                  size_t workspace_bytes, void* stream);
+
+/*
  * Streaming copy of `bytes` (multiple of 16) from src to dst, both device and
  * 16-byte aligned: the achievable-bandwidth reference kernel used when
  * reporting the fraction of HBM bandwidth the MSDA kernels reach.

@@ -30,7 +30,8 @@ ABI_VERSION = 1
 # Every symbol include/msda.h declares.
 EXPORTS = (
     "msda_forward", "msda_backward", "msda_backward_workspace_size", "msda_quantize_fp8",
-    "msda_quantize_workspace_size", "msda_stream_copy", "msda_set_kernel_events",
+    "msda_quantize_workspace_size", "msda_batched_workspace_size", "msda_forward_batched",
+    "msda_backward_batched", "msda_stream_copy", "msda_set_kernel_events",
     "msda_recorded_kernels", "msda_recorded_kernel_name", "msda_last_error", "msda_abi_version",
 )
 
@@ -51,6 +52,30 @@ class MsdaDesc(ctypes.Structure):
         ("channels", ctypes.c_int32), ("groups", ctypes.c_int32), ("feat_dtype", ctypes.c_int32),
         ("rows", ctypes.c_int64),
         ("host_spatial_shapes", ctypes.c_void_p), ("host_level_start_index", ctypes.c_void_p),
+        ("level_scale", ctypes.c_void_p), ("flags", ctypes.c_uint32),
+        ("tile", ctypes.POINTER(MsdaTile)),
+    ]
+
+
+class MsdaScene(ctypes.Structure):
+    _fields_ = [
+        ("feat", ctypes.c_void_p), ("spatial_shapes", ctypes.c_void_p),
+        ("level_start_index", ctypes.c_void_p), ("sampling_loc", ctypes.c_void_p),
+        ("weights", ctypes.c_void_p), ("out", ctypes.c_void_p), ("grad_out", ctypes.c_void_p),
+        ("grad_feat", ctypes.c_void_p), ("grad_sampling_loc", ctypes.c_void_p),
+        ("grad_weights", ctypes.c_void_p), ("rows", ctypes.c_int64), ("num_cams", ctypes.c_int32),
+        ("num_anchors", ctypes.c_int32),
+    ]
+
+
+class MsdaBatch(ctypes.Structure):
+    _fields_ = [
+        ("num_scenes", ctypes.c_int32), ("num_levels", ctypes.c_int32),
+        ("num_points", ctypes.c_int32), ("channels", ctypes.c_int32), ("groups", ctypes.c_int32),
+        ("feat_dtype", ctypes.c_int32), ("scenes", ctypes.c_void_p),
+        ("host_scenes", ctypes.POINTER(MsdaScene)),
+        ("host_spatial_shapes", ctypes.POINTER(ctypes.c_void_p)),
+        ("host_level_start_index", ctypes.POINTER(ctypes.c_void_p)),
         ("level_scale", ctypes.c_void_p), ("flags", ctypes.c_uint32),
         ("tile", ctypes.POINTER(MsdaTile)),
     ]
@@ -86,6 +111,13 @@ def load(path: str = LIB_PATH):
     lib.msda_quantize_fp8.restype = ctypes.c_int
     lib.msda_quantize_workspace_size.argtypes = [dp]
     lib.msda_quantize_workspace_size.restype = sz
+    bp = ctypes.POINTER(MsdaBatch)
+    lib.msda_batched_workspace_size.argtypes = [bp, ctypes.c_int32]
+    lib.msda_batched_workspace_size.restype = sz
+    lib.msda_forward_batched.argtypes = [bp, vp, sz, vp]
+    lib.msda_forward_batched.restype = ctypes.c_int
+    lib.msda_backward_batched.argtypes = [bp, vp, sz, vp]
+    lib.msda_backward_batched.restype = ctypes.c_int
     lib.msda_stream_copy.argtypes = [vp, vp, sz, vp]
     lib.msda_stream_copy.restype = ctypes.c_int
     lib.msda_set_kernel_events.argtypes = [vp, ctypes.c_int32]

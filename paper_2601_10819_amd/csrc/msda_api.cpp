@@ -467,6 +467,9 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
         a.rec_frac = reinterpret_cast<float2*>(ws + W.frac);
         a.cell_start = cell_start;
         a.cells_per_item = (uint32_t)cells;
+        a.cell_offset = 0;
+        a.no_cell = (uint32_t)ncells;
+        a.sample_offset = 0;
         // rows outside every region are not visited by a tile
         if (!cover && (e = msda::launch_fill_zero(grad_feat, gf_bytes, s)) != hipSuccess)
             return hip_fail(e, "zero grad_feat");
@@ -553,6 +556,357 @@ msda_status msda_quantize_fp8(const float* feat_f32, const int32_t* spatial_shap
                                   d.num_cams, d.num_levels, d.rows, d.channels, codes,
                                   level_scale, static_cast<uint32_t*>(workspace), s);
     if (e != hipSuccess) return hip_fail(e, "msda_quantize_fp8 launch");
+    return ok();
+}
+
+// ---------------------------------------------------------------- batched form
+
+}  // extern "C"
+
+namespace {
+
+struct BatchWs {
+    size_t anchor_start, sample_start, region_start, cell_start, slot_scene, slot_region,
+        tile_start, magic, magic_shift, keys_a, keys_b, vals_a, vals_b, frac, off, scratch, total;
+};
+
+BatchWs batch_layout(uint64_t S, uint64_t regions, uint64_t nsamp, uint64_t ncells, bool records) {
+    BatchWs w = {};
+    size_t at = 0;
+    auto take = [&](size_t bytes) { const size_t here = at; at += align256(bytes); return here; };
+    w.anchor_start = take((S + 1) * 4);
+    w.sample_start = take((S + 1) * 4);
+    w.region_start = take((S + 1) * 4);
+    w.cell_start = take(regions * 4);
+    w.slot_scene = take(regions * 4);
+    w.slot_region = take(regions * 4);
+    w.tile_start = take((regions + 1) * 4);
+    w.magic = take(S * 8);
+    w.magic_shift = take(S * 4);
+    if (records) {
+        w.keys_a = take(nsamp * 4);
+        w.keys_b = take(nsamp * 4);
+        w.vals_a = take(nsamp * 4);
+        w.vals_b = take(nsamp * 4);
+        w.frac = take(nsamp * 8);
+        w.off = take((ncells + 1) * 4);
+        w.scratch = take(msda::sort_scratch_words((uint32_t)nsamp) * 4);
+    }
+    w.total = at;
+    return w;
+}
+
+// Sizes of a validated batch.
+struct BatchPlan {
+    uint64_t anchors, samples, regions, cells, tiles, heavy_tiles;
+    int max_regions_per_scene, max_cams;
+    int cpl, waves;
+    int64_t max_batch_bytes;
+};
+
+// Validates the batch (every scene against its host mirrors) and sizes it.
+msda_status plan_batch(const msda_batch* b, bool backward, BatchPlan* p) {
+    if (!b) return fail(MSDA_ERR_INVALID_ARGUMENT, "batch is NULL");
+    if (b->num_scenes < 1 || b->num_scenes > msda::kMaxBatchScenes)
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "num_scenes=%d not in [1, %d]", b->num_scenes,
+                    msda::kMaxBatchScenes);
+    if (!b->scenes || !b->host_scenes || !b->host_spatial_shapes || !b->host_level_start_index)
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "scene table or host mirrors are NULL");
+    *p = BatchPlan{};
+    const int eb = elem_bytes(b->feat_dtype);
+    for (int s = 0; s < b->num_scenes; ++s) {
+        const msda_scene& sc = b->host_scenes[s];
+        msda_desc d = {};
+        d.batch = 1;
+        d.num_cams = sc.num_cams;
+        d.num_levels = b->num_levels;
+        d.num_anchors = sc.num_anchors;
+        d.num_points = b->num_points;
+        d.channels = b->channels;
+        d.groups = b->groups;
+        d.feat_dtype = b->feat_dtype;
+        d.rows = sc.rows;
+        d.host_spatial_shapes = b->host_spatial_shapes[s];
+        d.host_level_start_index = b->host_level_start_index[s];
+        d.level_scale = b->level_scale;
+        d.flags = b->flags;
+        d.tile = b->tile;
+        int64_t bb = 0;
+        msda_status st = check_regions(&d, &bb);
+        if (st != MSDA_OK) {
+            const std::string msg = g_error;
+            return fail(st, "scene %d: %s", s, msg.c_str());
+        }
+        if (!sc.feat || !sc.spatial_shapes || !sc.level_start_index)
+            return fail(MSDA_ERR_INVALID_ARGUMENT, "scene %d: a required device pointer is NULL", s);
+        if (sc.num_anchors > 0 && (!sc.sampling_loc || !sc.weights ||
+                                   (backward ? !sc.grad_out : !sc.out)))
+            return fail(MSDA_ERR_INVALID_ARGUMENT, "scene %d: a required device pointer is NULL", s);
+        if (!aligned(sc.feat, 16))
+            return fail(MSDA_ERR_UNSUPPORTED, "scene %d: feat must be 16-byte aligned", s);
+        p->anchors += (uint64_t)sc.num_anchors;
+        p->samples += (uint64_t)sc.num_anchors * b->num_points * sc.num_cams * b->num_levels;
+        p->regions += (uint64_t)sc.num_cams * b->num_levels;
+        p->max_regions_per_scene = std::max(p->max_regions_per_scene, sc.num_cams * b->num_levels);
+        p->max_cams = std::max(p->max_cams, sc.num_cams);
+        p->max_batch_bytes = std::max<int64_t>(p->max_batch_bytes, bb);
+        uint64_t cells = 0, tiles = 0;
+        cells_and_tiles(&d, &cells, &tiles);
+        p->cells += cells;
+        p->tiles += tiles;
+        // heavy (scene, level): camera 0's area at most 1/16 of its largest level
+        int64_t max_area = 0;
+        for (int l = 0; l < b->num_levels; ++l)
+            max_area = std::max<int64_t>(max_area, (int64_t)d.host_spatial_shapes[2 * l] *
+                                                       d.host_spatial_shapes[2 * l + 1]);
+        for (int l = 0; l < b->num_levels; ++l) {
+            if ((int64_t)d.host_spatial_shapes[2 * l] * d.host_spatial_shapes[2 * l + 1] * 16 >
+                max_area)
+                continue;
+            for (int n = 0; n < sc.num_cams; ++n) {
+                const int r = n * b->num_levels + l;
+                const uint64_t H = d.host_spatial_shapes[2 * r], W = d.host_spatial_shapes[2 * r + 1];
+                p->heavy_tiles += ((H + msda::kTileH - 1) / msda::kTileH) *
+                                  ((W + msda::kTileW - 1) / msda::kTileW);
+            }
+        }
+    }
+    (void)eb;
+    if (p->regions > (uint64_t)msda::kMaxBatchRegions)
+        return fail(MSDA_ERR_UNSUPPORTED, "%llu (camera, level) regions in the batch (limit %d)",
+                    (unsigned long long)p->regions, msda::kMaxBatchRegions);
+    if (p->anchors > 0x7fffffffull)
+        return fail(MSDA_ERR_UNSUPPORTED, "too many anchors in the batch");
+    // launch shape, from a single-call descriptor of the largest scene
+    msda_desc d = {};
+    d.batch = 1;
+    d.num_cams = p->max_cams;
+    d.num_levels = b->num_levels;
+    d.num_anchors = (int32_t)std::min<uint64_t>(p->anchors, 0x7fffffff);
+    d.num_points = b->num_points;
+    d.channels = b->channels;
+    d.groups = b->groups;
+    d.feat_dtype = b->feat_dtype;
+    d.rows = 1;
+    d.tile = b->tile;
+    msda::OpArgs a = {};
+    // prepare() needs valid host mirrors: one 1x1 region per camera and level
+    std::vector<int32_t> shp((size_t)p->max_cams * b->num_levels * 2, 1), st((size_t)p->max_cams * b->num_levels);
+    for (size_t i = 0; i < st.size(); ++i) st[i] = (int32_t)i;
+    d.rows = (int64_t)st.size();
+    d.host_spatial_shapes = shp.data();
+    d.host_level_start_index = st.data();
+    d.level_scale = b->level_scale;
+    msda_status stt = prepare(&d, &a, &p->cpl, &p->waves);
+    if (stt != MSDA_OK) return stt;
+    return MSDA_OK;
+}
+
+void fill_batch_args(const msda_batch* b, const BatchPlan& p, char* ws, const BatchWs& w,
+                     msda::BatchArgs* a) {
+    *a = msda::BatchArgs{};
+    a->scenes = b->scenes;
+    a->S = b->num_scenes;
+    a->L = b->num_levels;
+    a->P = b->num_points;
+    a->C = b->channels;
+    a->G = b->groups;
+    a->level_scale = b->feat_dtype == MSDA_FP8_E4M3 ? b->level_scale : nullptr;
+    a->t.anchor_start = reinterpret_cast<uint32_t*>(ws + w.anchor_start);
+    a->t.sample_start = reinterpret_cast<uint32_t*>(ws + w.sample_start);
+    a->t.region_start = reinterpret_cast<uint32_t*>(ws + w.region_start);
+    a->t.cell_start = reinterpret_cast<uint32_t*>(ws + w.cell_start);
+    a->t.slot_scene = reinterpret_cast<uint32_t*>(ws + w.slot_scene);
+    a->t.slot_region = reinterpret_cast<uint32_t*>(ws + w.slot_region);
+    a->t.tile_start = reinterpret_cast<uint32_t*>(ws + w.tile_start);
+    a->t.magic = reinterpret_cast<uint64_t*>(ws + w.magic);
+    a->t.magic_shift = reinterpret_cast<uint32_t*>(ws + w.magic_shift);
+    a->total_anchors = (uint32_t)p.anchors;
+    a->total_samples = (uint32_t)p.samples;
+    a->total_cells = (uint32_t)p.cells;
+    a->total_regions = (uint32_t)p.regions;
+    a->lps_shift = log2i(b->channels / p.cpl);
+    a->pairs_per_chunk = msda::max_pairs_per_chunk(b->num_levels, b->groups);
+    a->max_regions_per_scene = p.max_regions_per_scene;
+}
+
+size_t batch_lds(const msda_batch* b, const BatchPlan& p) {
+    msda::OpArgs o = {};
+    o.N = p.max_cams;
+    o.L = b->num_levels;
+    o.G = b->groups;
+    o.C = b->channels;
+    o.pairs_per_chunk = msda::max_pairs_per_chunk(b->num_levels, b->groups);
+    return msda::lds_bytes_for(o, p.waves);
+}
+
+int persistent_blocks(uint64_t items, int waves) {
+    const uint64_t cap = 256ull * (uint64_t)(16 / waves);     // 256 CUs, ~16 waves each
+    return (int)std::max<uint64_t>(1, std::min(items, cap));
+}
+
+// Which gradients the batch asks for; they must agree over the scenes.
+// grad_sampling_loc and grad_weights of a scene without anchors hold no
+// elements and may be NULL either way.
+msda_status batch_grads(const msda_batch* b, bool* gf, bool* gl, bool* gw) {
+    const msda_scene& s0 = b->host_scenes[0];
+    *gf = s0.grad_feat != nullptr;
+    int ref = -1;                                   // first scene with anchors
+    for (int s = 0; s < b->num_scenes && ref < 0; ++s)
+        if (b->host_scenes[s].num_anchors > 0) ref = s;
+    *gl = ref >= 0 && b->host_scenes[ref].grad_sampling_loc != nullptr;
+    *gw = ref >= 0 && b->host_scenes[ref].grad_weights != nullptr;
+    for (int s = 0; s < b->num_scenes; ++s) {
+        const msda_scene& sc = b->host_scenes[s];
+        const bool empty = sc.num_anchors == 0;
+        if ((sc.grad_feat != nullptr) != *gf ||
+            (!empty && ((sc.grad_sampling_loc != nullptr) != *gl ||
+                        (sc.grad_weights != nullptr) != *gw)))
+            return fail(MSDA_ERR_INVALID_ARGUMENT,
+                        "scene %d requests other gradients than scene %d (NULL in all or none)", s,
+                        ref < 0 ? 0 : ref);
+    }
+    return MSDA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t msda_batched_workspace_size(const msda_batch* b, int32_t backward) {
+    BatchPlan p;
+    if (plan_batch(b, backward != 0, &p) != MSDA_OK) return 0;
+    bool gf = false, gl = false, gw = false;
+    if (backward && batch_grads(b, &gf, &gl, &gw) != MSDA_OK) return 0;
+    return batch_layout(b->num_scenes, p.regions, p.samples, p.cells, backward && gf).total;
+}
+
+msda_status msda_forward_batched(const msda_batch* b, void* workspace, size_t workspace_bytes,
+                                 void* stream) {
+    BatchPlan p;
+    msda_status st = plan_batch(b, false, &p);
+    if (st != MSDA_OK) return st;
+    const BatchWs w = batch_layout(b->num_scenes, p.regions, p.samples, p.cells, false);
+    if (!workspace || workspace_bytes < w.total)
+        return fail(MSDA_ERR_WORKSPACE, "workspace of %zu bytes needed", w.total);
+    if (!aligned(workspace, 256)) return fail(MSDA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    const size_t lds = batch_lds(b, p);
+    if (lds > 65536) return fail(MSDA_ERR_UNSUPPORTED, "batched launch needs %zu bytes of LDS", lds);
+    msda::BatchArgs a;
+    fill_batch_args(b, p, static_cast<char*>(workspace), w, &a);
+    const hipStream_t s = (hipStream_t)stream;
+    hipError_t e = msda::launch_batch_tables(a, false, s);
+    if (e != hipSuccess) return hip_fail(e, "batch tables");
+    if (p.anchors == 0) return ok();
+    e = msda::launch_forward_batched(a, b->feat_dtype, p.cpl, p.waves,
+                                     persistent_blocks(p.anchors, p.waves), lds, s);
+    if (e != hipSuccess) return hip_fail(e, "msda_forward_batched launch");
+    return ok();
+}
+
+msda_status msda_backward_batched(const msda_batch* b, void* workspace, size_t workspace_bytes,
+                                  void* stream) {
+    BatchPlan p;
+    msda_status st = plan_batch(b, true, &p);
+    if (st != MSDA_OK) return st;
+    if (b->feat_dtype == MSDA_FP8_E4M3)
+        return fail(MSDA_ERR_UNSUPPORTED, "the backward takes FP32 or BF16 features (not FP8)");
+    if (b->tile && b->tile->scatter == MSDA_SCATTER_ATOMIC)
+        return fail(MSDA_ERR_UNSUPPORTED, "the batched backward has only the sorted grad_feat form");
+    bool gf, gl, gw;
+    if ((st = batch_grads(b, &gf, &gl, &gw)) != MSDA_OK) return st;
+    int rcpl = 0;
+    for (int c : {4, 2, 1})
+        if (cpl_fits(c, b->channels, b->groups)) { rcpl = c; break; }
+    if (gf) {
+        if (p.samples >= (1ull << 30))
+            return fail(MSDA_ERR_UNSUPPORTED, "%llu samples in the batch exceeds 2^30",
+                        (unsigned long long)p.samples);
+        if (p.cells >= 0x7fffffffull)
+            return fail(MSDA_ERR_UNSUPPORTED, "too many bilinear cells in the batch");
+        if (!rcpl) return fail(MSDA_ERR_UNSUPPORTED, "no reduction lane layout for C=%d G=%d",
+                               b->channels, b->groups);
+        if (b->groups > 64) return fail(MSDA_ERR_UNSUPPORTED, "sorted grad_feat supports G <= 64");
+    }
+    for (int s = 0; s < b->num_scenes; ++s) {
+        const msda_scene& sc = b->host_scenes[s];
+        if (gf && !aligned(sc.grad_feat, 16))
+            return fail(MSDA_ERR_UNSUPPORTED, "scene %d: grad_feat must be 16-byte aligned", s);
+        if (gf && rcpl == 4 && sc.grad_out && !aligned(sc.grad_out, 16))
+            return fail(MSDA_ERR_UNSUPPORTED, "scene %d: grad_out must be 16-byte aligned", s);
+        if (gf) {
+            msda_desc d = {};
+            d.num_cams = sc.num_cams;
+            d.num_levels = b->num_levels;
+            d.rows = sc.rows;
+            d.host_spatial_shapes = b->host_spatial_shapes[s];
+            d.host_level_start_index = b->host_level_start_index[s];
+            bool cover = true;
+            if (!regions_disjoint(&d, &cover))
+                return fail(MSDA_ERR_UNSUPPORTED, "scene %d: grad_feat needs disjoint regions", s);
+        }
+    }
+    const BatchWs w = batch_layout(b->num_scenes, p.regions, p.samples, p.cells, gf);
+    if (!workspace || workspace_bytes < w.total)
+        return fail(MSDA_ERR_WORKSPACE, "workspace of %zu bytes needed", w.total);
+    if (!aligned(workspace, 256)) return fail(MSDA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    const size_t lds = batch_lds(b, p);
+    if (lds > 65536) return fail(MSDA_ERR_UNSUPPORTED, "batched launch needs %zu bytes of LDS", lds);
+
+    char* ws = static_cast<char*>(workspace);
+    msda::BatchArgs a;
+    fill_batch_args(b, p, ws, w, &a);
+    const hipStream_t s = (hipStream_t)stream;
+    hipError_t e = msda::launch_batch_tables(a, true, s);
+    if (e != hipSuccess) return hip_fail(e, "batch tables");
+    if (gf) {
+        a.rec_key = reinterpret_cast<uint32_t*>(ws + w.keys_a);
+        a.rec_frac = reinterpret_cast<float2*>(ws + w.frac);
+        // rows outside every region are not visited by a tile
+        for (int sc = 0; sc < b->num_scenes; ++sc) {
+            msda_desc d = {};
+            d.num_cams = b->host_scenes[sc].num_cams;
+            d.num_levels = b->num_levels;
+            d.rows = b->host_scenes[sc].rows;
+            d.host_spatial_shapes = b->host_spatial_shapes[sc];
+            d.host_level_start_index = b->host_level_start_index[sc];
+            bool cover = true;
+            regions_disjoint(&d, &cover);
+            if (!cover) {
+                const size_t bytes = (size_t)d.rows * b->channels * (b->feat_dtype == MSDA_F32 ? 4 : 2);
+                if ((e = msda::launch_fill_zero(b->host_scenes[sc].grad_feat, bytes, s)) != hipSuccess)
+                    return hip_fail(e, "zero grad_feat");
+            }
+        }
+    }
+    if (p.anchors > 0 && (gf || gl || gw) &&
+        (e = msda::launch_backward_batched(a, b->feat_dtype, p.cpl, p.waves,
+                                           persistent_blocks(p.anchors, p.waves), lds, s)) !=
+            hipSuccess)
+        return hip_fail(e, "msda_backward_batched launch");
+    if (!gf) return ok();
+    uint32_t* sorted = nullptr;
+    uint32_t* off = reinterpret_cast<uint32_t*>(ws + w.off);
+    e = msda::launch_sort_records(reinterpret_cast<uint32_t*>(ws + w.keys_a),
+                                  reinterpret_cast<uint32_t*>(ws + w.keys_b),
+                                  reinterpret_cast<uint32_t*>(ws + w.vals_a),
+                                  reinterpret_cast<uint32_t*>(ws + w.vals_b), (uint32_t)p.samples,
+                                  (uint32_t)p.cells, reinterpret_cast<uint32_t*>(ws + w.scratch),
+                                  off, &sorted, s);
+    if (e != hipSuccess) return hip_fail(e, "sort grad_feat records");
+    a.vals = sorted ? sorted : reinterpret_cast<uint32_t*>(ws + w.vals_a);
+    a.off = off;
+    a.total_samples = (uint32_t)std::max<uint64_t>(p.samples, 1);
+    a.lps_shift = log2i(b->channels / rcpl);
+    const uint32_t split[3] = {0u, (uint32_t)p.heavy_tiles, (uint32_t)p.tiles};
+    for (int part = 0; part < 2; ++part) {
+        a.tile_begin = split[part];
+        a.tile_end = split[part + 1];
+        a.waves = part == 0 ? 4 : 1;
+        if (a.tile_end > a.tile_begin &&
+            (e = msda::launch_gfeat_tiles_batched(a, b->feat_dtype, rcpl, s)) != hipSuccess)
+            return hip_fail(e, "batched grad_feat tile reduction");
+    }
     return ok();
 }
 

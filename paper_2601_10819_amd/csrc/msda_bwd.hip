@@ -33,22 +33,18 @@
 
 namespace msda {
 
+// The backward gather of one anchor (index ba = b*A + a of `a`) by the
+// whole workgroup; the geometry of `a` is already staged in geo.
 template <class FT, int CPL>
-__global__ void __launch_bounds__(512) msda_bwd_kernel(OpArgs a) {
+__device__ __forceinline__ void bwd_anchor(const OpArgs& a, const int ba, const Geo* geo,
+                                           float* work) {
     using RowT = Row<FT, CPL>;
-    extern __shared__ __align__(16) unsigned char smem[];
-    Geo* geo = reinterpret_cast<Geo*>(smem);
-    float* work = reinterpret_cast<float*>(smem + (size_t)a.N * a.L * sizeof(Geo));
-    stage_geometry(geo, a);
-    __syncthreads();
-
     const int LG = a.L * a.G;
     const int J = a.pairs_per_chunk;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     float* sw = work + wave * J * (LG + 2);
     float* sl = sw + J * LG;
 
-    const int ba = blockIdx.x;
     const int b = ba / a.A;
     const int npairs = a.P * a.N;
     const float* gl = a.loc + (size_t)ba * npairs * 2;
@@ -74,8 +70,8 @@ __global__ void __launch_bounds__(512) msda_bwd_kernel(OpArgs a) {
     float* gwout = a.grad_w ? a.grad_w + (size_t)ba * npairs * LG : nullptr;
     float* glout = a.grad_loc ? a.grad_loc + (size_t)ba * npairs * 2 : nullptr;
     const bool need_vals = gwout || glout;
-    const u32 cell_base = (u32)b * a.cells_per_item;  // first cell of this batch item
-    const u32 no_cell = (u32)a.B * a.cells_per_item;  // key of a sample outside its level
+    const u32 cell_base = a.cell_offset + (u32)b * a.cells_per_item;  // this item's first cell
+    const u32 no_cell = a.no_cell;                 // key of a sample outside its level
 
     const int nchunks = (npairs + J - 1) / J;
     for (int k = wave; k < nchunks; k += nwaves) {
@@ -94,7 +90,7 @@ __global__ void __launch_bounds__(512) msda_bwd_kernel(OpArgs a) {
                 const float wl = wj[l * a.G];
                 if (a.rec_key && sl_lane == 0) {
                     // the sample's record: its bilinear cell and fractions
-                    const u32 sidx = (u32)(ba * npairs + j) * (u32)a.L + (u32)l;
+                    const u32 sidx = a.sample_offset + (u32)(ba * npairs + j) * (u32)a.L + (u32)l;
                     a.rec_key[sidx] = cr.valid ? cell_base + gm.cstart +
                                                      (u32)(cr.y0 + 1) * (u32)(gm.W + 1) +
                                                      (u32)(cr.x0 + 1)
@@ -150,6 +146,34 @@ __global__ void __launch_bounds__(512) msda_bwd_kernel(OpArgs a) {
             }
         }
         end_chunk();
+    }
+    (void)work;
+}
+
+template <class FT, int CPL>
+__global__ void __launch_bounds__(512) msda_bwd_kernel(OpArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    Geo* geo = reinterpret_cast<Geo*>(smem);
+    float* work = reinterpret_cast<float*>(smem + (size_t)a.N * a.L * sizeof(Geo));
+    stage_geometry(geo, a);
+    __syncthreads();
+    bwd_anchor<FT, CPL>(a, (int)blockIdx.x, geo, work);
+}
+
+// Batched backward gather: persistent workgroups stride over the anchors of
+// all scenes; records go to the global (all-scene) cell and sample spaces.
+template <class FT, int CPL>
+__global__ void __launch_bounds__(512) msda_bwd_batched_kernel(BatchArgs b) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    Geo* geo = reinterpret_cast<Geo*>(smem);
+    float* work = reinterpret_cast<float*>(smem + (size_t)b.max_regions_per_scene * sizeof(Geo));
+    for (u32 item = blockIdx.x; item < b.total_anchors; item += gridDim.x) {
+        const int s = scene_of(b.t.anchor_start, b.S, item);
+        const OpArgs a = scene_view(b, s, FT::kBytes);
+        __syncthreads();                    // the previous anchor is done with geo
+        stage_geometry(geo, a);
+        __syncthreads();
+        bwd_anchor<FT, CPL>(a, (int)(item - b.t.anchor_start[s]), geo, work);
     }
 }
 
@@ -293,53 +317,51 @@ __device__ __forceinline__ void add_sample_at(int pos, float (&acc)[4][4][CPL], 
 constexpr int kBndPerGroup = (kTileH + 1) * (kTileW + 2);
 
 // LDS bytes of the boundary slots: one per lane group of every wave.
-__host__ __device__ inline size_t bnd_lds_bytes(const TileArgs& t) {
-    const size_t groups = (size_t)t.waves * (size_t)(64 >> t.lps_shift);
+__host__ __device__ inline size_t bnd_lds_bytes(int waves, int lps_shift) {
+    const size_t groups = (size_t)waves * (size_t)(64 >> lps_shift);
     return (groups * kBndPerGroup * 4 + 15) & ~(size_t)15;
 }
 
 // Records handled per group of grad_out loads in flight.
 constexpr int kGoBatch = 8;
 
+// Everything one tile's reduction needs (from the single-call or the
+// batched tables).
+struct TileView {
+    const u32* vals;            // sorted record indices (global sample indices)
+    const u32* off;             // first record of each cell
+    const float2* frac;         // per record (global index): (lx, ly)
+    const float* w;             // the scene's weights [S][G]
+    const float* grad_out;      // the scene's grad_out [A][C]
+    void* grad_feat;            // the scene's grad_feat
+    size_t row_base;            // first grad_feat row of the tile's batch item
+    u32 nrec;                   // records in the sort (all scenes)
+    u32 sample_offset;          // first record index of the scene
+    u32 sample_count;           // records of the scene
+    u32 cbase;                  // first cell of the tile's region
+    int H, W, start;            // the region
+    int ty, tx;                 // the tile's first pixel
+    int C, G;
+    u64 magic;                  // scene-local sample -> anchor
+    int magic_shift;
+    bool active;
+};
+
+// The reduction of one tile by a group of lps lanes (grp-th group of its
+// wave, lane sl within it); `waves` waves of the block share its records.
 template <class OT, int CPL, bool WHOLE_WAVE>
-__global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
-    static_assert(kTileH == 4 && kTileW == 4, "the cell dispatch is written for 4x4 tiles");
-    // LDS: per lane group its tile's cell boundaries; per wave a record table
-    // (64 entries of G weights, lx, ly, anchor, cell position); after the
-    // records, the waves' partial sums reuse the record tables' space.
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, const int spw,
+                                            const int grp, const int sl, const int waves,
+                                            u32* bnd_lds, float* work) {
     constexpr int TH = kTileH, TW = kTileW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int lps = WHOLE_WAVE ? 64 : 1 << t.lps_shift;
-    const int spw = WHOLE_WAVE ? 1 : 64 >> t.lps_shift;
-    const int grp = WHOLE_WAVE ? 0 : lane >> t.lps_shift;
-    const int sl = WHOLE_WAVE ? lane : lane & (lps - 1);   // lane within its tile's group
-    const int stride = t.G + 4;                     // floats per record-table entry
-    u32* bnd_lds = reinterpret_cast<u32*>(smem_raw);
-    float* work = reinterpret_cast<float*>(smem_raw + bnd_lds_bytes(t));
+    const int stride = v.G + 4;                     // floats per record-table entry
     float* tab = work + (size_t)wave * 64 * stride + (size_t)(lane - sl) * stride;
-
-    // tiles of one block: spw consecutive ids, one per lane group; ids run
-    // over processing slots (within [tile_begin, tile_end)) first, batch
-    // items second
-    const u32 span = t.tile_end - t.tile_begin;
-    const u32 gt = blockIdx.x * (u32)spw + (u32)grp;
-    const bool active = gt < span * (u32)t.B;
-    const u32 tt = t.tile_begin + (active ? gt / (u32)t.B : 0u);
-    const int b = active ? (int)(gt % (u32)t.B) : 0;
-    int lo = 0, hi = t.NL - 1;                      // last slot with tile_start <= tt
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (t.tile_start[mid] <= tt) lo = mid; else hi = mid - 1;
-    }
-    const int r = (int)t.tile_region[lo];
-    const int H = t.shapes[2 * r], W = t.shapes[2 * r + 1];
-    const u32 lt = tt - t.tile_start[lo];
-    const u32 tpr = (u32)(W + TW - 1) / TW;
-    const int ty = (int)(lt / tpr) * TH, tx = (int)(lt % tpr) * TW;
+    const bool active = v.active;
+    const int H = v.H, W = v.W, ty = v.ty, tx = v.tx;
+    const u32 cbase = v.cbase;
     const int c0 = sl * CPL;
-    const int g = c0 / (t.C / t.G);
-    const u32 cbase = (u32)b * t.cells_per_item + t.cell_start[r];
+    const int g = c0 / (v.C / v.G);
 
     // The tile's cells are TH+1 rows of TW+1 consecutive cells; each row's
     // records are one contiguous range of the sorted order. The group stores
@@ -348,13 +370,13 @@ __global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
     u32* bslot = bnd_lds + ((size_t)wave * spw + (size_t)grp) * NB;
     for (int k = sl; k < NB; k += lps) {
         const int dy = k / (TW + 2), dx = k % (TW + 2);
-        u32 v = 0u;
+        u32 bv = 0u;
         if (active && ty + dy <= H) {
             // cells past W+1 clamp to the row's end
             const u32 cell = cbase + (u32)(ty + dy) * (u32)(W + 1) + (u32)min(tx + dx, W + 1);
-            v = min(t.off[cell], t.nrec);
+            bv = min(v.off[cell], v.nrec);
         }
-        bslot[k] = v;
+        bslot[k] = bv;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -381,7 +403,7 @@ __global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
     // The tile's records as one flat list, in chunks of lps; chunk k goes to
     // wave k % waves. Each lane of the group fills one table entry (all the
     // chunk's loads in flight together), then the group walks the chunk.
-    for (u32 base = (u32)(wave * lps); base < total; base += (u32)(t.waves * lps)) {
+    for (u32 base = (u32)(wave * lps); base < total; base += (u32)(waves * lps)) {
         const int n = (int)min((u32)lps, total - base);
         if (sl < n) {
             // flat index -> (row dy, sorted position e) -> cell position dx
@@ -398,15 +420,18 @@ __global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
 #pragma unroll
             for (int k = 1; k <= TW; ++k)
                 if (e >= bslot[dy * (TW + 2) + k]) dx = k;
-            const u32 s = min(t.vals[e], t.nrec - 1u);
-            const float2 fr = t.frac[s];
+            const u32 s = min(v.vals[e], v.nrec - 1u);
+            const float2 fr = v.frac[s];
             float* ent = tab + sl * stride;
-            const float* ws = t.w + (size_t)s * t.G;
-            for (int k = 0; k < t.G; ++k) ent[k] = ws[k];
-            ent[t.G] = fr.x;
-            ent[t.G + 1] = fr.y;
-            ent[t.G + 2] = __uint_as_float(fast_div(s, t.magic, t.magic_shift));
-            ent[t.G + 3] = __int_as_float(dy * (TW + 1) + dx);
+            // the scene-local sample (clamped into the scene: an inconsistent
+            // sort could only give wrong sums, never a read outside it)
+            const u32 ls = s - v.sample_offset < v.sample_count ? s - v.sample_offset : 0u;
+            const float* ws = v.w + (size_t)ls * v.G;
+            for (int k = 0; k < v.G; ++k) ent[k] = ws[k];
+            ent[v.G] = fr.x;
+            ent[v.G + 1] = fr.y;
+            ent[v.G + 2] = __uint_as_float(fast_div(ls, v.magic, v.magic_shift));
+            ent[v.G + 3] = __int_as_float(dy * (TW + 1) + dx);
         }
         // LDS accesses of one wave are performed in order; keep the compiler
         // from hoisting the reads above the writes
@@ -419,20 +444,20 @@ __global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
 #pragma unroll
             for (int k = 0; k < kGoBatch; ++k) {
                 const float* ent = tab + (q + k) * stride;
-                load_go<CPL>(t.grad_out + (size_t)__float_as_uint(ent[t.G + 2]) * t.C + c0, gv[k]);
+                load_go<CPL>(v.grad_out + (size_t)__float_as_uint(ent[v.G + 2]) * v.C + c0, gv[k]);
             }
 #pragma unroll
             for (int k = 0; k < kGoBatch; ++k) {
                 const float* ent = tab + (q + k) * stride;
-                add_sample_at<CPL>(__float_as_int(ent[t.G + 3]), acc, ent[t.G], ent[t.G + 1],
+                add_sample_at<CPL>(__float_as_int(ent[v.G + 3]), acc, ent[v.G], ent[v.G + 1],
                                    ent[g], gv[k]);
             }
         }
         for (; q < n; ++q) {
             const float* ent = tab + q * stride;
             float gv[CPL];
-            load_go<CPL>(t.grad_out + (size_t)__float_as_uint(ent[t.G + 2]) * t.C + c0, gv);
-            add_sample_at<CPL>(__float_as_int(ent[t.G + 3]), acc, ent[t.G], ent[t.G + 1], ent[g],
+            load_go<CPL>(v.grad_out + (size_t)__float_as_uint(ent[v.G + 2]) * v.C + c0, gv);
+            add_sample_at<CPL>(__float_as_int(ent[v.G + 3]), acc, ent[v.G], ent[v.G + 1], ent[g],
                                gv);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -442,11 +467,11 @@ __global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
 
     // partial sums of the waves, added pairwise in a fixed tree order:
     // wave w += wave w + h for h = waves/2, waves/4, ..., 1
-    if (t.waves > 1) {
+    if (waves > 1) {
         constexpr int E = TH * TW * CPL;
         float* part = work;
         __syncthreads();                             // record tables are dead from here on
-        for (int h = t.waves >> 1; h >= 1; h >>= 1) {
+        for (int h = waves >> 1; h >= 1; h >>= 1) {
             if (wave >= h && wave < 2 * h) {
 #pragma unroll
                 for (int py = 0; py < TH; ++py)
@@ -471,18 +496,120 @@ __global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
         }
     }
     if (wave != 0 || !active) return;
-    const int start = t.starts[r];
+    const int start = v.start;
 #pragma unroll
     for (int py = 0; py < TH; ++py) {
 #pragma unroll
         for (int px = 0; px < TW; ++px) {
             const int y = ty + py, x = tx + px;
             if (y < H && x < W) {
-                const size_t row = (size_t)b * (size_t)t.R + (size_t)(start + y * W + x);
-                store_row<OT, CPL>(t.grad_feat, row * (size_t)t.C + (size_t)c0, acc[py][px]);
+                const size_t row = v.row_base + (size_t)(start + y * W + x);
+                store_row<OT, CPL>(v.grad_feat, row * (size_t)v.C + (size_t)c0, acc[py][px]);
             }
         }
     }
+}
+
+template <class OT, int CPL, bool WHOLE_WAVE>
+__global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
+    static_assert(kTileH == 4 && kTileW == 4, "the cell dispatch is written for 4x4 tiles");
+    // LDS: per lane group its tile's cell boundaries; per wave a record table
+    // (64 entries of G weights, lx, ly, anchor, cell position); after the
+    // records, the waves' partial sums reuse the record tables' space.
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int TH = kTileH, TW = kTileW;
+    const int lane = threadIdx.x & 63;
+    const int lps = WHOLE_WAVE ? 64 : 1 << t.lps_shift;
+    const int spw = WHOLE_WAVE ? 1 : 64 >> t.lps_shift;
+    const int grp = WHOLE_WAVE ? 0 : lane >> t.lps_shift;
+    const int sl = WHOLE_WAVE ? lane : lane & (lps - 1);   // lane within its tile's group
+    u32* bnd_lds = reinterpret_cast<u32*>(smem_raw);
+    float* work = reinterpret_cast<float*>(smem_raw + bnd_lds_bytes(t.waves, t.lps_shift));
+
+    // tiles of one block: spw consecutive ids, one per lane group; ids run
+    // over processing slots (within [tile_begin, tile_end)) first, batch
+    // items second
+    const u32 span = t.tile_end - t.tile_begin;
+    const u32 gt = blockIdx.x * (u32)spw + (u32)grp;
+    TileView v;
+    v.active = gt < span * (u32)t.B;
+    const u32 tt = t.tile_begin + (v.active ? gt / (u32)t.B : 0u);
+    const int b = v.active ? (int)(gt % (u32)t.B) : 0;
+    int lo = 0, hi = t.NL - 1;                      // last slot with tile_start <= tt
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t.tile_start[mid] <= tt) lo = mid; else hi = mid - 1;
+    }
+    const int r = (int)t.tile_region[lo];
+    v.H = t.shapes[2 * r];
+    v.W = t.shapes[2 * r + 1];
+    v.start = t.starts[r];
+    const u32 lt = tt - t.tile_start[lo];
+    const u32 tpr = (u32)(v.W + TW - 1) / TW;
+    v.ty = (int)(lt / tpr) * TH;
+    v.tx = (int)(lt % tpr) * TW;
+    v.cbase = (u32)b * t.cells_per_item + t.cell_start[r];
+    v.row_base = (size_t)b * (size_t)t.R;
+    v.vals = t.vals;
+    v.off = t.off;
+    v.frac = t.frac;
+    v.w = t.w;
+    v.grad_out = t.grad_out;
+    v.grad_feat = t.grad_feat;
+    v.nrec = t.nrec;
+    v.sample_offset = 0;
+    v.sample_count = t.nrec;
+    v.C = t.C;
+    v.G = t.G;
+    v.magic = t.magic;
+    v.magic_shift = t.magic_shift;
+    tile_reduce<OT, CPL, WHOLE_WAVE>(v, lps, spw, grp, sl, t.waves, bnd_lds, work);
+}
+
+// Batched tiled reduction: tiles of all scenes' regions in slot order.
+template <class OT, int CPL, bool WHOLE_WAVE>
+__global__ void __launch_bounds__(256) gfeat_tile_batched_kernel(BatchArgs b) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int TH = kTileH, TW = kTileW;
+    const int lane = threadIdx.x & 63;
+    const int lps = WHOLE_WAVE ? 64 : 1 << b.lps_shift;
+    const int spw = WHOLE_WAVE ? 1 : 64 >> b.lps_shift;
+    const int grp = WHOLE_WAVE ? 0 : lane >> b.lps_shift;
+    const int sl = WHOLE_WAVE ? lane : lane & (lps - 1);
+    u32* bnd_lds = reinterpret_cast<u32*>(smem_raw);
+    float* work = reinterpret_cast<float*>(smem_raw + bnd_lds_bytes(b.waves, b.lps_shift));
+
+    const u32 gt = blockIdx.x * (u32)spw + (u32)grp;
+    TileView v;
+    v.active = gt < b.tile_end - b.tile_begin;
+    const u32 tt = b.tile_begin + (v.active ? gt : 0u);
+    const int slot = scene_of(b.t.tile_start, (int)b.total_regions, tt);
+    const int s = (int)b.t.slot_scene[slot];
+    const int r = (int)b.t.slot_region[slot];
+    const msda_scene& sc = b.scenes[s];
+    v.H = sc.spatial_shapes[2 * r];
+    v.W = sc.spatial_shapes[2 * r + 1];
+    v.start = sc.level_start_index[r];
+    const u32 lt = tt - b.t.tile_start[slot];
+    const u32 tpr = (u32)(v.W + TW - 1) / TW;
+    v.ty = (int)(lt / tpr) * TH;
+    v.tx = (int)(lt % tpr) * TW;
+    v.cbase = b.t.cell_start[b.t.region_start[s] + (u32)r];
+    v.row_base = 0;
+    v.vals = b.vals;
+    v.off = b.off;
+    v.frac = b.rec_frac;
+    v.w = sc.weights;
+    v.grad_out = sc.grad_out;
+    v.grad_feat = sc.grad_feat;
+    v.nrec = b.total_samples;
+    v.sample_offset = b.t.sample_start[s];
+    v.sample_count = b.t.sample_start[s + 1] - b.t.sample_start[s];
+    v.C = b.C;
+    v.G = b.G;
+    v.magic = b.t.magic[s];
+    v.magic_shift = (int)b.t.magic_shift[s];
+    tile_reduce<OT, CPL, WHOLE_WAVE>(v, lps, spw, grp, sl, b.waves, bnd_lds, work);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -517,7 +644,7 @@ static hipError_t tile_launch(const TileArgs& t, hipStream_t s) {
     if (blocks == 0) return hipSuccess;
     const size_t part = t.waves > 1 ? (size_t)(t.waves / 2) * kTileH * kTileW * CPL * 64 * 4 : 0;
     const size_t tables = (size_t)t.waves * 64 * (t.G + 4) * sizeof(float);
-    const size_t lds = bnd_lds_bytes(t) + (part > tables ? part : tables);
+    const size_t lds = bnd_lds_bytes(t.waves, t.lps_shift) + (part > tables ? part : tables);
     mark_begin(t.waves > 1 ? "gfeat_tile_kernel_coarse" : "gfeat_tile_kernel", s);
     if (t.lps_shift == 6)
         hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL, true>), dim3(blocks), dim3(64 * t.waves),
@@ -527,6 +654,61 @@ static hipError_t tile_launch(const TileArgs& t, hipStream_t s) {
                            lds, s, t);
     mark_end(s);
     return hipGetLastError();
+}
+
+template <class FT, int CPL>
+static hipError_t bwd_batched_launch(const BatchArgs& b, int waves, int blocks, size_t lds,
+                                     hipStream_t s) {
+    mark_begin("msda_bwd_batched_kernel", s);
+    hipLaunchKernelGGL((msda_bwd_batched_kernel<FT, CPL>), dim3(blocks), dim3(64 * waves), lds, s,
+                       b);
+    mark_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward_batched(const BatchArgs& b, int dtype, int cpl, int waves, int blocks,
+                                   size_t lds, hipStream_t s) {
+    switch (dtype * 100 + cpl) {
+        case kF32 * 100 + 1: return bwd_batched_launch<TF32, 1>(b, waves, blocks, lds, s);
+        case kF32 * 100 + 2: return bwd_batched_launch<TF32, 2>(b, waves, blocks, lds, s);
+        case kF32 * 100 + 4: return bwd_batched_launch<TF32, 4>(b, waves, blocks, lds, s);
+        case kBF16 * 100 + 2: return bwd_batched_launch<TBF16, 2>(b, waves, blocks, lds, s);
+        case kBF16 * 100 + 4: return bwd_batched_launch<TBF16, 4>(b, waves, blocks, lds, s);
+        case kBF16 * 100 + 8: return bwd_batched_launch<TBF16, 8>(b, waves, blocks, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class OT, int CPL>
+static hipError_t tile_batched_launch(const BatchArgs& b, hipStream_t s) {
+    const u32 spw = 64u >> b.lps_shift;
+    const u32 ntiles = b.tile_end - b.tile_begin;
+    const u32 blocks = (ntiles + spw - 1) / spw;
+    if (blocks == 0) return hipSuccess;
+    const size_t part = b.waves > 1 ? (size_t)(b.waves / 2) * kTileH * kTileW * CPL * 64 * 4 : 0;
+    const size_t tables = (size_t)b.waves * 64 * (b.G + 4) * sizeof(float);
+    const size_t lds = bnd_lds_bytes(b.waves, b.lps_shift) + (part > tables ? part : tables);
+    mark_begin(b.waves > 1 ? "gfeat_tile_batched_coarse" : "gfeat_tile_batched", s);
+    if (b.lps_shift == 6)
+        hipLaunchKernelGGL((gfeat_tile_batched_kernel<OT, CPL, true>), dim3(blocks),
+                           dim3(64 * b.waves), lds, s, b);
+    else
+        hipLaunchKernelGGL((gfeat_tile_batched_kernel<OT, CPL, false>), dim3(blocks),
+                           dim3(64 * b.waves), lds, s, b);
+    mark_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_gfeat_tiles_batched(const BatchArgs& b, int out_dtype, int cpl, hipStream_t s) {
+    switch (out_dtype * 100 + cpl) {
+        case kF32 * 100 + 1: return tile_batched_launch<TF32, 1>(b, s);
+        case kF32 * 100 + 2: return tile_batched_launch<TF32, 2>(b, s);
+        case kF32 * 100 + 4: return tile_batched_launch<TF32, 4>(b, s);
+        case kBF16 * 100 + 1: return tile_batched_launch<TBF16, 1>(b, s);
+        case kBF16 * 100 + 2: return tile_batched_launch<TBF16, 2>(b, s);
+        case kBF16 * 100 + 4: return tile_batched_launch<TBF16, 4>(b, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_gfeat_tiles(const TileArgs& t, int out_dtype, int cpl, hipStream_t s) {

@@ -243,6 +243,54 @@ __device__ __forceinline__ u32 block_inclusive_scan(u32 v, u32* lds4, u32* total
     return v + before;
 }
 
+// ---------------------------------------------------------------- batched form
+
+// The scene of a batch item index: the last s with start[s] <= item (start
+// is a non-decreasing prefix table of S+1 entries).
+__device__ __forceinline__ int scene_of(const u32* start, int S, u32 item) {
+    int lo = 0, hi = S - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Scene s of a batch as a single-call argument set with B = 1.
+__device__ __forceinline__ OpArgs scene_view(const BatchArgs& b, int s, int feat_bytes) {
+    const msda_scene& sc = b.scenes[s];
+    OpArgs a = {};
+    a.feat = sc.feat;
+    a.shapes = sc.spatial_shapes;
+    a.starts = sc.level_start_index;
+    a.loc = sc.sampling_loc;
+    a.w = sc.weights;
+    a.level_scale = b.level_scale;
+    a.grad_out = sc.grad_out;
+    a.out = sc.out;
+    a.grad_loc = sc.grad_sampling_loc;
+    a.grad_w = sc.grad_weights;
+    a.rec_key = b.rec_key;
+    a.rec_frac = b.rec_frac;
+    a.cell_start = b.rec_key ? b.t.cell_start + b.t.region_start[s] : nullptr;
+    a.cells_per_item = 0;
+    a.cell_offset = 0;
+    a.no_cell = b.total_cells;
+    a.sample_offset = b.rec_key ? b.t.sample_start[s] : 0u;
+    a.B = 1;
+    a.N = sc.num_cams;
+    a.L = b.L;
+    a.A = sc.num_anchors;
+    a.P = b.P;
+    a.C = b.C;
+    a.G = b.G;
+    a.R = sc.rows;
+    a.batch_bytes = (u32)(sc.rows * (int64_t)b.C * feat_bytes);
+    a.lps_shift = b.lps_shift;
+    a.pairs_per_chunk = b.pairs_per_chunk;
+    return a;
+}
+
 // Quotient of n < 2^30 by the divisor whose magic is (m, shift): exact
 // (Granlund-Montgomery with a round-up multiplier, see divmagic()).
 __device__ __forceinline__ u32 fast_div(u32 n, u64 m, int shift) {

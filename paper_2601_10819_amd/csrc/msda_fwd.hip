@@ -24,22 +24,19 @@ size_t lds_bytes_for(const OpArgs& a, int waves) {
     return geo + (stage > red ? stage : red);
 }
 
+// The forward of one anchor (index ba = b*A + a of `a`) by the whole
+// workgroup; the geometry of `a` is already staged in geo. Called by every
+// thread of the block (it ends with block-wide barriers).
 template <class FT, int CPL>
-__global__ void __launch_bounds__(512) msda_fwd_kernel(OpArgs a) {
+__device__ __forceinline__ void fwd_anchor(const OpArgs& a, const int ba, const Geo* geo,
+                                           float* work) {
     using RowT = Row<FT, CPL>;
-    extern __shared__ __align__(16) unsigned char smem[];
-    Geo* geo = reinterpret_cast<Geo*>(smem);
-    float* work = reinterpret_cast<float*>(smem + (size_t)a.N * a.L * sizeof(Geo));
-    stage_geometry(geo, a);
-    __syncthreads();
-
     const int LG = a.L * a.G;
     const int J = a.pairs_per_chunk;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     float* sw = work + wave * J * (LG + 2);
     float* sl = sw + J * LG;
 
-    const int ba = blockIdx.x;
     const int b = ba / a.A;
     const int npairs = a.P * a.N;
     const float* gl = a.loc + (size_t)ba * npairs * 2;
@@ -131,6 +128,60 @@ __global__ void __launch_bounds__(512) msda_fwd_kernel(OpArgs a) {
         float s = 0.f;
         for (int w = 0; w < nwaves; ++w) s += work[w * a.C + c];   // fixed order
         out[c] = s;
+    }
+    __syncthreads();                       // work is free again
+}
+
+template <class FT, int CPL>
+__global__ void __launch_bounds__(512) msda_fwd_kernel(OpArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    Geo* geo = reinterpret_cast<Geo*>(smem);
+    float* work = reinterpret_cast<float*>(smem + (size_t)a.N * a.L * sizeof(Geo));
+    stage_geometry(geo, a);
+    __syncthreads();
+    fwd_anchor<FT, CPL>(a, (int)blockIdx.x, geo, work);
+}
+
+// Batched forward: persistent workgroups stride over the anchors of all
+// scenes; each restages its scene's geometry before the anchor.
+template <class FT, int CPL>
+__global__ void __launch_bounds__(512) msda_fwd_batched_kernel(BatchArgs b) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    Geo* geo = reinterpret_cast<Geo*>(smem);
+    float* work = reinterpret_cast<float*>(smem + (size_t)b.max_regions_per_scene * sizeof(Geo));
+    for (u32 item = blockIdx.x; item < b.total_anchors; item += gridDim.x) {
+        const int s = scene_of(b.t.anchor_start, b.S, item);
+        const OpArgs a = scene_view(b, s, FT::kBytes);
+        __syncthreads();                    // the previous anchor is done with geo and work
+        stage_geometry(geo, a);
+        __syncthreads();
+        fwd_anchor<FT, CPL>(a, (int)(item - b.t.anchor_start[s]), geo, work);
+    }
+}
+
+template <class FT, int CPL>
+static hipError_t fwd_batched_launch(const BatchArgs& b, int waves, int blocks, size_t lds,
+                                     hipStream_t s) {
+    mark_begin("msda_fwd_batched_kernel", s);
+    hipLaunchKernelGGL((msda_fwd_batched_kernel<FT, CPL>), dim3(blocks), dim3(64 * waves), lds, s,
+                       b);
+    mark_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_batched(const BatchArgs& b, int dtype, int cpl, int waves, int blocks,
+                                  size_t lds, hipStream_t s) {
+    switch (dtype * 100 + cpl) {
+        case kF32 * 100 + 1: return fwd_batched_launch<TF32, 1>(b, waves, blocks, lds, s);
+        case kF32 * 100 + 2: return fwd_batched_launch<TF32, 2>(b, waves, blocks, lds, s);
+        case kF32 * 100 + 4: return fwd_batched_launch<TF32, 4>(b, waves, blocks, lds, s);
+        case kBF16 * 100 + 2: return fwd_batched_launch<TBF16, 2>(b, waves, blocks, lds, s);
+        case kBF16 * 100 + 4: return fwd_batched_launch<TBF16, 4>(b, waves, blocks, lds, s);
+        case kBF16 * 100 + 8: return fwd_batched_launch<TBF16, 8>(b, waves, blocks, lds, s);
+        case kFP8 * 100 + 4: return fwd_batched_launch<TFP8, 4>(b, waves, blocks, lds, s);
+        case kFP8 * 100 + 8: return fwd_batched_launch<TFP8, 8>(b, waves, blocks, lds, s);
+        case kFP8 * 100 + 16: return fwd_batched_launch<TFP8, 16>(b, waves, blocks, lds, s);
+        default: return hipErrorInvalidValue;
     }
 }
 

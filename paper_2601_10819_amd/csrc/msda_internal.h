@@ -7,6 +7,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/msda.h"
+
 namespace msda {
 
 // Everything one forward/backward launch needs. Pointers are device memory.
@@ -24,6 +26,9 @@ struct OpArgs {
     float2* rec_frac;             // sorted grad_feat: [S] (lx, ly) bilinear fractions
     const uint32_t* cell_start;   // [N*L] first cell of each region (sorted grad_feat)
     uint32_t cells_per_item;      // cells of one batch item: sum of (H+1)(W+1)
+    uint32_t cell_offset;         // added to every cell key (a scene's place in a batch)
+    uint32_t no_cell;             // key of a sample outside its level (sorts last)
+    uint32_t sample_offset;       // added to every record index
     float* grad_loc;              // or nullptr
     float* grad_w;                // or nullptr
     int32_t B, N, L, A, P, C, G;
@@ -62,6 +67,47 @@ struct TileArgs {
     int32_t magic_shift;
 };
 
+// Batched form: tables over all scenes, built on the device from the scene
+// table by batch_tables_kernel. Regions are numbered scene by scene (scene
+// s owns regions [region_start[s], region_start[s+1]), camera-major); slots
+// order the regions for the tiled reduction: heavy (coarse) levels first,
+// then by level (coarsest first), scene and camera.
+constexpr int kMaxBatchScenes = 256;
+constexpr int kMaxBatchRegions = 4096;
+
+struct BatchTables {
+    uint32_t* anchor_start;       // [S+1] first anchor (over all scenes) of each scene
+    uint32_t* sample_start;       // [S+1] first sample / record of each scene
+    uint32_t* region_start;       // [S+1] first region of each scene
+    uint32_t* cell_start;         // [regions] first cell of each region (global)
+    uint32_t* slot_scene;         // [regions] scene of each slot
+    uint32_t* slot_region;        // [regions] region (within its scene) of each slot
+    uint32_t* tile_start;         // [regions + 1] first tile of each slot
+    uint64_t* magic;              // [S] sample -> anchor division by P*Ncam*L
+    uint32_t* magic_shift;        // [S]
+};
+
+struct BatchArgs {
+    const msda_scene* scenes;     // device scene table
+    int32_t S, L, P, C, G;
+    const float* level_scale;
+    BatchTables t;
+    uint32_t total_anchors;
+    uint32_t total_samples;
+    uint32_t total_cells;
+    uint32_t total_regions;
+    int32_t lps_shift;            // log2(C / chans_per_lane)
+    int32_t pairs_per_chunk;
+    int32_t max_regions_per_scene;   // LDS sizing of the geometry table
+    uint32_t* rec_key;            // backward, grad_feat records (or nullptr)
+    float2* rec_frac;
+    // tiled reduction
+    const uint32_t* vals;
+    const uint32_t* off;
+    int32_t waves;
+    uint32_t tile_begin, tile_end;
+};
+
 enum FeatType { kF32 = 0, kBF16 = 1, kFP8 = 2 };
 
 // Launchers return hipSuccess or the launch error. They enqueue only.
@@ -81,6 +127,13 @@ hipError_t launch_sort_records(uint32_t* keys_a, uint32_t* keys_b, uint32_t* val
                                uint32_t* off, uint32_t** sorted_vals, hipStream_t s);
 size_t sort_scratch_words(uint32_t n);
 int sort_passes(uint32_t max_key);
+
+hipError_t launch_batch_tables(const BatchArgs& b, bool backward, hipStream_t s);
+hipError_t launch_forward_batched(const BatchArgs& b, int dtype, int cpl, int waves, int blocks,
+                                  size_t lds_bytes, hipStream_t s);
+hipError_t launch_backward_batched(const BatchArgs& b, int dtype, int cpl, int waves, int blocks,
+                                   size_t lds_bytes, hipStream_t s);
+hipError_t launch_gfeat_tiles_batched(const BatchArgs& b, int out_dtype, int cpl, hipStream_t s);
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, size_t n, hipStream_t s);

@@ -213,3 +213,116 @@ def msda(feat, layout: Layout, sampling_loc, weights, level_scale=None, determin
          tile=None):
     """Autograd-aware MSDA."""
     return MSDAFunction.apply(feat, sampling_loc, weights, layout, level_scale, deterministic, tile)
+
+
+class SceneBatch:
+    """Uneven scenes processed together: the batched form of MSDA.
+
+    Each scene has its own cameras, feature geometry and anchors; levels,
+    keypoints, channels, groups and the feature dtype are shared. The batch
+    owns every output and gradient buffer and a device copy of the scene
+    table, built once here, so forward() / backward() allocate nothing and
+    can be captured in a HIP graph (torch.cuda.graph). Write each scene's
+    upstream gradient into ``grad_out[s]`` before backward().
+
+    scenes: list of (feat [R, C], Layout, sampling_loc [A, P, Ncam, 2],
+    weights [A, P, Ncam, L, G]) on the device.
+    """
+
+    def __init__(self, scenes, level_scale=None, need_feat=True, need_loc=True, need_w=True,
+                 tile=None, deterministic=False):
+        lib = _lib.load()
+        if not scenes:
+            raise ValueError("empty batch")
+        feat0, lay0, loc0, w0 = scenes[0]
+        self.device = feat0.device
+        self.C = feat0.shape[-1]
+        self.L, self.G = w0.shape[-2], w0.shape[-1]
+        self.P = loc0.shape[1]
+        self.dtype = feat0.dtype
+        self.scenes = scenes
+        self.level_scale = level_scale
+        self.out, self.grad_out, self.grad_feat, self.grad_loc, self.grad_w = [], [], [], [], []
+        n = len(scenes)
+        host = (_lib.MsdaScene * n)()
+        self._host_shapes = (ctypes.c_void_p * n)()
+        self._host_starts = (ctypes.c_void_p * n)()
+        for s, (feat, layout, loc, w) in enumerate(scenes):
+            for name, t in (("feat", feat), ("sampling_loc", loc), ("weights", w)):
+                _need_cuda_contig(f"scene {s} {name}", t)
+            if feat.dim() != 2 or loc.dim() != 4 or w.dim() != 5:
+                raise ValueError("scene tensors: feat [R,C], loc [A,P,Ncam,2], w [A,P,Ncam,L,G]")
+            if feat.dtype != self.dtype or feat.shape[1] != self.C:
+                raise ValueError(f"scene {s}: feat dtype / channels differ from scene 0")
+            A = loc.shape[0]
+            out = torch.empty(A, self.C, device=self.device, dtype=torch.float32)
+            go = torch.zeros(A, self.C, device=self.device, dtype=torch.float32)
+            gf = torch.empty_like(feat) if need_feat else None
+            gl = torch.empty_like(loc) if need_loc else None
+            gw = torch.empty_like(w) if need_w else None
+            self.out.append(out)
+            self.grad_out.append(go)
+            self.grad_feat.append(gf)
+            self.grad_loc.append(gl)
+            self.grad_w.append(gw)
+            h = host[s]
+            h.feat, h.spatial_shapes = feat.data_ptr(), layout.shapes.data_ptr()
+            h.level_start_index = layout.starts.data_ptr()
+            h.sampling_loc, h.weights = loc.data_ptr(), w.data_ptr()
+            h.out, h.grad_out = out.data_ptr(), go.data_ptr()
+            h.grad_feat = gf.data_ptr() if gf is not None else None
+            h.grad_sampling_loc = gl.data_ptr() if gl is not None else None
+            h.grad_weights = gw.data_ptr() if gw is not None else None
+            h.rows, h.num_cams, h.num_anchors = feat.shape[0], layout.num_cams, A
+            if layout.num_levels != self.L:
+                raise ValueError(f"scene {s}: {layout.num_levels} levels, scene 0 has {self.L}")
+            self._host_shapes[s] = layout.host_shapes.ctypes.data
+            self._host_starts[s] = layout.host_starts.ctypes.data
+        self._host = host
+        raw = bytes(host)
+        self._dev_table = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
+        b = _lib.MsdaBatch()
+        b.num_scenes, b.num_levels, b.num_points = n, self.L, self.P
+        b.channels, b.groups, b.feat_dtype = self.C, self.G, _DTYPES[self.dtype]
+        b.scenes = self._dev_table.data_ptr()
+        b.host_scenes = ctypes.cast(host, ctypes.POINTER(_lib.MsdaScene))
+        b.host_spatial_shapes = ctypes.cast(self._host_shapes, ctypes.POINTER(ctypes.c_void_p))
+        b.host_level_start_index = ctypes.cast(self._host_starts, ctypes.POINTER(ctypes.c_void_p))
+        b.level_scale = level_scale.data_ptr() if level_scale is not None else None
+        b.flags = _lib.MSDA_DETERMINISTIC if deterministic else 0
+        if tile:
+            self._tile = _lib.MsdaTile(int(tile.get("waves_per_anchor", 0)),
+                                       int(tile.get("chans_per_lane", 0)),
+                                       int(tile.get("anchors_per_block", 0)), int(tile.get("scatter", 0)))
+            b.tile = ctypes.pointer(self._tile)
+        self._batch = b
+        fwd_ws = int(lib.msda_batched_workspace_size(ctypes.byref(b), 0))
+        bwd_ws = int(lib.msda_batched_workspace_size(ctypes.byref(b), 1))
+        # the size query returns 0 for an invalid batch: a call without a
+        # workspace then reports why (validation comes first)
+        if fwd_ws == 0:
+            _lib.check(lib.msda_forward_batched(ctypes.byref(b), None, 0, None))
+        if bwd_ws == 0:
+            _lib.check(lib.msda_backward_batched(ctypes.byref(b), None, 0, None))
+        self._ws = torch.empty(max(fwd_ws, bwd_ws) + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self._ws_len = self._ws.numel() - (self._ws_ptr - base)
+
+    @property
+    def samples(self) -> int:
+        return sum(loc.shape[0] * loc.shape[1] * loc.shape[2] * self.L
+                   for _, _, loc, _ in self.scenes)
+
+    def forward(self, stream=None):
+        lib = _lib.load()
+        _lib.check(lib.msda_forward_batched(ctypes.byref(self._batch), ctypes.c_void_p(self._ws_ptr),
+                                            self._ws_len, _stream(stream)))
+        return self.out
+
+    def backward(self, stream=None):
+        lib = _lib.load()
+        _lib.check(lib.msda_backward_batched(ctypes.byref(self._batch),
+                                             ctypes.c_void_p(self._ws_ptr), self._ws_len,
+                                             _stream(stream)))
+        return self.grad_feat, self.grad_loc, self.grad_w

@@ -208,3 +208,60 @@ def test_python_binding_fails_loudly_without_library(tmp_path):
             mod.load(str(tmp_path / "nope.so"))
     finally:
         mod._lib = saved
+
+
+def batch_desc(geos, anchors, grads=(True, True, True)):
+    n = len(geos)
+    host = (_lib.MsdaScene * n)()
+    shp = (ctypes.c_void_p * n)()
+    sts = (ctypes.c_void_p * n)()
+    for s, (g, a) in enumerate(zip(geos, anchors)):
+        h = host[s]
+        h.feat = h.spatial_shapes = h.level_start_index = FAKE
+        h.sampling_loc = h.weights = h.out = h.grad_out = FAKE
+        h.grad_feat = FAKE if grads[0] else None
+        h.grad_sampling_loc = FAKE if grads[1] else None
+        h.grad_weights = FAKE if grads[2] else None
+        h.rows, h.num_cams, h.num_anchors = g.rows, g.shapes.shape[0], a
+        shp[s] = g.shapes.ctypes.data
+        sts[s] = g.starts.ctypes.data
+    b = _lib.MsdaBatch()
+    b.num_scenes, b.num_levels, b.num_points, b.channels, b.groups = n, geos[0].shapes.shape[1], 3, 32, 4
+    b.feat_dtype = _lib.MSDA_F32
+    b.scenes = FAKE
+    b.host_scenes = ctypes.cast(host, ctypes.POINTER(_lib.MsdaScene))
+    b.host_spatial_shapes = ctypes.cast(shp, ctypes.POINTER(ctypes.c_void_p))
+    b.host_level_start_index = ctypes.cast(sts, ctypes.POINTER(ctypes.c_void_p))
+    b._keep = (host, shp, sts, geos)
+    return b
+
+
+def test_batched_validation(lib):
+    geos = [Geo(ncam=2), Geo(ncam=5, levels=((6, 10), (3, 5)))]
+    b = batch_desc(geos, [4, 7])
+    fwd_ws = lib.msda_batched_workspace_size(ctypes.byref(b), 0)
+    bwd_ws = lib.msda_batched_workspace_size(ctypes.byref(b), 1)
+    assert 0 < fwd_ws < bwd_ws
+    expect(lib, lib.msda_forward_batched(ctypes.byref(b), None, 0, None), WS, "workspace")
+    expect(lib, lib.msda_backward_batched(ctypes.byref(b), FAKE, bwd_ws - 1, None), WS)
+    b.num_scenes = 0
+    expect(lib, lib.msda_forward_batched(ctypes.byref(b), FAKE, 1 << 30, None), INV, "num_scenes")
+    assert lib.msda_batched_workspace_size(ctypes.byref(b), 0) == 0
+    # a scene whose regions leave its rows
+    bad = Geo(ncam=2)
+    bad.rows -= 1
+    b = batch_desc([Geo(ncam=2), bad], [4, 4])
+    expect(lib, lib.msda_forward_batched(ctypes.byref(b), FAKE, 1 << 30, None), INV, "scene 1")
+    # gradients requested by some scenes only
+    b = batch_desc(geos, [4, 7])
+    b.host_scenes[1].grad_weights = None
+    expect(lib, lib.msda_backward_batched(ctypes.byref(b), FAKE, 1 << 30, None), INV, "NULL in all")
+    # more (camera, level) regions than the batched tables hold
+    big = [Geo(ncam=64, levels=((2, 2),) * 4) for _ in range(17)]
+    b = batch_desc(big, [1] * 17)
+    expect(lib, lib.msda_forward_batched(ctypes.byref(b), FAKE, 1 << 30, None), UNS, "regions")
+    # the batched backward has no atomic form
+    b = batch_desc(geos, [4, 7])
+    t = _lib.MsdaTile(0, 0, 0, _lib.MSDA_SCATTER_ATOMIC)
+    b.tile = ctypes.pointer(t)
+    expect(lib, lib.msda_backward_batched(ctypes.byref(b), FAKE, 1 << 30, None), UNS, "sorted")

@@ -1,0 +1,178 @@
+"""Batched form: uneven scenes (cameras, resolution, anchors) in one
+persistent launch per pass. Checked bit for bit against the single-call
+entry points on each scene (same launch shape), against the FP64 oracle,
+and under HIP-graph capture and replay."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import (BF16_TOL, FWD_F32_MAXREL, FWD_F32_TOL, GRAD_F32_MAXREL, GRAD_F32_TOL,
+                     anchor_subset, assert_close, host, normwise)
+from paper_2601_10819_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TILE = {"waves_per_anchor": 4}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_2601_10819_amd import ops as o
+    o._lib.load()
+    return o
+
+
+def small_batch(seed=0, scenes=6, scale=0.04, max_cams=6, empty_scene=True):
+    probs = synth.batched(seed=seed, scenes=scenes, scale_anchors=scale, max_cams=max_cams)
+    if empty_scene:
+        p = probs[1]
+        probs[1] = synth.Problem(p.name + "_empty", p.feat, p.spatial_shapes, p.level_start_index,
+                                 p.sampling_loc[:, :0].contiguous(), p.weights[:, :0].contiguous())
+    return probs
+
+
+def to_scenes(ops, probs, dtype):
+    out = []
+    for p in probs:
+        out.append((p.feat[0].to(dtype).cuda(), ops.Layout(p.spatial_shapes, p.level_start_index),
+                    p.sampling_loc[0].cuda(), p.weights[0].cuda()))
+    return out
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16], ids=["f32", "bf16"])
+def test_batched_equals_single_calls_bitwise(ops, dtype):
+    probs = small_batch()
+    print("case", [p.dims() for p in probs], flush=True)
+    scenes = to_scenes(ops, probs, dtype)
+    batch = ops.SceneBatch(scenes, tile=TILE)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    for go in batch.grad_out:
+        go.normal_(generator=gen)
+    batch.forward()
+    batch.backward()
+    torch.cuda.synchronize()
+    for s, (feat, layout, loc, w) in enumerate(scenes):
+        out = ops.forward(feat[None], layout, loc[None], w[None], tile=TILE)
+        gf, gl, gw = ops.backward(feat[None], layout, loc[None], w[None], batch.grad_out[s][None],
+                                  tile=TILE)
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], batch.out[s]), f"scene {s} out"
+        assert torch.equal(gf[0], batch.grad_feat[s]), f"scene {s} grad_feat"
+        assert torch.equal(gl[0], batch.grad_loc[s]), f"scene {s} grad_loc"
+        assert torch.equal(gw[0], batch.grad_w[s]), f"scene {s} grad_w"
+
+
+def test_batched_matches_oracle(ops, oracle_mod):
+    probs = small_batch(seed=1, scenes=4, scale=0.02, max_cams=4)
+    scenes = to_scenes(ops, probs, torch.float32)
+    batch = ops.SceneBatch(scenes)
+    gos = [synth.grad_out_like(p, seed=10 + s)[0] for s, p in enumerate(probs)]
+    for go, g in zip(batch.grad_out, gos):
+        go.copy_(g)
+    batch.forward()
+    batch.backward()
+    torch.cuda.synchronize()
+    for s, p in enumerate(probs):
+        if p.num_anchors == 0:
+            assert batch.out[s].numel() == 0
+            assert torch.all(batch.grad_feat[s] == 0)
+            continue
+        ref = oracle_mod.forward(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                                 p.weights)
+        assert_close(host(batch.out[s])[None], ref, FWD_F32_TOL, FWD_F32_MAXREL, f"scene {s} out")
+        rgf, rgl, rgw = oracle_mod.backward(p.feat, p.spatial_shapes, p.level_start_index,
+                                            p.sampling_loc, p.weights, gos[s][None])
+        assert_close(host(batch.grad_feat[s])[None], rgf, GRAD_F32_TOL, GRAD_F32_MAXREL, "gf")
+        assert_close(host(batch.grad_loc[s])[None], rgl, GRAD_F32_TOL, GRAD_F32_MAXREL, "gl")
+        assert_close(host(batch.grad_w[s])[None], rgw, GRAD_F32_TOL, GRAD_F32_MAXREL, "gw")
+
+
+def test_batched_graph_capture_replay(ops):
+    """Forward + backward captured once and replayed: every replay equals the
+    eager result bit for bit, with eager work and synchronisation between
+    replays; an input updated in place between replays is picked up."""
+    probs = small_batch(seed=2, scenes=5, scale=0.03, max_cams=5)
+    scenes = to_scenes(ops, probs, torch.bfloat16)
+    batch = ops.SceneBatch(scenes)
+    gen = torch.Generator(device="cuda").manual_seed(6)
+    for go in batch.grad_out:
+        go.normal_(generator=gen)
+    batch.forward()
+    batch.backward()
+    torch.cuda.synchronize()
+    eager = [t.clone() for t in batch.out + batch.grad_feat + batch.grad_loc + batch.grad_w]
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            batch.forward()
+            batch.backward()
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for t in batch.out + batch.grad_feat + batch.grad_loc + batch.grad_w:
+            t.fill_(float("nan") if t.is_floating_point() else 0)   # eager work in between
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        now = batch.out + batch.grad_feat + batch.grad_loc + batch.grad_w
+        for a, b in zip(now, eager):
+            assert torch.equal(a, b), f"replay {rep}"
+    # update one scene's weights in place: the replay uses the new values
+    scenes[0][3].mul_(2.0)
+    graph.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(batch.out[0], eager[0] * 2.0)
+
+
+def test_batched_full_size_bf16(ops, oracle_mod):
+    """The 12-scene uneven batch at full size (BF16 features): a sampled
+    check against the oracle per scene and the Euler identity per scene."""
+    probs = synth.batched(seed=0)
+    print("scenes", [(p.num_cams, p.rows, p.num_anchors) for p in probs], flush=True)
+    scenes = to_scenes(ops, probs, torch.bfloat16)
+    batch = ops.SceneBatch(scenes)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    for go in batch.grad_out:
+        go.normal_(generator=gen)
+    batch.forward()
+    batch.backward()
+    torch.cuda.synchronize()
+    for s in (0, 5, 11):
+        p = probs[s]
+        idx = anchor_subset(p, 8, seed=s)
+        feat64 = p.feat.to(torch.bfloat16).double()
+        ref = oracle_mod.forward(feat64, p.spatial_shapes, p.level_start_index,
+                                 p.sampling_loc[:, idx].contiguous(), p.weights[:, idx].contiguous())
+        assert_close(host(batch.out[s])[idx][None], ref, FWD_F32_TOL, FWD_F32_MAXREL, f"scene {s}")
+    for s in range(len(probs)):
+        feat, layout, loc, w = scenes[s]
+        e_out = float((batch.out[s].double() * batch.grad_out[s].double()).sum())
+        pf = batch.grad_feat[s].double() * feat.double()
+        pw = batch.grad_w[s].double() * w.double()
+        # grad_feat is rounded to BF16 once per element (relative error <= 2^-9
+        # each), so the identity holds to 2^-9 of the sum of |terms|
+        assert abs(float(pf.sum()) - e_out) <= 2.0 ** -9 * float(pf.abs().sum()), (s, e_out)
+        assert abs(float(pw.sum()) - e_out) <= 1e-5 * float(pw.abs().sum()), (s, e_out)
+
+
+def test_batched_single_scene_and_validation(ops):
+    probs = small_batch(seed=3, scenes=1, empty_scene=False)
+    scenes = to_scenes(ops, probs, torch.float32)
+    batch = ops.SceneBatch(scenes, tile=TILE)
+    batch.forward()
+    torch.cuda.synchronize()
+    feat, layout, loc, w = scenes[0]
+    out = ops.forward(feat[None], layout, loc[None], w[None], tile=TILE)
+    torch.cuda.synchronize()
+    assert torch.equal(out[0], batch.out[0])
+    # mixed gradient requests are rejected
+    with pytest.raises(ValueError):
+        ops.SceneBatch(scenes + [(feat.to(torch.bfloat16), layout, loc, w)])
