@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--workload", default="cam64", choices=["cam64", "train16", "sparse4d"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage comparison")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 12-scene batched form (graph-replayed, autotuned)")
     ap.add_argument("--cpu-anchors", type=int, default=0,
                     help="anchors in the oracle's timed sample (0 = all of them)")
     return ap.parse_args()
@@ -159,6 +161,63 @@ def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup):
     return {"total_s": t1 - t0, "kernels": kern}
 
 
+def run_batched(torch, ops, synth, steps, warmup):
+    """The uneven 12-scene batch (BF16 storage) in the batched form: launch
+    shape from the autotuner (tuned here, not cached), forward + backward
+    captured once in a HIP graph and replayed `steps` times; the eager rate of
+    the same calls beside it."""
+    from paper_2601_10819_amd import autotune
+    probs = synth.batched(seed=0)
+    scenes = [(p.feat[0].to(torch.bfloat16).cuda(), ops.Layout(p.spatial_shapes, p.level_start_index),
+               p.sampling_loc[0].cuda(), p.weights[0].cuda()) for p in probs]
+    batch = ops.SceneBatch(scenes)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    for go in batch.grad_out:
+        go.normal_(generator=gen)
+    tuned = autotune.tune_batch(batch, reps=3, save=False)
+
+    def step():
+        batch.forward()
+        batch.backward()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    eager_s = time.perf_counter() - t0
+
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            step()
+    torch.cuda.current_stream().wait_stream(stream)
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    graph_s = time.perf_counter() - t0
+    S = batch.samples
+    return {
+        "workload": "batch_12scenes_uneven",
+        "scenes": [[p.num_cams, int(p.rows), p.num_anchors] for p in probs],
+        "samples_per_step": S,
+        "tile": tuned["tile"],
+        "graph_ms_per_step": round(graph_s / steps * 1e3, 4),
+        "graph_value": round(S * steps / graph_s / 1e9, 4),
+        "eager_ms_per_step": round(eager_s / steps * 1e3, 4),
+        "eager_value": round(S * steps / eager_s / 1e9, 4),
+        "unit": "GSamples/s",
+    }
+
+
 def copy_bandwidth(torch, ops, nbytes=1 << 30, reps=10):
     """Achievable streaming bandwidth (read + write) of the library's copy kernel."""
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -236,9 +295,8 @@ def main():
     alg_per_sample = {"msda_fwd_kernel": fwd_b,
                       # the backward's gather kernel: re-gather, weights + grad_w,
                       # loc + grad_loc, grad_out; the grad_feat scatter bytes are
-                      # charged to the row-reduction kernel
-                      "msda_bwd_kernel": bwd_b - 4 * C * 2,
-                      "gfeat_reduce_kernel": 4 * C * 2}.get(kern)
+                      # charged to the tiled grad_feat reduction
+                      "msda_bwd_kernel": bwd_b - 4 * C * 2}.get(kern)
     kbytes = S * alg_per_sample if alg_per_sample else None
     achieved = kbytes / (kms * 1e-3) / 1e9 if kbytes else None
     traffic = measured_traffic(kern, p.name, "bf16")
@@ -275,6 +333,9 @@ def main():
         res["fp32_value"] = round(S * args.steps / fp["total_s"] / 1e9, 4)
         res["bf16_speedup_vs_fp32"] = round(fp_ms / ms_step, 3)
         res["fp32_kernels_ms"] = {n: round(v["ms"], 4) for n, v in fp["kernels"].items()}
+    if not args.no_batched:
+        res["batched"] = run_batched(torch, ops, synth, args.steps, args.warmup)
+        print(f"# batched done: {res['batched']}", file=sys.stderr, flush=True)
     res["copy_GBps"] = round(copy_bandwidth(torch, ops), 1)
 
     if not args.no_cpu:

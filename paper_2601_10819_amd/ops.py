@@ -99,10 +99,25 @@ def make_desc(feat: torch.Tensor, layout: Layout, sampling_loc: torch.Tensor,
     return d
 
 
+def _resolve_tile(tile, which, feat, sampling_loc, weights):
+    """tile="auto": the autotuner's cached shape for this workload (or the
+    library's own choice when nothing is cached)."""
+    if tile != "auto":
+        return tile
+    from . import autotune
+    B, _, C = feat.shape
+    A, P, N = sampling_loc.shape[1], sampling_loc.shape[2], sampling_loc.shape[3]
+    entry = autotune.lookup(autotune.shape_key(feat.dtype, C, weights.shape[5], weights.shape[4],
+                                               P, N, A, B, "single"))
+    return entry.get(which) if entry else None
+
+
 def forward(feat, layout: Layout, sampling_loc, weights, level_scale=None, tile=None,
             out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """out [B, A, C] FP32 = MSDA(feat, loc, weights) on the current stream."""
+    """out [B, A, C] FP32 = MSDA(feat, loc, weights) on the current stream.
+    tile: None (the library's choice), a dict of msda_tile fields, or "auto"."""
     lib = _lib.load()
+    tile = _resolve_tile(tile, "forward", feat, sampling_loc, weights)
     _need_cuda_contig("feat", feat)
     _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
     _need_cuda_contig("weights", weights, torch.float32)
@@ -130,6 +145,7 @@ def backward(feat, layout: Layout, sampling_loc, weights, grad_out,
              ) -> Tuple[Optional[torch.Tensor], Optional[torch.Tensor], Optional[torch.Tensor]]:
     """(grad_feat, grad_sampling_loc, grad_weights); an unrequested one is None."""
     lib = _lib.load()
+    tile = _resolve_tile(tile, "backward", feat, sampling_loc, weights)
     _need_cuda_contig("feat", feat)
     _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
     _need_cuda_contig("weights", weights, torch.float32)
@@ -290,12 +306,16 @@ class SceneBatch:
         b.host_level_start_index = ctypes.cast(self._host_starts, ctypes.POINTER(ctypes.c_void_p))
         b.level_scale = level_scale.data_ptr() if level_scale is not None else None
         b.flags = _lib.MSDA_DETERMINISTIC if deterministic else 0
-        if tile:
-            self._tile = _lib.MsdaTile(int(tile.get("waves_per_anchor", 0)),
-                                       int(tile.get("chans_per_lane", 0)),
-                                       int(tile.get("anchors_per_block", 0)), int(tile.get("scatter", 0)))
-            b.tile = ctypes.pointer(self._tile)
         self._batch = b
+        self._tile = _lib.MsdaTile()
+        if tile == "auto":
+            from . import autotune
+            cams = max(layout.num_cams for _, layout, _, _ in scenes)
+            anchors = sum(loc.shape[0] for _, _, loc, _ in scenes)
+            entry = autotune.lookup(autotune.shape_key(self.dtype, self.C, self.G, self.L, self.P,
+                                                       cams, anchors, 1, "batch"))
+            tile = entry.get("tile") if entry else None
+        self.set_tile(tile)
         fwd_ws = int(lib.msda_batched_workspace_size(ctypes.byref(b), 0))
         bwd_ws = int(lib.msda_batched_workspace_size(ctypes.byref(b), 1))
         # the size query returns 0 for an invalid batch: a call without a
@@ -308,6 +328,19 @@ class SceneBatch:
         base = self._ws.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         self._ws_len = self._ws.numel() - (self._ws_ptr - base)
+
+    def set_tile(self, tile: Optional[dict]):
+        """Launch shape of later calls: None for the library's choice."""
+        if tile:
+            t = self._tile
+            t.waves_per_anchor = int(tile.get("waves_per_anchor", 0))
+            t.chans_per_lane = int(tile.get("chans_per_lane", 0))
+            t.anchors_per_block = int(tile.get("anchors_per_block", 0))
+            t.scatter = int(tile.get("scatter", 0))
+            self._batch.tile = ctypes.pointer(self._tile)
+        else:
+            self._batch.tile = None
+        self.tile = dict(tile) if tile else None
 
     @property
     def samples(self) -> int:
