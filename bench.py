@@ -121,9 +121,11 @@ def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup):
     out = torch.empty(p.batch, p.num_anchors, p.channels, device=dev)
     ws_bytes = ops.backward_workspace_bytes(feat, layout, loc, w)
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev) if ws_bytes else None
+    fws_bytes = ops.forward_workspace_bytes(feat, layout, loc, w)
+    fws = torch.empty(fws_bytes + 256, dtype=torch.uint8, device=dev) if fws_bytes else None
 
     def step():
-        ops.forward(feat, layout, loc, w, out=out)
+        ops.forward(feat, layout, loc, w, out=out, workspace=fws)
         ops.backward(feat, layout, loc, w, go, workspace=ws)
 
     for _ in range(warmup):
@@ -292,11 +294,12 @@ def main():
     ks = bf["kernels"]
     kern = max(ks, key=lambda n: ks[n]["ms"] * ks[n]["per_step"])
     kms = ks[kern]["ms"]
-    alg_per_sample = {"msda_fwd_kernel": fwd_b,
+    gather_bwd = bwd_b - 4 * C * 2
+    alg_per_sample = {"msda_fwd_kernel": fwd_b, "msda_fwd_view_kernel": fwd_b,
                       # the backward's gather kernel: re-gather, weights + grad_w,
                       # loc + grad_loc, grad_out; the grad_feat scatter bytes are
                       # charged to the tiled grad_feat reduction
-                      "msda_bwd_kernel": bwd_b - 4 * C * 2}.get(kern)
+                      "msda_bwd_kernel": gather_bwd, "msda_bwd_view_kernel": gather_bwd}.get(kern)
     kbytes = S * alg_per_sample if alg_per_sample else None
     achieved = kbytes / (kms * 1e-3) / 1e9 if kbytes else None
     traffic = measured_traffic(kern, p.name, "bf16")

@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define MSDA_ABI_VERSION 1
+#define MSDA_ABI_VERSION 2
 
 typedef enum msda_status {
     MSDA_OK = 0,
@@ -80,12 +80,25 @@ typedef enum msda_dtype {
 #define MSDA_SCATTER_ATOMIC 2 /* FP32 float atomics into an accumulator: run-to-run
                                  differences in the last bits                        */
 
+/* msda_tile.order: how the gathers split the work */
+#define MSDA_ORDER_AUTO 0   /* the library's choice                                    */
+#define MSDA_ORDER_ANCHOR 1 /* one workgroup per (batch item, anchor); its waves split
+                               the anchor's (keypoint, camera) pairs                   */
+#define MSDA_ORDER_VIEW 2   /* the (batch item, camera) x anchor work is cut, camera-
+                               major, into 8 equal ranges, one per XCD, so each XCD's
+                               L2 holds the pyramids of a few cameras at a time; each
+                               wave takes one anchor over its cameras in a range. The
+                               forward then adds 8 partial sums per anchor in a fixed
+                               order and needs a workspace (msda_forward_ws)           */
+
 /* Launch shape. A zero field means "choose". */
 typedef struct msda_tile {
-    int32_t waves_per_anchor; /* wavefronts (64 lanes) sharing one anchor: 1, 2, 4, 8 */
+    int32_t waves_per_anchor; /* anchor order: wavefronts (64 lanes) sharing one
+                                 anchor; view order: wavefronts per workgroup, one
+                                 anchor each. 1, 2, 4 or 8                            */
     int32_t chans_per_lane;   /* channels each lane owns: 1, 2, 4 (FP32), 2, 4, 8
                                  (BF16), 4, 8, 16 (FP8)                              */
-    int32_t anchors_per_block;/* reserved, must be 0 or 1                              */
+    int32_t order;            /* MSDA_ORDER_*                                          */
     int32_t scatter;          /* MSDA_SCATTER_* (backward only)                        */
 } msda_tile;
 
@@ -121,6 +134,25 @@ msda_status msda_forward(const void* feat, const int32_t* spatial_shapes,
                          const int32_t* level_start_index, const float* sampling_loc,
                          const float* weights, float* out, const msda_desc* desc,
                          void* stream);
+
+/*
+ * msda_forward with a workspace, which lets the library use view order
+ * (MSDA_ORDER_VIEW) for the forward: the library's choice for inputs with at
+ * least 8 (batch item, camera) views. Same results contract as
+ * msda_forward; the two orders add the samples in different orders, each
+ * fixed (deterministic).
+ * workspace: device, 256-byte aligned, at least
+ * msda_forward_workspace_size(desc) bytes (may be NULL when that is 0).
+ * Returns MSDA_ERR_WORKSPACE if it is missing or too small.
+ */
+msda_status msda_forward_ws(const void* feat, const int32_t* spatial_shapes,
+                            const int32_t* level_start_index, const float* sampling_loc,
+                            const float* weights, float* out, void* workspace,
+                            size_t workspace_bytes, const msda_desc* desc, void* stream);
+
+/* Bytes of device workspace msda_forward_ws needs for desc: 8*B*A*C*4 when
+ * the forward runs in view order (chosen or requested), else 0. */
+size_t msda_forward_workspace_size(const msda_desc* desc);
 
 /*
  * Backward: gradients of <grad_out, out> with respect to feat, sampling_loc

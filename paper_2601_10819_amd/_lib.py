@@ -25,11 +25,12 @@ MSDA_FP8_E4M3 = 2
 
 MSDA_DETERMINISTIC = 1
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 # Every symbol include/msda.h declares.
 EXPORTS = (
-    "msda_forward", "msda_backward", "msda_backward_workspace_size", "msda_quantize_fp8",
+    "msda_forward", "msda_forward_ws", "msda_forward_workspace_size", "msda_backward",
+    "msda_backward_workspace_size", "msda_quantize_fp8",
     "msda_quantize_workspace_size", "msda_batched_workspace_size", "msda_forward_batched",
     "msda_backward_batched", "msda_stream_copy", "msda_set_kernel_events",
     "msda_recorded_kernels", "msda_recorded_kernel_name", "msda_last_error", "msda_abi_version",
@@ -39,10 +40,15 @@ MSDA_SCATTER_AUTO = 0
 MSDA_SCATTER_SORTED = 1
 MSDA_SCATTER_ATOMIC = 2
 
+MSDA_ORDER_AUTO = 0
+MSDA_ORDER_ANCHOR = 1
+MSDA_ORDER_VIEW = 2
+ORDERS = {"auto": MSDA_ORDER_AUTO, "anchor": MSDA_ORDER_ANCHOR, "view": MSDA_ORDER_VIEW}
+
 
 class MsdaTile(ctypes.Structure):
     _fields_ = [("waves_per_anchor", ctypes.c_int32), ("chans_per_lane", ctypes.c_int32),
-                ("anchors_per_block", ctypes.c_int32), ("scatter", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("scatter", ctypes.c_int32)]
 
 
 class MsdaDesc(ctypes.Structure):
@@ -103,6 +109,10 @@ def load(path: str = LIB_PATH):
     vp, sz, dp = ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(MsdaDesc)
     lib.msda_forward.argtypes = [vp] * 6 + [dp, vp]
     lib.msda_forward.restype = ctypes.c_int
+    lib.msda_forward_ws.argtypes = [vp] * 7 + [sz, dp, vp]
+    lib.msda_forward_ws.restype = ctypes.c_int
+    lib.msda_forward_workspace_size.argtypes = [dp]
+    lib.msda_forward_workspace_size.restype = sz
     lib.msda_backward.argtypes = [vp] * 10 + [sz, dp, vp]
     lib.msda_backward.restype = ctypes.c_int
     lib.msda_backward_workspace_size.argtypes = [dp]

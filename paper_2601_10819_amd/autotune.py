@@ -1,8 +1,9 @@
 """Launch-shape autotuner for the MSDA kernels.
 
-A launch shape ("tile") is the number of waves that share one anchor and
-the number of channels each lane owns (which fixes how many samples a wave
-processes at once). The best choice depends on the problem: anchors and
+A launch shape ("tile") is the work order (anchor or view, see
+include/msda.h), the number of waves per anchor (anchor order) or per
+workgroup (view order), and the number of channels each lane owns (which
+fixes how many samples a wave processes at once). The best choice depends on the problem: anchors and
 cameras set the parallelism, the feature dtype the load width. For a given
 workload the tuner runs every shape the library accepts, checks that its
 results agree with the library's own choice (a shape that disagrees is
@@ -85,17 +86,22 @@ def lookup(key: str, path: Optional[str] = None) -> Optional[dict]:
     return load_cache(path).get(key)
 
 
-def candidates(dtype, C: int, G: int) -> List[dict]:
+ORDERS = ("anchor", "view")
+
+
+def candidates(dtype, C: int, G: int, orders=ORDERS) -> List[dict]:
     """Launch shapes the library accepts for C channels in G groups: C/cpl a
-    power of two <= 64 and whole lanes per group."""
+    power of two <= 64 and whole lanes per group, in each work order."""
     out = []
-    for cpl in CPL[dtype]:
-        lps = C // cpl if C % cpl == 0 else 0
-        cpg = C // G
-        if not lps or lps & (lps - 1) or lps > 64 or cpg % cpl or (cpg // cpl) & (cpg // cpl - 1):
-            continue
-        for w in WAVES:
-            out.append({"waves_per_anchor": w, "chans_per_lane": cpl})
+    for order in orders:
+        for cpl in CPL[dtype]:
+            lps = C // cpl if C % cpl == 0 else 0
+            cpg = C // G
+            if (not lps or lps & (lps - 1) or lps > 64 or cpg % cpl or
+                    (cpg // cpl) & (cpg // cpl - 1)):
+                continue
+            for w in WAVES:
+                out.append({"waves_per_anchor": w, "chans_per_lane": cpl, "order": order})
     return out
 
 
@@ -176,7 +182,7 @@ def tune_batch(batch, reps: int = 3, save: bool = True, path: Optional[str] = No
     ref = [t.clone() for t in batch.out + [g for g in batch.grad_feat if g is not None]]
     best = None
     tol = 1e-2 if batch.dtype == torch.bfloat16 else 1e-4
-    for t in candidates(batch.dtype, batch.C, batch.G):
+    for t in candidates(batch.dtype, batch.C, batch.G, orders=("anchor",)):
         batch.set_tile(t)
         batch.forward()
         batch.backward()

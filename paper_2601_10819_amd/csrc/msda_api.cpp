@@ -126,8 +126,20 @@ msda_status check_regions(const msda_desc* d, int64_t* batch_bytes_out) {
     return MSDA_OK;
 }
 
-// Validates everything and chooses the launch shape; fills `a` except pointers.
-msda_status prepare(const msda_desc* d, msda::OpArgs* a, int* cpl_out, int* waves_out) {
+// The gathers' work order: explicit, else view order once there are at
+// least kSlots (batch item, camera) views to spread over the XCDs. A
+// forward without a workspace always runs in anchor order.
+int resolve_order(const msda_desc* d, bool can_view) {
+    const int o = d->tile ? d->tile->order : MSDA_ORDER_AUTO;
+    if (o != MSDA_ORDER_AUTO) return o;
+    const int64_t views = (int64_t)d->batch * d->num_cams;
+    return can_view && views >= msda::kSlots ? MSDA_ORDER_VIEW : MSDA_ORDER_ANCHOR;
+}
+
+// Validates everything and chooses the launch shape for the given order;
+// fills `a` except pointers.
+msda_status prepare(const msda_desc* d, int order, msda::OpArgs* a, int* cpl_out,
+                    int* waves_out) {
     int64_t batch_bytes = 0;
     msda_status st = check_regions(d, &batch_bytes);
     if (st != MSDA_OK) return st;
@@ -146,8 +158,8 @@ msda_status prepare(const msda_desc* d, msda::OpArgs* a, int* cpl_out, int* wave
                         "C/G/k a power of two for k in the dtype's lane widths",
                         d->channels, d->groups);
     }
-    if (d->tile && d->tile->anchors_per_block > 1)
-        return fail(MSDA_ERR_UNSUPPORTED, "anchors_per_block > 1 is not implemented");
+    if (order != MSDA_ORDER_ANCHOR && order != MSDA_ORDER_VIEW)
+        return fail(MSDA_ERR_UNSUPPORTED, "unknown order %d", order);
 
     a->B = d->batch;
     a->N = d->num_cams;
@@ -168,6 +180,8 @@ msda_status prepare(const msda_desc* d, msda::OpArgs* a, int* cpl_out, int* wave
         waves = d->tile->waves_per_anchor;
         if (!is_pow2(waves) || waves > 8)
             return fail(MSDA_ERR_UNSUPPORTED, "waves_per_anchor=%d not in {1,2,4,8}", waves);
+    } else if (order == MSDA_ORDER_VIEW) {
+        waves = 4;
     } else {
         // Aim for about 8 waves per SIMD across the chip (256 CUs x 4 SIMDs),
         // but no more waves than the anchor has staging chunks.
@@ -175,7 +189,13 @@ msda_status prepare(const msda_desc* d, msda::OpArgs* a, int* cpl_out, int* wave
         waves = 1;
         while (waves < 8 && blocks * waves * 2 <= 8192 && waves * 2 <= nchunks) waves *= 2;
     }
-    const size_t lds = msda::lds_bytes_for(*a, waves);
+    auto lds_of = [&](int w) {
+        return order == MSDA_ORDER_VIEW ? msda::lds_bytes_view(*a, w) : msda::lds_bytes_for(*a, w);
+    };
+    // a chosen (not requested) wave count shrinks until the staging fits
+    if (!(d->tile && d->tile->waves_per_anchor))
+        while (waves > 1 && lds_of(waves) > 65536) waves /= 2;
+    const size_t lds = lds_of(waves);
     if (lds > 65536)
         return fail(MSDA_ERR_UNSUPPORTED, "launch needs %zu bytes of LDS (limit 65536)", lds);
     *cpl_out = cpl;
@@ -325,18 +345,31 @@ const char* msda_recorded_kernel_name(int32_t i) {
 
 const char* msda_last_error(void) { return g_error.c_str(); }
 
-msda_status msda_forward(const void* feat, const int32_t* spatial_shapes,
-                         const int32_t* level_start_index, const float* sampling_loc,
-                         const float* weights, float* out, const msda_desc* desc, void* stream) {
+// Shared body of msda_forward / msda_forward_ws.
+static msda_status forward_impl(const void* feat, const int32_t* spatial_shapes,
+                                const int32_t* level_start_index, const float* sampling_loc,
+                                const float* weights, float* out, void* workspace,
+                                size_t workspace_bytes, bool has_ws, const msda_desc* desc,
+                                void* stream) {
+    if (!desc) return fail(MSDA_ERR_INVALID_ARGUMENT, "desc is NULL");
+    const int order = resolve_order(desc, has_ws);
+    if (order == MSDA_ORDER_VIEW && !has_ws)
+        return fail(MSDA_ERR_WORKSPACE, "the view-order forward needs a workspace "
+                                        "(msda_forward_ws)");
     msda::OpArgs a = {};
     int cpl = 0, waves = 0;
-    msda_status st = prepare(desc, &a, &cpl, &waves);
+    msda_status st = prepare(desc, order, &a, &cpl, &waves);
     if (st != MSDA_OK) return st;
     // sampling_loc, weights and out hold zero elements when A == 0 and may be NULL then
     if (!feat || !spatial_shapes || !level_start_index ||
         (a.A > 0 && (!sampling_loc || !weights || !out)))
         return fail(MSDA_ERR_INVALID_ARGUMENT, "a required device pointer is NULL");
     if (!aligned(feat, 16)) return fail(MSDA_ERR_UNSUPPORTED, "feat must be 16-byte aligned");
+    const size_t need = order == MSDA_ORDER_VIEW
+                            ? (size_t)msda::kSlots * a.B * a.A * a.C * sizeof(float) : 0;
+    if (need && (!workspace || workspace_bytes < need || !aligned(workspace, 256)))
+        return fail(MSDA_ERR_WORKSPACE, "forward workspace: need %zu bytes, 256-byte aligned "
+                                        "(got %zu at %p)", need, workspace_bytes, workspace);
     if (a.A == 0) return ok();
     a.feat = feat;
     a.shapes = spatial_shapes;
@@ -345,10 +378,45 @@ msda_status msda_forward(const void* feat, const int32_t* spatial_shapes,
     a.w = weights;
     a.level_scale = desc->feat_dtype == MSDA_FP8_E4M3 ? desc->level_scale : nullptr;
     a.out = out;
-    const hipError_t e = msda::launch_forward(a, desc->feat_dtype, cpl, waves,
-                                              msda::lds_bytes_for(a, waves), (hipStream_t)stream);
+    const hipError_t e =
+        order == MSDA_ORDER_VIEW
+            ? msda::launch_forward_view(a, desc->feat_dtype, cpl, waves,
+                                        msda::lds_bytes_view(a, waves),
+                                        static_cast<float*>(workspace), (hipStream_t)stream)
+            : msda::launch_forward(a, desc->feat_dtype, cpl, waves, msda::lds_bytes_for(a, waves),
+                                   (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "msda_forward launch");
     return ok();
+}
+
+msda_status msda_forward(const void* feat, const int32_t* spatial_shapes,
+                         const int32_t* level_start_index, const float* sampling_loc,
+                         const float* weights, float* out, const msda_desc* desc, void* stream) {
+    return forward_impl(feat, spatial_shapes, level_start_index, sampling_loc, weights, out,
+                        nullptr, 0, false, desc, stream);
+}
+
+msda_status msda_forward_ws(const void* feat, const int32_t* spatial_shapes,
+                            const int32_t* level_start_index, const float* sampling_loc,
+                            const float* weights, float* out, void* workspace,
+                            size_t workspace_bytes, const msda_desc* desc, void* stream) {
+    return forward_impl(feat, spatial_shapes, level_start_index, sampling_loc, weights, out,
+                        workspace, workspace_bytes, true, desc, stream);
+}
+
+size_t msda_forward_workspace_size(const msda_desc* d) {
+    if (!d || d->batch < 1 || d->num_cams < 1 || d->channels < 1 || d->num_anchors < 0) return 0;
+    if (resolve_order(d, true) != MSDA_ORDER_VIEW) return 0;
+    return (size_t)msda::kSlots * (size_t)d->batch * (size_t)d->num_anchors *
+           (size_t)d->channels * sizeof(float);
+}
+
+// The backward gather in the chosen order.
+static hipError_t launch_gather(const msda::OpArgs& a, int order, int dtype, int cpl, int waves,
+                                hipStream_t s) {
+    if (order == MSDA_ORDER_VIEW)
+        return msda::launch_backward_view(a, dtype, cpl, waves, msda::lds_bytes_view(a, waves), s);
+    return msda::launch_backward(a, dtype, cpl, waves, msda::lds_bytes_for(a, waves), s);
 }
 
 size_t msda_backward_workspace_size(const msda_desc* d) {
@@ -370,9 +438,11 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
                           const float* weights, const float* grad_out, void* grad_feat,
                           float* grad_sampling_loc, float* grad_weights, void* workspace,
                           size_t workspace_bytes, const msda_desc* desc, void* stream) {
+    if (!desc) return fail(MSDA_ERR_INVALID_ARGUMENT, "desc is NULL");
+    const int order = resolve_order(desc, true);
     msda::OpArgs a = {};
     int cpl = 0, waves = 0;
-    msda_status st = prepare(desc, &a, &cpl, &waves);
+    msda_status st = prepare(desc, order, &a, &cpl, &waves);
     if (st != MSDA_OK) return st;
     // sampling_loc, weights and grad_out hold zero elements when A == 0 and may be NULL then
     if (!feat || !spatial_shapes || !level_start_index ||
@@ -442,9 +512,8 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
         if ((e = msda::launch_fill_zero(acc, gf_elems * sizeof(float), s)) != hipSuccess)
             return hip_fail(e, "zero grad_feat accumulator");
         a.gfeat_acc = acc;
-        if (a.A > 0 &&
-            (e = msda::launch_backward(a, desc->feat_dtype, cpl, waves,
-                                       msda::lds_bytes_for(a, waves), s)) != hipSuccess)
+        if (a.A > 0 && (e = launch_gather(a, order, desc->feat_dtype, cpl, waves, s)) !=
+                           hipSuccess)
             return hip_fail(e, "msda_backward launch");
         if (desc->feat_dtype == MSDA_BF16 &&
             (e = msda::launch_f32_to_bf16(acc, static_cast<uint16_t*>(grad_feat), gf_elems, s)) !=
@@ -475,8 +544,7 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
             return hip_fail(e, "zero grad_feat");
     }
     if (a.A > 0 && (grad_feat || grad_sampling_loc || grad_weights) &&
-        (e = msda::launch_backward(a, desc->feat_dtype, cpl, waves, msda::lds_bytes_for(a, waves),
-                                   s)) != hipSuccess)
+        (e = launch_gather(a, order, desc->feat_dtype, cpl, waves, s)) != hipSuccess)
         return hip_fail(e, "msda_backward launch");
     if (!grad_feat) return ok();
 
@@ -697,7 +765,9 @@ msda_status plan_batch(const msda_batch* b, bool backward, BatchPlan* p) {
     d.host_spatial_shapes = shp.data();
     d.host_level_start_index = st.data();
     d.level_scale = b->level_scale;
-    msda_status stt = prepare(&d, &a, &p->cpl, &p->waves);
+    if (b->tile && b->tile->order == MSDA_ORDER_VIEW)
+        return fail(MSDA_ERR_UNSUPPORTED, "the batched form runs in anchor order only");
+    msda_status stt = prepare(&d, MSDA_ORDER_ANCHOR, &a, &p->cpl, &p->waves);
     if (stt != MSDA_OK) return stt;
     return MSDA_OK;
 }

@@ -33,131 +33,186 @@
 
 namespace msda {
 
-// The backward gather of one anchor (index ba = b*A + a of `a`) by the
-// whole workgroup; the geometry of `a` is already staged in geo.
-template <class FT, int CPL>
-__device__ __forceinline__ void bwd_anchor(const OpArgs& a, const int ba, const Geo* geo,
-                                           float* work) {
-    using RowT = Row<FT, CPL>;
-    const int LG = a.L * a.G;
-    const int J = a.pairs_per_chunk;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    float* sw = work + wave * J * (LG + 2);
-    float* sl = sw + J * LG;
+// Per-anchor context of the backward gather: grad_out row in registers and
+// the anchor's output and record bases.
+struct BwdAnchor {
+    const float* gw;       // weights of the anchor [P*N][L*G]
+    const float* gl;       // locations [P*N][2]
+    float* gwout;          // grad_weights of the anchor (or nullptr)
+    float* glout;          // grad_sampling_loc of the anchor (or nullptr)
+    float* gacc;           // atomic grad_feat: FP32 accumulator row base + c0 (or nullptr)
+    RecordSink rec;        // sorted grad_feat records
+    rsrc_t feat;
+};
 
+template <class FT, int CPL>
+__device__ __forceinline__ BwdAnchor bwd_anchor_ctx(const OpArgs& a, int ba, const Lanes& q,
+                                                    float* go) {
     const int b = ba / a.A;
     const int npairs = a.P * a.N;
-    const float* gl = a.loc + (size_t)ba * npairs * 2;
-    const float* gw = a.w + (size_t)ba * npairs * LG;
+    const int LG = a.L * a.G;
+    BwdAnchor x;
+    x.gw = a.w + (size_t)ba * npairs * LG;
+    x.gl = a.loc + (size_t)ba * npairs * 2;
+    x.gwout = a.grad_w ? a.grad_w + (size_t)ba * npairs * LG : nullptr;
+    x.glout = a.grad_loc ? a.grad_loc + (size_t)ba * npairs * 2 : nullptr;
+    x.gacc = a.gfeat_acc ? a.gfeat_acc + (size_t)b * a.R * a.C + q.c0 : nullptr;
+    x.rec.key = a.rec_key;
+    x.rec.frac = a.rec_frac;
+    x.rec.base = a.sample_offset + (u32)ba * (u32)npairs * (u32)a.L;
+    x.rec.cell_base = a.cell_offset + (u32)b * a.cells_per_item;
+    x.rec.no_cell = a.no_cell;
+    x.feat = make_rsrc(static_cast<const char*>(a.feat) + (size_t)b * a.batch_bytes,
+                       a.batch_bytes);
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) go[i] = a.grad_out[(size_t)ba * a.C + q.c0 + i];
+    return x;
+}
 
-    const int lps = 1 << a.lps_shift;
-    const int spw = 64 >> a.lps_shift;
-    const int sub = lane >> a.lps_shift;
-    const int sl_lane = lane & (lps - 1);          // lane within the sample
-    const int c0 = sl_lane * CPL;
-    const int cpg = a.C / a.G;
-    const int g = c0 / cpg;
-    const int lpg = cpg / CPL;                     // lanes of one group (a power of two)
-    const u32 row_bytes = (u32)a.C * FT::kBytes;
-    const u32 lane_off = (u32)c0 * FT::kBytes;
-    const rsrc_t feat = make_rsrc(static_cast<const char*>(a.feat) + (size_t)b * a.batch_bytes,
-                                  a.batch_bytes);
-
-    float go[CPL];
-#pragma unroll
-    for (int i = 0; i < CPL; ++i) go[i] = a.grad_out[(size_t)ba * a.C + c0 + i];
-    float* gacc = a.gfeat_acc ? a.gfeat_acc + (size_t)b * a.R * a.C + c0 : nullptr;
-    float* gwout = a.grad_w ? a.grad_w + (size_t)ba * npairs * LG : nullptr;
-    float* glout = a.grad_loc ? a.grad_loc + (size_t)ba * npairs * 2 : nullptr;
-    const bool need_vals = gwout || glout;
-    const u32 cell_base = a.cell_offset + (u32)b * a.cells_per_item;  // this item's first cell
-    const u32 no_cell = a.no_cell;                 // key of a sample outside its level
-
-    const int nchunks = (npairs + J - 1) / J;
-    for (int k = wave; k < nchunks; k += nwaves) {
-        const int j0 = k * J;
-        const int nj = min(J, npairs - j0);
-        stage_chunk(sw, sl, gw + (size_t)j0 * LG, gl + (size_t)j0 * 2, nj, LG, lane);
-        for (int jj = sub; jj < nj; jj += spw) {
-            const int j = j0 + jj;
-            const int n = j % a.N;
-            const float u = sl[2 * jj], v = sl[2 * jj + 1];
-            const float* wj = sw + jj * LG + g;
-            float gx = 0.f, gy = 0.f;
-            for (int l = 0; l < a.L; ++l) {
-                const Geo gm = geo[n * a.L + l];
-                const Corners cr = corners_of(u, v, gm, row_bytes, lane_off);
-                const float wl = wj[l * a.G];
-                if (a.rec_key && sl_lane == 0) {
-                    // the sample's record: its bilinear cell and fractions
-                    const u32 sidx = a.sample_offset + (u32)(ba * npairs + j) * (u32)a.L + (u32)l;
-                    a.rec_key[sidx] = cr.valid ? cell_base + gm.cstart +
-                                                     (u32)(cr.y0 + 1) * (u32)(gm.W + 1) +
-                                                     (u32)(cr.x0 + 1)
-                                               : no_cell;
-                    a.rec_frac[sidx] = make_float2(cr.lx, cr.ly);
-                }
-                if (gacc) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        if (cr.row[c] >= 0) {
-                            float* dst = gacc + (size_t)cr.row[c] * a.C;
-                            const float cwl = cr.cw[c] * wl;
-#pragma unroll
-                            for (int i = 0; i < CPL; ++i) unsafeAtomicAdd(dst + i, cwl * go[i]);
-                        }
-                    }
-                }
-                if (!need_vals) continue;
-                u32 raw[4][RowT::kWords];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) load_words<RowT::kWords>(feat, cr.off[c], raw[c]);
-                // d[c] = <grad_out, corner c> over this lane's channels
-                float d[4];
+// The gradients of one staged chunk of nj pairs. Per sample it re-gathers
+// the 4 corners and forms d[c] = <grad_out, corner c> over the lane's
+// channels; grad_w is a shuffle reduction over the group's lanes, grad_loc
+// one over the sample's lanes per pair; the atomic grad_feat form adds
+// w * cw * grad_out into the FP32 accumulator.
+template <class FT, int CPL>
+__device__ __forceinline__ void bwd_chunk(const OpArgs& a, const StageSlot& st, int nj,
+                                          const Geo* geo, const Lanes& q, const BwdAnchor& x,
+                                          const float* go) {
+    using RowT = Row<FT, CPL>;
+    const int L = a.L, G = a.G, LG = L * G;
+    const int lpg = (a.C / a.G) / CPL;             // lanes of one group (a power of two)
+    const bool need_vals = x.gwout || x.glout;
+    // byte offset of a row -> float offset in the FP32 accumulator
+    constexpr int kOffToAcc = FT::kBytes == 4 ? 2 : FT::kBytes == 2 ? 1 : 0;
+    for (int jj = q.sub; jj < nj; jj += q.spw) {
+        const u32 src = st.src[jj];
+        const int n = (int)st.cam[jj];
+        const float* wj = st.w + jj * LG + q.g;
+        const Taps* tj = st.taps + jj * L;
+        const float2* fj = st.frac + jj * L;
+        float gx = 0.f, gy = 0.f;
+        for (int l = 0; l < L; ++l) {
+            const Taps t = tj[l];
+            const float wl = wj[l * G];
+            if (x.gacc) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    float f[CPL];
-                    widen<FT, CPL>(raw[c], f);
-                    float sum = 0.f;
+                    if (t.off[c] != kOOB) {
+                        float* dst = x.gacc + (t.off[c] >> kOffToAcc);
+                        const float cwl = t.cw[c] * wl;
 #pragma unroll
-                    for (int i = 0; i < CPL; ++i) sum = fmaf(go[i], f[i], sum);
-                    d[c] = sum;
+                        for (int i = 0; i < CPL; ++i) unsafeAtomicAdd(dst + i, cwl * go[i]);
+                    }
                 }
-                if (gwout) {
-                    float t = cr.cw[0] * d[0] + cr.cw[1] * d[1] + cr.cw[2] * d[2] +
-                              cr.cw[3] * d[3];
-                    for (int sft = 1; sft < lpg; sft <<= 1) t += xor_shuffle(t, sft);
-                    if ((lane & (lpg - 1)) == 0) gwout[(size_t)j * LG + l * a.G + g] = t;
-                }
-                // d val / dx = hy (F01 - F00) + ly (F11 - F10); x = u W - 0.5
-                const float hx = 1.f - cr.lx, hy = 1.f - cr.ly;
-                gx += (float)gm.W * wl * (hy * (d[1] - d[0]) + cr.ly * (d[3] - d[2]));
-                gy += (float)gm.H * wl * (hx * (d[2] - d[0]) + cr.lx * (d[3] - d[1]));
             }
-            if (glout) {
-                for (int s = 1; s < lps; s <<= 1) {
-                    gx += xor_shuffle(gx, s);
-                    gy += xor_shuffle(gy, s);
-                }
-                if (sl_lane == 0) {
-                    glout[(size_t)j * 2] = gx;
-                    glout[(size_t)j * 2 + 1] = gy;
-                }
+            if (!need_vals) continue;
+            u32 raw[4][RowT::kWords];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                load_words<RowT::kWords>(x.feat, t.off[c] + q.lane_off, raw[c]);
+            float d[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                float f[CPL];
+                widen<FT, CPL>(raw[c], f);
+                float sum = 0.f;
+#pragma unroll
+                for (int i = 0; i < CPL; ++i) sum = fmaf(go[i], f[i], sum);
+                d[c] = sum;
+            }
+            if (x.gwout) {
+                float tw = t.cw[0] * d[0] + t.cw[1] * d[1] + t.cw[2] * d[2] + t.cw[3] * d[3];
+                for (int sft = 1; sft < lpg; sft <<= 1) tw += xor_shuffle(tw, sft);
+                if ((q.lane & (lpg - 1)) == 0) x.gwout[(size_t)src * LG + l * G + q.g] = tw;
+            }
+            // d val / dx = hy (F01 - F00) + ly (F11 - F10); x = u W - 0.5
+            const Geo gm = geo[n * L + l];
+            const float2 fr = fj[l];
+            const float hx = 1.f - fr.x, hy = 1.f - fr.y;
+            gx += (float)gm.W * wl * (hy * (d[1] - d[0]) + fr.y * (d[3] - d[2]));
+            gy += (float)gm.H * wl * (hx * (d[2] - d[0]) + fr.x * (d[3] - d[1]));
+        }
+        if (x.glout) {
+            for (int s = 1; s < q.lps; s <<= 1) {
+                gx += xor_shuffle(gx, s);
+                gy += xor_shuffle(gy, s);
+            }
+            if ((q.lane & (q.lps - 1)) == 0) {
+                x.glout[(size_t)src * 2] = gx;
+                x.glout[(size_t)src * 2 + 1] = gy;
             }
         }
+    }
+}
+
+// The backward gather of one anchor (index ba = b*A + a of `a`) by the
+// whole workgroup in anchor order; the geometry of `a` is already staged in
+// geo. The lane that stages a sample also writes its grad_feat record.
+template <class FT, int CPL>
+__device__ __forceinline__ void bwd_anchor(const OpArgs& a, const int ba, const Geo* geo,
+                                           unsigned char* work) {
+    const int J = a.pairs_per_chunk;
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const Lanes q = lanes_of<FT, CPL>(a);
+    const StageSlot st = stage_slot(work, wave, J, a.L, a.G);
+    float go[CPL];
+    const BwdAnchor x = bwd_anchor_ctx<FT, CPL>(a, ba, q, go);
+    const AnchorOrder order{a.N};
+    const int npairs = a.P * a.N;
+    const int nchunks = (npairs + J - 1) / J;
+    for (int k = wave; k < nchunks; k += nwaves) {
+        const int k0 = k * J;
+        const int nj = min(J, npairs - k0);
+        stage_chunk<false, true>(st, order, k0, nj, x.gw, x.gl, geo, a.L, a.L * a.G,
+                                 (u32)a.C * FT::kBytes, q.lane, x.rec);
+        bwd_chunk<FT, CPL>(a, st, nj, geo, q, x, go);
         end_chunk();
     }
-    (void)work;
 }
 
 template <class FT, int CPL>
 __global__ void __launch_bounds__(512) msda_bwd_kernel(OpArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     Geo* geo = reinterpret_cast<Geo*>(smem);
-    float* work = reinterpret_cast<float*>(smem + (size_t)a.N * a.L * sizeof(Geo));
+    unsigned char* work = smem + (size_t)a.N * a.L * sizeof(Geo);
     stage_geometry(geo, a);
     __syncthreads();
     bwd_anchor<FT, CPL>(a, (int)blockIdx.x, geo, work);
+}
+
+// View order (see slot_span): workgroup w serves slot w % kSlots, each wave
+// one row (an anchor over its views in the slot). Every output is per
+// sample or per pair, so the rows need no combining.
+template <class FT, int CPL>
+__global__ void __launch_bounds__(512) msda_bwd_view_kernel(OpArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    Geo* geo = reinterpret_cast<Geo*>(smem);
+    unsigned char* work = smem + (size_t)a.N * a.L * sizeof(Geo);
+    stage_geometry(geo, a);
+    __syncthreads();                       // the only block-wide barrier
+
+    const int xs = (int)(blockIdx.x % kSlots);
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int64_t r = (int64_t)(blockIdx.x / kSlots) * nwaves + wave;
+    const SlotSpan span = slot_span(xs, a.B, a.N, a.A);
+    if (r >= slot_rows(span, a.A)) return;
+    const ViewRow row = view_row(span, r, a.N, a.A);
+    if (row.nv == 0) return;
+
+    const int J = a.pairs_per_chunk;
+    const Lanes q = lanes_of<FT, CPL>(a);
+    const StageSlot st = stage_slot(work, wave, J, a.L, a.G);
+    float go[CPL];
+    const BwdAnchor x = bwd_anchor_ctx<FT, CPL>(a, row.b * a.A + row.a, q, go);
+    const ViewOrder order{a.N, a.P, row.n_lo};
+    const int nk = row.nv * a.P;
+    for (int k0 = 0; k0 < nk; k0 += J) {
+        const int nj = min(J, nk - k0);
+        stage_chunk<false, true>(st, order, k0, nj, x.gw, x.gl, geo, a.L, a.L * a.G,
+                                 (u32)a.C * FT::kBytes, q.lane, x.rec);
+        bwd_chunk<FT, CPL>(a, st, nj, geo, q, x, go);
+        end_chunk();
+    }
 }
 
 // Batched backward gather: persistent workgroups stride over the anchors of
@@ -166,7 +221,7 @@ template <class FT, int CPL>
 __global__ void __launch_bounds__(512) msda_bwd_batched_kernel(BatchArgs b) {
     extern __shared__ __align__(16) unsigned char smem[];
     Geo* geo = reinterpret_cast<Geo*>(smem);
-    float* work = reinterpret_cast<float*>(smem + (size_t)b.max_regions_per_scene * sizeof(Geo));
+    unsigned char* work = smem + (size_t)b.max_regions_per_scene * sizeof(Geo);
     for (u32 item = blockIdx.x; item < b.total_anchors; item += gridDim.x) {
         const int s = scene_of(b.t.anchor_start, b.S, item);
         const OpArgs a = scene_view(b, s, FT::kBytes);
@@ -632,6 +687,30 @@ hipError_t launch_backward(const OpArgs& a, int dtype, int cpl, int waves, size_
         case kBF16 * 100 + 2: return bwd_launch<TBF16, 2>(a, waves, lds, s);
         case kBF16 * 100 + 4: return bwd_launch<TBF16, 4>(a, waves, lds, s);
         case kBF16 * 100 + 8: return bwd_launch<TBF16, 8>(a, waves, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class FT, int CPL>
+static hipError_t bwd_view_launch(const OpArgs& a, int waves, size_t lds, hipStream_t s) {
+    const int64_t rows = max_slot_rows(a.B, a.N, a.A);
+    const unsigned blocks = (unsigned)(kSlots * ((rows + waves - 1) / waves));
+    mark_begin("msda_bwd_view_kernel", s);
+    hipLaunchKernelGGL((msda_bwd_view_kernel<FT, CPL>), dim3(blocks), dim3(64 * waves), lds, s,
+                       a);
+    mark_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward_view(const OpArgs& a, int dtype, int cpl, int waves, size_t lds,
+                                hipStream_t s) {
+    switch (dtype * 100 + cpl) {
+        case kF32 * 100 + 1: return bwd_view_launch<TF32, 1>(a, waves, lds, s);
+        case kF32 * 100 + 2: return bwd_view_launch<TF32, 2>(a, waves, lds, s);
+        case kF32 * 100 + 4: return bwd_view_launch<TF32, 4>(a, waves, lds, s);
+        case kBF16 * 100 + 2: return bwd_view_launch<TBF16, 2>(a, waves, lds, s);
+        case kBF16 * 100 + 4: return bwd_view_launch<TBF16, 4>(a, waves, lds, s);
+        case kBF16 * 100 + 8: return bwd_view_launch<TBF16, 8>(a, waves, lds, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -200,30 +200,159 @@ __device__ __forceinline__ float xor_shuffle(float v, int mask) {
 // Per-lane registers' worth of weights staged per wave step.
 constexpr int kStageWords = 8;
 
-// Copy one chunk of nj pairs' weights (nj*LG floats) and locations (nj*2)
-// into this wave's LDS slot; both are contiguous in global memory.
-__device__ __forceinline__ void stage_chunk(float* sw, float* sl, const float* gw,
-                                            const float* gl, int nj, int LG, int lane) {
-    const int nw = nj * LG;
-#pragma unroll
-    for (int t = 0; t < kStageWords; ++t) {
-        const int i = t * 64 + lane;
-        if (i < nw) sw[i] = gw[i];
-    }
-    if (lane < 2 * nj) sl[lane] = gl[lane];
-    // LDS accesses of one wave are performed in program order; the fences
-    // keep the compiler from moving the reads that follow above the writes.
+// The 4 corner taps of one sample as staged in LDS: byte offsets of the
+// corner rows within the batch item (kOOB outside; each lane adds its own
+// channel offset) and the bilinear weights (times the FP8 level scale).
+struct alignas(16) Taps { u32 off[4]; float cw[4]; };
+
+__host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// One wave's LDS staging slot for a chunk of up to J (keypoint, camera)
+// pairs of one anchor: per pair its index p*N + n among the anchor's pairs
+// and its camera, its L*G weights, and the taps and bilinear fractions of
+// its L samples.
+struct StageSlot {
+    u32* src;
+    u32* cam;
+    float* w;
+    Taps* taps;
+    float2* frac;
+};
+
+// Every part starts 16-byte aligned (taps are read as 16-byte words), and so
+// does every wave's slot.
+__host__ __device__ constexpr size_t wave_stage_bytes(int J, int L, int G) {
+    return align16((size_t)J * 8) + align16((size_t)J * L * G * 4) +
+           (size_t)J * L * sizeof(Taps) + align16((size_t)J * L * sizeof(float2));
+}
+
+__device__ __forceinline__ StageSlot stage_slot(unsigned char* work, int wave, int J, int L,
+                                                int G) {
+    unsigned char* p = work + (size_t)wave * wave_stage_bytes(J, L, G);
+    StageSlot s;
+    s.src = reinterpret_cast<u32*>(p);
+    s.cam = s.src + J;
+    p += align16((size_t)J * 8);
+    s.w = reinterpret_cast<float*>(p);
+    p += align16((size_t)J * L * G * 4);
+    s.taps = reinterpret_cast<Taps*>(p);
+    s.frac = reinterpret_cast<float2*>(s.taps + (size_t)J * L);
+    return s;
+}
+
+// Makes this wave's LDS writes visible to its later reads: LDS accesses of
+// one wave are performed in program order; the fences keep the compiler
+// from moving the reads that follow above the writes.
+__device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Ends a chunk: the next stage_chunk may overwrite the slot.
-__device__ __forceinline__ void end_chunk() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Pair orders: the k-th pair a wave processes -> (index p*N + n, camera n).
+// Anchor order walks the anchor's pairs as stored (keypoint-major); view
+// order walks cameras [n_lo, n_lo + nv) one after the other, every
+// keypoint of a camera before the next camera.
+struct AnchorOrder {
+    int N;
+    __device__ __forceinline__ void operator()(int k, u32* src, u32* cam) const {
+        *src = (u32)k;
+        *cam = (u32)(k % N);
+    }
+};
+
+struct ViewOrder {
+    int N, P, n_lo;
+    __device__ __forceinline__ void operator()(int k, u32* src, u32* cam) const {
+        const int q = k / P, p = k - q * P;
+        *cam = (u32)(n_lo + q);
+        *src = (u32)(p * N + n_lo + q);
+    }
+};
+
+// Where the backward writes its grad_feat records (key = bilinear cell,
+// frac = (lx, ly)) while staging: record of (pair src, level l) at
+// base + src*L + l. key == nullptr: none.
+struct RecordSink {
+    u32* key;
+    float2* frac;
+    u32 base;            // first record of the anchor
+    u32 cell_base;       // first cell of the batch item
+    u32 no_cell;         // key of a sample outside its level
+};
+
+// Stages pairs [k0, k0 + nj) (in the wave's pair order) of the anchor whose
+// weights / locations start at gw / gl: pair table, weights (coalesced
+// within each pair's L*G run), and one sample's taps per lane. Ends with
+// the slot readable by the whole wave.
+template <bool SCALE_TAPS, bool FRACS, class Order>
+__device__ __forceinline__ void stage_chunk(const StageSlot& s, const Order& order, int k0, int nj,
+                                            const float* gw, const float* gl, const Geo* geo,
+                                            int L, int LG, u32 row_bytes, int lane,
+                                            const RecordSink& rec) {
+    if (lane < nj) {
+        u32 src, cam;
+        order(k0 + lane, &src, &cam);
+        s.src[lane] = src;
+        s.cam[lane] = cam;
+    }
+    wave_lds_sync();
+    const int nw = nj * LG;
+#pragma unroll
+    for (int t = 0; t < kStageWords; ++t) {
+        const int i = t * 64 + lane;
+        if (i < nw) {
+            const int jj = i / LG;
+            s.w[i] = gw[(size_t)s.src[jj] * LG + (i - jj * LG)];
+        }
+    }
+    for (int i = lane; i < nj * L; i += 64) {
+        const int jj = i / L, l = i - jj * L;
+        const u32 src = s.src[jj];
+        const Geo gm = geo[s.cam[jj] * L + l];
+        const Corners cr = corners_of(gl[2 * src], gl[2 * src + 1], gm, row_bytes, 0u);
+        Taps t;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            t.off[c] = cr.off[c];
+            t.cw[c] = SCALE_TAPS ? cr.cw[c] * gm.scale : cr.cw[c];
+        }
+        s.taps[i] = t;
+        if constexpr (FRACS) {
+            s.frac[i] = make_float2(cr.lx, cr.ly);
+            if (rec.key) {
+                const u32 r = rec.base + src * (u32)L + (u32)l;
+                rec.key[r] = cr.valid ? rec.cell_base + gm.cstart +
+                                            (u32)(cr.y0 + 1) * (u32)(gm.W + 1) + (u32)(cr.x0 + 1)
+                                      : rec.no_cell;
+                rec.frac[r] = make_float2(cr.lx, cr.ly);
+            }
+        }
+    }
+    wave_lds_sync();
 }
+
+// Lane layout of one wave: CPL channels per lane, C/CPL lanes per sample.
+struct Lanes {
+    int lane, lps, spw, sub, c0, g;
+    u32 lane_off;
+};
+
+template <class FT, int CPL>
+__device__ __forceinline__ Lanes lanes_of(const OpArgs& a) {
+    Lanes q;
+    q.lane = threadIdx.x & 63;
+    q.lps = 1 << a.lps_shift;
+    q.spw = 64 >> a.lps_shift;
+    q.sub = q.lane >> a.lps_shift;
+    q.c0 = (q.lane & (q.lps - 1)) * CPL;
+    q.g = q.c0 / (a.C / a.G);
+    q.lane_off = (u32)q.c0 * FT::kBytes;
+    return q;
+}
+
+// Ends a chunk: the next staging may overwrite the slot.
+__device__ __forceinline__ void end_chunk() { wave_lds_sync(); }
 
 // Inclusive scan across the 256 threads of a block (4 waves); returns the
 // thread's inclusive sum and the block total in *total.

@@ -110,11 +110,86 @@ struct BatchArgs {
 
 enum FeatType { kF32 = 0, kBF16 = 1, kFP8 = 2 };
 
+// ---------------------------------------------------------------- view order
+//
+// In view order the work of a call -- every (view, anchor) item, a view
+// being one (batch item, camera), P*L samples each -- is cut, view-major,
+// into kSlots contiguous ranges of equal size. Slot x runs on the workgroups
+// whose index is x modulo kSlots: the hardware hands workgroups to the
+// chip's kSlots XCDs round-robin, so slot x stays on one XCD and its L2
+// holds the pyramids of the few cameras the slot is working through instead
+// of every camera's. A wave takes one "row" of its slot: one anchor of a
+// batch item the slot touches, over the anchor's views inside the slot
+// (possibly none at the slot's edges).
+constexpr int kSlots = 8;
+
+struct SlotSpan {
+    int64_t lo, hi;               // items [lo, hi), item = (b*N + n)*A + a
+    int32_t b_first, b_last;      // batch items touched (b_last < b_first: none)
+};
+
+__host__ __device__ inline SlotSpan slot_span(int x, int B, int N, int A) {
+    const int64_t T = (int64_t)B * N * A;
+    SlotSpan s;
+    s.lo = T * x / kSlots;
+    s.hi = T * (x + 1) / kSlots;
+    if (s.hi <= s.lo) {
+        s.b_first = 1;
+        s.b_last = 0;
+    } else {
+        s.b_first = (int32_t)(s.lo / A / N);
+        s.b_last = (int32_t)((s.hi - 1) / A / N);
+    }
+    return s;
+}
+
+// Rows of slot x: (batch items touched) * A.
+__host__ __device__ inline int64_t slot_rows(const SlotSpan& s, int A) {
+    return s.b_last < s.b_first ? 0 : (int64_t)(s.b_last - s.b_first + 1) * A;
+}
+
+struct ViewRow {
+    int32_t b, a;                 // batch item and anchor
+    int32_t n_lo, nv;             // cameras [n_lo, n_lo + nv) of this row (nv may be 0)
+};
+
+// Row r (< slot_rows) of slot span s.
+__host__ __device__ inline ViewRow view_row(const SlotSpan& s, int64_t r, int N, int A) {
+    ViewRow v;
+    v.b = s.b_first + (int32_t)(r / A);
+    v.a = (int32_t)(r % A);
+    // items of anchor a lie at views v with v*A + a in [lo, hi)
+    int64_t v0 = (s.lo - v.a + A - 1) / A, v1 = (s.hi - v.a + A - 1) / A;
+    const int64_t first = (int64_t)v.b * N, last = first + N;
+    if (v0 < first) v0 = first;
+    if (v1 > last) v1 = last;
+    v.n_lo = (int32_t)(v0 - first);
+    v.nv = v1 > v0 ? (int32_t)(v1 - v0) : 0;
+    return v;
+}
+
+// The largest slot_rows over the slots (sizes the grid of a view launch).
+inline int64_t max_slot_rows(int B, int N, int A) {
+    int64_t m = 0;
+    for (int x = 0; x < kSlots; ++x) {
+        const int64_t r = slot_rows(slot_span(x, B, N, A), A);
+        if (r > m) m = r;
+    }
+    return m;
+}
+
 // Launchers return hipSuccess or the launch error. They enqueue only.
 hipError_t launch_forward(const OpArgs& a, int dtype, int cpl, int waves, size_t lds_bytes,
                           hipStream_t s);
 hipError_t launch_backward(const OpArgs& a, int dtype, int cpl, int waves, size_t lds_bytes,
                            hipStream_t s);
+// View order: `waves` waves per workgroup, each its own row. The forward
+// writes per-slot partial sums to part ([kSlots][B*A][C] FP32) and adds
+// them into out in slot order.
+hipError_t launch_forward_view(const OpArgs& a, int dtype, int cpl, int waves, size_t lds_bytes,
+                               float* part, hipStream_t s);
+hipError_t launch_backward_view(const OpArgs& a, int dtype, int cpl, int waves, size_t lds_bytes,
+                                hipStream_t s);
 hipError_t launch_gfeat_tiles(const TileArgs& t, int out_dtype, int cpl, hipStream_t s);
 // cell_start[N*L], tile_start[N*L + 1] and tile_region[N*L] from the shapes.
 hipError_t launch_region_tables(const int32_t* shapes, int32_t N, int32_t L, uint32_t* cell_start,
@@ -146,6 +221,8 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStrea
 // LDS bytes of a forward/backward launch: geometry table + per-wave staging
 // (or the cross-wave reduction area, whichever is larger).
 size_t lds_bytes_for(const OpArgs& a, int waves);
+// The same for a view-order launch (staging only).
+size_t lds_bytes_view(const OpArgs& a, int waves);
 int max_pairs_per_chunk(int L, int G);
 
 // Benchmark instrumentation (msda_set_kernel_events): called around every

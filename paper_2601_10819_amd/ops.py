@@ -64,6 +64,25 @@ def _need_cuda_contig(name, t, dtype=None):
         raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
 
 
+def _order_code(order) -> int:
+    if isinstance(order, str):
+        if order not in _lib.ORDERS:
+            raise ValueError(f"order must be one of {sorted(_lib.ORDERS)}, got {order!r}")
+        return _lib.ORDERS[order]
+    return int(order or 0)
+
+
+def tile_struct(tile: dict, into=None):
+    """msda_tile from a dict: waves_per_anchor, chans_per_lane, order
+    ("anchor", "view", "auto" or the MSDA_ORDER_* code), scatter."""
+    t = into if into is not None else _lib.MsdaTile()
+    t.waves_per_anchor = int(tile.get("waves_per_anchor", 0))
+    t.chans_per_lane = int(tile.get("chans_per_lane", 0))
+    t.order = _order_code(tile.get("order", 0))
+    t.scatter = int(tile.get("scatter", 0))
+    return t
+
+
 def make_desc(feat: torch.Tensor, layout: Layout, sampling_loc: torch.Tensor,
               weights: torch.Tensor, level_scale: Optional[torch.Tensor] = None,
               deterministic: bool = False, tile: Optional[dict] = None):
@@ -91,8 +110,7 @@ def make_desc(feat: torch.Tensor, layout: Layout, sampling_loc: torch.Tensor,
     d.flags = _lib.MSDA_DETERMINISTIC if deterministic else 0
     keep = [layout]
     if tile:
-        t = _lib.MsdaTile(int(tile.get("waves_per_anchor", 0)), int(tile.get("chans_per_lane", 0)),
-                          int(tile.get("anchors_per_block", 0)), int(tile.get("scatter", 0)))
+        t = tile_struct(tile)
         keep.append(t)
         d.tile = ctypes.pointer(t)
     d._keep = keep        # host arrays must outlive the call
@@ -112,10 +130,35 @@ def _resolve_tile(tile, which, feat, sampling_loc, weights):
     return entry.get(which) if entry else None
 
 
+def _workspace(nbytes: int, workspace: Optional[torch.Tensor], device):
+    """(pointer, usable bytes) of a 256-byte aligned workspace of at least
+    nbytes: the caller's tensor if large enough, else a new one."""
+    if not nbytes:
+        return None, 0, workspace
+
+    def usable(t):
+        base = t.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        return aligned, t.numel() * t.element_size() - (aligned - base)
+
+    if workspace is None or usable(workspace)[1] < nbytes:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    aligned, n = usable(workspace)
+    return ctypes.c_void_p(aligned), n, workspace
+
+
+def forward_workspace_bytes(feat, layout, sampling_loc, weights, tile=None) -> int:
+    d = make_desc(feat, layout, sampling_loc, weights, tile=tile)
+    return int(_lib.load().msda_forward_workspace_size(ctypes.byref(d)))
+
+
 def forward(feat, layout: Layout, sampling_loc, weights, level_scale=None, tile=None,
-            out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+            out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+            stream=None) -> torch.Tensor:
     """out [B, A, C] FP32 = MSDA(feat, loc, weights) on the current stream.
-    tile: None (the library's choice), a dict of msda_tile fields, or "auto"."""
+    tile: None (the library's choice), a dict of msda_tile fields, or "auto".
+    workspace: optional uint8 device tensor for the view-order forward (one
+    is allocated when needed and not given)."""
     lib = _lib.load()
     tile = _resolve_tile(tile, "forward", feat, sampling_loc, weights)
     _need_cuda_contig("feat", feat)
@@ -127,9 +170,11 @@ def forward(feat, layout: Layout, sampling_loc, weights, level_scale=None, tile=
     if out is None:
         out = torch.empty(d.batch, d.num_anchors, d.channels, device=feat.device,
                           dtype=torch.float32)
-    _lib.check(lib.msda_forward(_ptr(feat), _ptr(layout.shapes), _ptr(layout.starts),
-                                _ptr(sampling_loc), _ptr(weights), _ptr(out), ctypes.byref(d),
-                                _stream(stream)))
+    ws_ptr, ws_len, workspace = _workspace(int(lib.msda_forward_workspace_size(ctypes.byref(d))),
+                                           workspace, feat.device)
+    _lib.check(lib.msda_forward_ws(_ptr(feat), _ptr(layout.shapes), _ptr(layout.starts),
+                                   _ptr(sampling_loc), _ptr(weights), _ptr(out), ws_ptr, ws_len,
+                                   ctypes.byref(d), _stream(stream)))
     return out
 
 
@@ -156,14 +201,7 @@ def backward(feat, layout: Layout, sampling_loc, weights, grad_out,
     gl = torch.empty_like(sampling_loc) if need_loc else None
     gw = torch.empty_like(weights) if need_w else None
     ws_bytes = int(lib.msda_backward_workspace_size(ctypes.byref(d))) if need_feat else 0
-    if ws_bytes and (workspace is None or workspace.numel() * workspace.element_size() < ws_bytes):
-        workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=feat.device)
-    ws_ptr, ws_len = None, 0
-    if workspace is not None and ws_bytes:
-        base = workspace.data_ptr()
-        aligned = (base + 255) // 256 * 256
-        ws_ptr = ctypes.c_void_p(aligned)
-        ws_len = workspace.numel() * workspace.element_size() - (aligned - base)
+    ws_ptr, ws_len, workspace = _workspace(ws_bytes, workspace, feat.device)
     _lib.check(lib.msda_backward(_ptr(feat), _ptr(layout.shapes), _ptr(layout.starts),
                                  _ptr(sampling_loc), _ptr(weights), _ptr(grad_out), _ptr(gf),
                                  _ptr(gl), _ptr(gw), ws_ptr, ws_len, ctypes.byref(d),
@@ -332,11 +370,7 @@ class SceneBatch:
     def set_tile(self, tile: Optional[dict]):
         """Launch shape of later calls: None for the library's choice."""
         if tile:
-            t = self._tile
-            t.waves_per_anchor = int(tile.get("waves_per_anchor", 0))
-            t.chans_per_lane = int(tile.get("chans_per_lane", 0))
-            t.anchors_per_block = int(tile.get("anchors_per_block", 0))
-            t.scatter = int(tile.get("scatter", 0))
+            tile_struct(tile, self._tile)
             self._batch.tile = ctypes.pointer(self._tile)
         else:
             self._batch.tile = None

@@ -135,7 +135,7 @@ def test_unsupported_requests(lib):
     expect(lib, fwd(lib, desc(Geo()), feat=FAKE + 4), UNS, "aligned")
     expect(lib, fwd(lib, desc(Geo(), tile=(3, 0, 0, 0))), UNS, "waves_per_anchor")
     expect(lib, fwd(lib, desc(Geo(), tile=(0, 16, 0, 0))), UNS, "chans_per_lane")
-    expect(lib, fwd(lib, desc(Geo(), tile=(0, 0, 2, 0))), UNS, "anchors_per_block")
+    expect(lib, fwd(lib, desc(Geo(), tile=(0, 0, 5, 0))), UNS, "order")
     # one batch item beyond 2^31 bytes of features
     g = Geo(ncam=1, levels=((4096, 4096),))
     expect(lib, fwd(lib, desc(g, C=64, G=4)), UNS, "bytes")
@@ -265,3 +265,70 @@ def test_batched_validation(lib):
     t = _lib.MsdaTile(0, 0, 0, _lib.MSDA_SCATTER_ATOMIC)
     b.tile = ctypes.pointer(t)
     expect(lib, lib.msda_backward_batched(ctypes.byref(b), FAKE, 1 << 30, None), UNS, "sorted")
+    # the batched form runs in anchor order
+    b = batch_desc(geos, [4, 7])
+    t = _lib.MsdaTile(0, 0, _lib.MSDA_ORDER_VIEW, 0)
+    b.tile = ctypes.pointer(t)
+    expect(lib, lib.msda_forward_batched(ctypes.byref(b), FAKE, 1 << 30, None), UNS, "anchor order")
+
+
+def fwd_ws(lib, d, ws=None, ws_bytes=0):
+    return lib.msda_forward_ws(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE + 4096, ws, ws_bytes,
+                               ctypes.byref(d), None)
+
+
+def test_view_order_forward_workspace(lib):
+    # 2 (batch item, camera) views: the library keeps anchor order, no workspace
+    d = desc(Geo(), A=4, C=32)
+    assert lib.msda_forward_workspace_size(ctypes.byref(d)) == 0
+    # 4 x 2 = 8 views: view order, 8 partial sums per (batch item, anchor)
+    d = desc(Geo(), B=4, A=4, C=32)
+    need = lib.msda_forward_workspace_size(ctypes.byref(d))
+    assert need == 8 * 4 * 4 * 32 * 4
+    expect(lib, fwd_ws(lib, d), WS, "workspace")
+    expect(lib, fwd_ws(lib, d, ws=FAKE + (1 << 20), ws_bytes=need - 4), WS)
+    expect(lib, fwd_ws(lib, d, ws=FAKE + (1 << 20) + 8, ws_bytes=need + 64), WS, "aligned")
+    # the plain forward cannot run in view order: asked for explicitly, it says why
+    d = desc(Geo(), tile=(0, 0, _lib.MSDA_ORDER_VIEW, 0))
+    expect(lib, fwd(lib, d), WS, "msda_forward_ws")
+    assert lib.msda_forward_workspace_size(ctypes.byref(d)) == 8 * 1 * 4 * 32 * 4
+    # anchor order asked for: no workspace whatever the view count
+    d = desc(Geo(), B=4, tile=(0, 0, _lib.MSDA_ORDER_ANCHOR, 0))
+    assert lib.msda_forward_workspace_size(ctypes.byref(d)) == 0
+    # empty anchor set in view order: validated, nothing launched
+    d = desc(Geo(), B=4, A=0)
+    assert lib.msda_forward_workspace_size(ctypes.byref(d)) == 0
+    assert lib.msda_forward_ws(FAKE, FAKE, FAKE, None, None, None, None, 0, ctypes.byref(d),
+                               None) == _lib.MSDA_OK
+
+
+def test_view_partition_covers_every_item_once():
+    """The slot / row partition of view order (mirrored from the C++ helpers
+    in csrc/msda_internal.h): every (batch item, anchor, camera) lands in
+    exactly one row of one slot, every row's cameras lie in [0, N), and the
+    slots' item counts differ by at most one."""
+    def span(x, B, N, A):
+        T = B * N * A
+        lo, hi = T * x // 8, T * (x + 1) // 8
+        if hi <= lo:
+            return lo, hi, 1, 0
+        return lo, hi, lo // A // N, (hi - 1) // A // N
+
+    for B, N, A in [(1, 64, 900), (2, 16, 1800), (1, 6, 900), (3, 7, 5), (2, 3, 1), (1, 1, 3)]:
+        seen = set()
+        sizes = []
+        for x in range(8):
+            lo, hi, bf, bl = span(x, B, N, A)
+            sizes.append(hi - lo)
+            rows = (bl - bf + 1) * A if bl >= bf else 0
+            for r in range(rows):
+                b, a = bf + r // A, r % A
+                v0, v1 = (lo - a + A - 1) // A, (hi - a + A - 1) // A
+                v0, v1 = max(v0, b * N), min(v1, (b + 1) * N)
+                for v in range(v0, v1):
+                    n = v - b * N
+                    assert 0 <= n < N and 0 <= b < B
+                    assert (b, a, n) not in seen
+                    seen.add((b, a, n))
+        assert len(seen) == B * N * A
+        assert max(sizes) - min(sizes) <= 1

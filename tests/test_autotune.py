@@ -21,10 +21,12 @@ def _accepted(lib, dtype_code, C, G, tile):
     d.host_spatial_shapes = ctypes.addressof(shapes)
     d.host_level_start_index = ctypes.addressof(starts)
     d.level_scale = FAKE if dtype_code == _lib.MSDA_FP8_E4M3 else None
-    t = _lib.MsdaTile(tile["waves_per_anchor"], tile["chans_per_lane"], 0, 0)
+    t = _lib.MsdaTile(tile["waves_per_anchor"], tile["chans_per_lane"],
+                      _lib.ORDERS[tile.get("order", "auto")], 0)
     d.tile = ctypes.pointer(t)
     # A = 0: validated, nothing launched
-    return lib.msda_forward(FAKE, FAKE, FAKE, None, None, None, ctypes.byref(d), None) == 0
+    return lib.msda_forward_ws(FAKE, FAKE, FAKE, None, None, None, None, 0, ctypes.byref(d),
+                               None) == 0
 
 
 @pytest.mark.parametrize("dtype,code", [(torch.float32, 0), (torch.bfloat16, 1),
@@ -35,8 +37,8 @@ def test_candidates_are_exactly_what_the_library_accepts(dtype, code, C, G):
     cands = autotune.candidates(dtype, C, G)
     for t in cands:
         assert _accepted(lib, code, C, G, t), t
-    every = [{"waves_per_anchor": w, "chans_per_lane": c} for w in (1, 2, 4, 8)
-             for c in (1, 2, 4, 8, 16)]
+    every = [{"waves_per_anchor": w, "chans_per_lane": c, "order": o} for w in (1, 2, 4, 8)
+             for c in (1, 2, 4, 8, 16) for o in ("anchor", "view")]
     for t in every:
         if t not in cands:
             assert not _accepted(lib, code, C, G, t), t
@@ -97,7 +99,7 @@ def test_tune_batch(tmp_path, monkeypatch):
                p.sampling_loc[0].cuda(), p.weights[0].cuda()) for p in probs]
     batch = ops.SceneBatch(scenes)
     res = autotune.tune_batch(batch, reps=2)
-    assert res["tile"] in autotune.candidates(torch.bfloat16, 256, 8)
+    assert res["tile"] in autotune.candidates(torch.bfloat16, 256, 8, orders=("anchor",))
     assert batch.tile == res["tile"]
     again = ops.SceneBatch(scenes, tile="auto")
     assert again.tile == res["tile"]

@@ -171,7 +171,8 @@ def test_sorted_grad_feat_is_bitwise_reproducible(ops, oracle_mod, dtype):
     feat, layout, loc, w = to_device(p, dtype)
     runs = []
     for tile in [None, {"waves_per_anchor": 1}, {"waves_per_anchor": 8},
-                 {"waves_per_anchor": 2, "chans_per_lane": 4}, None]:
+                 {"waves_per_anchor": 2, "chans_per_lane": 4}, {"order": "view"},
+                 {"order": "view", "waves_per_anchor": 8}, None]:
         gf, _, _ = ops.backward(feat, layout, loc, w, go, need_loc=False, need_w=False,
                                 tile=tile, deterministic=True)
         runs.append(gf)
