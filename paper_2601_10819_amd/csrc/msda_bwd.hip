@@ -88,8 +88,8 @@ __device__ __forceinline__ void bwd_chunk(const OpArgs& a, const StageSlot& st, 
         const u32 src = st.src[jj];
         const int n = (int)st.cam[jj];
         const float* wj = st.w + jj * LG + q.g;
-        const Taps* tj = st.taps + jj * L;
-        const float2* fj = st.frac + jj * L;
+        const Taps* tj = st.taps + jj * padded_levels(L);
+        const float2* fj = st.frac + jj * padded_levels(L);
         float gx = 0.f, gy = 0.f;
         for (int l = 0; l < L; ++l) {
             const Taps t = tj[l];
@@ -152,7 +152,7 @@ template <class FT, int CPL>
 __device__ __forceinline__ void bwd_anchor(const OpArgs& a, const int ba, const Geo* geo,
                                            unsigned char* work) {
     const int J = a.pairs_per_chunk;
-    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int wave = wave_index(), nwaves = blockDim.x >> 6;
     const Lanes q = lanes_of<FT, CPL>(a);
     const StageSlot st = stage_slot(work, wave, J, a.L, a.G);
     float go[CPL];
@@ -192,11 +192,16 @@ __global__ void __launch_bounds__(512) msda_bwd_view_kernel(OpArgs a) {
     __syncthreads();                       // the only block-wide barrier
 
     const int xs = (int)(blockIdx.x % kSlots);
-    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int wave = wave_index(), nwaves = blockDim.x >> 6;
     const int64_t r = (int64_t)(blockIdx.x / kSlots) * nwaves + wave;
     const SlotSpan span = slot_span(xs, a.B, a.N, a.A);
     if (r >= slot_rows(span, a.A)) return;
-    const ViewRow row = view_row(span, r, a.N, a.A);
+    ViewRow row = view_row(span, r, a.N, a.A);
+    // every field is the same across the wave (r is per wave)
+    row.b = uniform(row.b);
+    row.a = uniform(row.a);
+    row.n_lo = uniform(row.n_lo);
+    row.nv = uniform(row.nv);
     if (row.nv == 0) return;
 
     const int J = a.pairs_per_chunk;

@@ -193,6 +193,26 @@ __device__ __forceinline__ Corners corners_of(float u, float v, const Geo& g, u3
 
 // ---------------------------------------------------------------- lanes and LDS
 
+// Index of the calling wave in its workgroup, as a wave-uniform (scalar)
+// value: the compiler cannot see that threadIdx.x / 64 is the same for the
+// whole wave, and values derived from it (a batch item's buffer resource, a
+// loop bound) would otherwise live in vector registers -- a buffer load
+// with a per-lane resource becomes a loop over the distinct resources.
+__device__ __forceinline__ int wave_index() {
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
+// A value the caller knows to be the same in every lane, marked as such for
+// the compiler (it is then kept in scalar registers).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ const void* uniform(const void* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return reinterpret_cast<const void*>(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ float xor_shuffle(float v, int mask) {
     return __shfl_xor(v, mask, 64);
 }
@@ -219,11 +239,17 @@ struct StageSlot {
     float2* frac;
 };
 
+// Levels per pair in the staged taps: L rounded up to a multiple of 4, so the
+// forward issues the loads of 4 levels at a time without a branch (a padded
+// level's taps point outside the feature and weigh 0).
+__host__ __device__ constexpr int padded_levels(int L) { return (L + 3) & ~3; }
+
 // Every part starts 16-byte aligned (taps are read as 16-byte words), and so
 // does every wave's slot.
 __host__ __device__ constexpr size_t wave_stage_bytes(int J, int L, int G) {
     return align16((size_t)J * 8) + align16((size_t)J * L * G * 4) +
-           (size_t)J * L * sizeof(Taps) + align16((size_t)J * L * sizeof(float2));
+           (size_t)J * padded_levels(L) * sizeof(Taps) +
+           align16((size_t)J * padded_levels(L) * sizeof(float2));
 }
 
 __device__ __forceinline__ StageSlot stage_slot(unsigned char* work, int wave, int J, int L,
@@ -236,7 +262,7 @@ __device__ __forceinline__ StageSlot stage_slot(unsigned char* work, int wave, i
     s.w = reinterpret_cast<float*>(p);
     p += align16((size_t)J * L * G * 4);
     s.taps = reinterpret_cast<Taps*>(p);
-    s.frac = reinterpret_cast<float2*>(s.taps + (size_t)J * L);
+    s.frac = reinterpret_cast<float2*>(s.taps + (size_t)J * padded_levels(L));
     return s;
 }
 
@@ -306,12 +332,23 @@ __device__ __forceinline__ void stage_chunk(const StageSlot& s, const Order& ord
             s.w[i] = gw[(size_t)s.src[jj] * LG + (i - jj * LG)];
         }
     }
-    for (int i = lane; i < nj * L; i += 64) {
-        const int jj = i / L, l = i - jj * L;
+    const int Lp = padded_levels(L);
+    for (int i = lane; i < nj * Lp; i += 64) {
+        const int jj = i / Lp, l = i - jj * Lp;
+        Taps t;
+        if (l >= L) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                t.off[c] = kOOB;
+                t.cw[c] = 0.f;
+            }
+            s.taps[i] = t;
+            if constexpr (FRACS) s.frac[i] = make_float2(0.f, 0.f);
+            continue;
+        }
         const u32 src = s.src[jj];
         const Geo gm = geo[s.cam[jj] * L + l];
         const Corners cr = corners_of(gl[2 * src], gl[2 * src + 1], gm, row_bytes, 0u);
-        Taps t;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             t.off[c] = cr.off[c];
@@ -357,7 +394,7 @@ __device__ __forceinline__ void end_chunk() { wave_lds_sync(); }
 // Inclusive scan across the 256 threads of a block (4 waves); returns the
 // thread's inclusive sum and the block total in *total.
 __device__ __forceinline__ u32 block_inclusive_scan(u32 v, u32* lds4, u32* total) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_index();
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         const u32 t = __shfl_up(v, d, 64);

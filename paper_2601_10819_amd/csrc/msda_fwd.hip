@@ -43,36 +43,28 @@ size_t lds_bytes_view(const OpArgs& a, int waves) {
 }
 
 // Adds the staged chunk's nj pairs into acc: each group of lanes takes a
-// pair and loads the 4 corners of up to 4 levels before using them.
+// pair and loads the 4 corners of 4 levels at a time (padded levels read
+// zeros without touching memory) before using them.
 template <class FT, int CPL>
 __device__ __forceinline__ void fwd_chunk(const StageSlot& st, int nj, int L, int G,
                                           const Lanes& q, rsrc_t feat, float* acc) {
     using RowT = Row<FT, CPL>;
-    const int LG = L * G;
+    const int LG = L * G, Lp = padded_levels(L);
     for (int jj = q.sub; jj < nj; jj += q.spw) {
         const float* wj = st.w + jj * LG + q.g;
-        const Taps* tj = st.taps + jj * L;
-        for (int l0 = 0; l0 < L; l0 += 4) {
+        const Taps* tj = st.taps + jj * Lp;
+        for (int l0 = 0; l0 < Lp; l0 += 4) {
             u32 raw[4][4][RowT::kWords];
             float cw[4][4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int l = l0 + k;
-                if (l < L) {
-                    const Taps t = tj[l];
-                    const float wl = wj[l * G];
+                const Taps t = tj[l0 + k];
+                // a padded level has zero taps; any real weight keeps them zero
+                const float wl = wj[min(l0 + k, L - 1) * G];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        cw[k][c] = t.cw[c] * wl;
-                        load_words<RowT::kWords>(feat, t.off[c] + q.lane_off, raw[k][c]);
-                    }
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        cw[k][c] = 0.f;
-#pragma unroll
-                        for (int t = 0; t < RowT::kWords; ++t) raw[k][c][t] = 0u;
-                    }
+                for (int c = 0; c < 4; ++c) {
+                    cw[k][c] = t.cw[c] * wl;
+                    load_words<RowT::kWords>(feat, t.off[c] + q.lane_off, raw[k][c]);
                 }
             }
 #pragma unroll
@@ -107,7 +99,7 @@ __device__ __forceinline__ void fwd_anchor(const OpArgs& a, const int ba, const 
                                            unsigned char* work) {
     const int LG = a.L * a.G;
     const int J = a.pairs_per_chunk;
-    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int wave = wave_index(), nwaves = blockDim.x >> 6;
     const Lanes q = lanes_of<FT, CPL>(a);
     const StageSlot st = stage_slot(work, wave, J, a.L, a.G);
     const int b = ba / a.A;
@@ -179,11 +171,16 @@ __global__ void __launch_bounds__(512) msda_fwd_view_kernel(OpArgs a, float* par
     __syncthreads();                       // the only block-wide barrier
 
     const int x = (int)(blockIdx.x % kSlots);
-    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int wave = wave_index(), nwaves = blockDim.x >> 6;
     const int64_t r = (int64_t)(blockIdx.x / kSlots) * nwaves + wave;
     const SlotSpan span = slot_span(x, a.B, a.N, a.A);
     if (r >= slot_rows(span, a.A)) return;
-    const ViewRow row = view_row(span, r, a.N, a.A);
+    ViewRow row = view_row(span, r, a.N, a.A);
+    // every field is the same across the wave (r is per wave)
+    row.b = uniform(row.b);
+    row.a = uniform(row.a);
+    row.n_lo = uniform(row.n_lo);
+    row.nv = uniform(row.nv);
 
     const int LG = a.L * a.G;
     const int J = a.pairs_per_chunk;
