@@ -1,17 +1,19 @@
 // Stable LSD radix sort of (key, value) u32 pairs and segment boundaries,
 // the grouping step of the deterministic grad_feat reduction.
 //
-// The backward kernel writes one record per (sample, corner) at position
-// 4*sample + corner: key = the feature row the corner touches (or the number
-// of rows, a sentinel that sorts last, for a corner outside its level). A
-// stable sort by key leaves each row's records contiguous and in sample
-// order, so the per-row reduction that follows sums them in a fixed order:
-// grad_feat is bitwise reproducible, and no float atomics are needed.
+// The backward gather writes one record per sample, at the sample's index:
+// key = the bilinear cell the sample falls in (or the number of cells, a
+// sentinel that sorts last, for a sample outside its level). A stable sort
+// by key leaves each cell's records contiguous and in sample order, so the
+// tiled reduction that follows sums them in a fixed order: grad_feat is
+// bitwise reproducible, and no float atomics are needed.
 //
-// Each pass sorts by 8 key bits: a per-tile digit histogram, an exclusive
-// scan of the histograms in digit-major order, then a stable scatter where a
-// tile ranks equal digits by wave ballots (lanes in order), then waves in
-// order, then rounds in order.
+// The key bits are split into as few passes as digits of at most 10 bits
+// allow (a 20-bit key space, about a million cells, takes two). Each pass:
+// a per-tile digit histogram, an exclusive scan of the histograms in
+// digit-major order, then a stable scatter where a tile ranks equal digits
+// by wave ballots (lanes in order), then waves in order, then rounds in
+// order.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -22,23 +24,27 @@ namespace msda {
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // elements per tile
-constexpr int kDigits = 256;
+constexpr int kMaxDigitBits = 10;
+constexpr int kMaxDigits = 1 << kMaxDigitBits;
 constexpr int kScanTile = 4096;                          // scan: 256 threads x 16
 
 __global__ void __launch_bounds__(kSortThreads)
-radix_hist_kernel(const u32* __restrict__ keys, u32 n, int shift, u32* __restrict__ table,
-                  u32 ntiles) {
-    __shared__ u32 h[kDigits];
-    h[threadIdx.x] = 0;
+radix_hist_kernel(const u32* __restrict__ keys, u32 n, int shift, int bits,
+                  u32* __restrict__ table, u32 ntiles) {
+    __shared__ u32 h[kMaxDigits];
+    const int digits = 1 << bits;
+    for (int d = threadIdx.x; d < digits; d += kSortThreads) h[d] = 0;
     __syncthreads();
+    const u32 mask = (u32)digits - 1u;
     const u32 base = blockIdx.x * (u32)kSortTile;
 #pragma unroll 4
     for (int i = 0; i < kSortItems; ++i) {
         const u32 idx = base + i * kSortThreads + threadIdx.x;
-        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & (kDigits - 1)], 1u);
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
-    table[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];   // digit-major
+    for (int d = threadIdx.x; d < digits; d += kSortThreads)
+        table[(size_t)d * ntiles + blockIdx.x] = h[d];      // digit-major
 }
 
 // Scan, phase 1: per-tile sums.
@@ -94,36 +100,47 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(u32* x, u32 n,
     }
 }
 
-// Stable scatter of one tile by the digit at `shift`. vals_in == nullptr
-// means the value is the element's index (first pass).
+// Stable scatter of one tile by the `bits`-bit digit at `shift`. vals_in ==
+// nullptr means the value is the element's index (first pass). Per round of
+// 256 elements: lanes of a wave with equal digits are found with one ballot
+// per digit bit and ranked by lane; the first lane of each such group
+// publishes the group size for its wave, so a lane's place is the tile's
+// offset for the digit + the digit's count in earlier rounds + the groups
+// of earlier waves + its rank. Only the entries a round sets are cleared.
 __global__ void __launch_bounds__(kSortThreads)
 radix_scatter_kernel(const u32* __restrict__ keys_in, const u32* __restrict__ vals_in,
                      u32* __restrict__ keys_out, u32* __restrict__ vals_out, u32 n, int shift,
-                     const u32* __restrict__ table, u32 ntiles) {
-    __shared__ u32 base_off[kDigits];
-    __shared__ u32 running[kDigits];
-    __shared__ u32 wcount[4][kDigits];
+                     int bits, const u32* __restrict__ table, u32 ntiles) {
+    __shared__ u32 base_off[kMaxDigits];
+    __shared__ u32 running[kMaxDigits];
+    __shared__ u32 wcount[kSortThreads / 64][kMaxDigits];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    base_off[tid] = table[(size_t)tid * ntiles + blockIdx.x];
-    running[tid] = 0;
+    const int digits = 1 << bits;
+    const u32 mask = (u32)digits - 1u;
+    for (int d = tid; d < digits; d += kSortThreads) {
+        base_off[d] = table[(size_t)d * ntiles + blockIdx.x];
+        running[d] = 0;
+#pragma unroll
+        for (int w = 0; w < kSortThreads / 64; ++w) wcount[w][d] = 0;
+    }
+    __syncthreads();
     const u64 lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int r = 0; r < kSortItems; ++r) {
         const u32 idx = blockIdx.x * (u32)kSortTile + r * kSortThreads + tid;
         const bool valid = idx < n;
         const u32 key = valid ? keys_in[idx] : 0u;
         const u32 val = valid ? (vals_in ? vals_in[idx] : idx) : 0u;
-        const u32 d = (key >> shift) & (kDigits - 1);
+        const u32 d = (key >> shift) & mask;
         // lanes of this wave holding the same digit
         u64 peers = __ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
+        for (int bit = 0; bit < bits; ++bit) {
             const u64 b = __ballot((d >> bit) & 1u);
             peers &= ((d >> bit) & 1u) ? b : ~b;
         }
         const u32 rank = __popcll(peers & lt_mask);
-        for (int k = tid; k < 4 * kDigits; k += kSortThreads) (&wcount[0][0])[k] = 0;
-        __syncthreads();
-        if (valid && rank == 0) wcount[wave][d] = __popcll(peers);
+        const u32 count = __popcll(peers);
+        const bool leader = valid && rank == 0;
+        if (leader) wcount[wave][d] = count;
         __syncthreads();
         if (valid) {
             u32 before = 0;
@@ -135,7 +152,10 @@ radix_scatter_kernel(const u32* __restrict__ keys_in, const u32* __restrict__ va
             }
         }
         __syncthreads();
-        running[tid] += wcount[0][tid] + wcount[1][tid] + wcount[2][tid] + wcount[3][tid];
+        if (leader) {
+            atomicAdd(&running[d], count);   // integer: the order of the adds does not matter
+            wcount[wave][d] = 0;
+        }
         __syncthreads();
     }
 }
@@ -168,15 +188,25 @@ static hipError_t launch_scan(u32* x, u32 n, u32* partial, hipStream_t s) {
 
 size_t sort_scratch_words(u32 n) {
     const u32 ntiles = (n + kSortTile - 1) / kSortTile;
-    const size_t table = (size_t)kDigits * ntiles;
+    const size_t table = (size_t)kMaxDigits * ntiles;
     const size_t partial = (table + kScanTile - 1) / kScanTile + 1;
     return table + partial;
 }
 
+// Passes and digit width for keys in [0, max_key]: the fewest passes of at
+// most kMaxDigitBits bits, the bits shared evenly.
+static void sort_plan(u32 max_key, int* passes, int* bits) {
+    int kb = 0;
+    while (kb < 32 && (max_key >> kb) != 0) ++kb;
+    if (kb == 0) kb = 1;
+    *passes = (kb + kMaxDigitBits - 1) / kMaxDigitBits;
+    *bits = (kb + *passes - 1) / *passes;
+}
+
 int sort_passes(u32 max_key) {
-    int bits = 0;
-    while (bits < 32 && (max_key >> bits) != 0) ++bits;
-    return bits == 0 ? 1 : (bits + 7) / 8;
+    int passes, bits;
+    sort_plan(max_key, &passes, &bits);
+    return passes;
 }
 
 hipError_t launch_sort_records(u32* keys_a, u32* keys_b, u32* vals_a, u32* vals_b, u32 n,
@@ -185,23 +215,24 @@ hipError_t launch_sort_records(u32* keys_a, u32* keys_b, u32* vals_a, u32* vals_
     hipError_t e = hipSuccess;
     const u32 ntiles = (n + kSortTile - 1) / kSortTile;
     u32* table = scratch;
-    u32* partial = scratch + (size_t)kDigits * ntiles;
+    u32* partial = scratch + (size_t)kMaxDigits * ntiles;
     u32* kin = keys_a;
     u32* kout = keys_b;
     u32* vin = nullptr;       // first pass: values are the indices
     u32* vout = vals_a;
-    const int passes = sort_passes(nrows);
+    int passes, bits;
+    sort_plan(nrows, &passes, &bits);
     for (int p = 0; p < passes && n > 0; ++p) {
-        const int shift = 8 * p;
+        const int shift = bits * p;
         mark_begin("radix_hist", s);
         hipLaunchKernelGGL(radix_hist_kernel, dim3(ntiles), dim3(kSortThreads), 0, s, kin, n,
-                           shift, table, ntiles);
+                           shift, bits, table, ntiles);
         mark_end(s);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = launch_scan(table, kDigits * ntiles, partial, s)) != hipSuccess) return e;
+        if ((e = launch_scan(table, (u32)(ntiles << bits), partial, s)) != hipSuccess) return e;
         mark_begin("radix_scatter", s);
         hipLaunchKernelGGL(radix_scatter_kernel, dim3(ntiles), dim3(kSortThreads), 0, s, kin, vin,
-                           kout, vout, n, shift, table, ntiles);
+                           kout, vout, n, shift, bits, table, ntiles);
         mark_end(s);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // next pass reads what this one wrote
