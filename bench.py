@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage comparison")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 12-scene batched form (graph-replayed, autotuned)")
+    ap.add_argument("--no-cold", action="store_true",
+                    help="skip the cold-cache steps (1 GiB write before each step)")
+    ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 forward")
     ap.add_argument("--cpu-anchors", type=int, default=0,
                     help="anchors in the oracle's timed sample (0 = all of them)")
     return ap.parse_args()
@@ -67,6 +70,7 @@ class HipEvents:
         self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
                                                  ctypes.c_void_p]
         self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
 
     def create(self):
         e = ctypes.c_void_p()
@@ -82,6 +86,13 @@ class HipEvents:
 
     def destroy(self, e):
         self.hip.hipEventDestroy(e)
+
+    def record(self, e):
+        """Record on torch's current stream (the stream the library launches on)."""
+        import torch
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        if self.hip.hipEventRecord(e, stream) != 0:
+            raise RuntimeError("hipEventRecord failed")
 
 
 def kernel_source_hash():
@@ -108,7 +119,7 @@ def measured_traffic(kernel: str, workload: str, dtype: str):
     return ent.get("hbm_bytes_per_launch")
 
 
-def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup):
+def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup, cold=False):
     """Time `steps` forward+backward steps. Every kernel the library launches
     is bracketed by HIP events on its stream (the library's benchmark hook),
     so per-kernel average durations come from the timed region itself."""
@@ -152,15 +163,77 @@ def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     per_kernel = {}
+    steps_ms, fwd_ms = [], []
     for arr, nm in zip(arrays, names):
         for j, name in enumerate(nm):
             per_kernel.setdefault(name, []).append(ev.elapsed_ms(arr[2 * j], arr[2 * j + 1]))
+        # first kernel's start to last kernel's end: the step on the GPU;
+        # the forward is every kernel before the backward's first
+        steps_ms.append(ev.elapsed_ms(arr[0], arr[2 * len(nm) - 1]))
+        nf = sum(1 for name in nm if name.startswith(FWD_KERNELS))
+        fwd_ms.append(ev.elapsed_ms(arr[0], arr[2 * nf - 1]))
     for arr in arrays:
         for e in arr:
             ev.destroy(e)
     # average duration of one launch, and launches per step
     kern = {n: {"ms": sum(v) / len(v), "per_step": len(v) / steps} for n, v in per_kernel.items()}
-    return {"total_s": t1 - t0, "kernels": kern}
+    res = {"total_s": t1 - t0, "kernels": kern, "step_ms": pct(steps_ms),
+           "fwd_ms": pct(fwd_ms), "bwd_ms": pct([a - b for a, b in zip(steps_ms, fwd_ms)])}
+    if cold:
+        # the same steps with the caches cold: a 1 GiB write (twice the
+        # memory-side cache) before each, outside the events
+        flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        cold_ms = []
+        a, b = ev.create(), ev.create()
+        for _ in range(steps):
+            flush.fill_(1.0)
+            ev.record(a)
+            step()
+            ev.record(b)
+            torch.cuda.synchronize()
+            cold_ms.append(ev.elapsed_ms(a, b))
+        ev.destroy(a)
+        ev.destroy(b)
+        del flush
+        res["cold_ms"] = pct(cold_ms)
+    return res
+
+
+# kernels of the forward call (the rest of a step is the backward)
+FWD_KERNELS = ("msda_fwd", "fwd_view_reduce")
+
+
+def pct(v):
+    """median, p10 and p90 of a list of milliseconds."""
+    import numpy as np
+    a = np.asarray(v, dtype=np.float64)
+    return {"median": round(float(np.median(a)), 4), "p10": round(float(np.percentile(a, 10)), 4),
+            "p90": round(float(np.percentile(a, 90)), 4)}
+
+
+def run_fp8_forward(torch, ops, p, steps, warmup):
+    """The FP8 precision form's forward (per-level scales; the quantiser runs
+    once, outside the timing), event-timed per call."""
+    dev = "cuda"
+    layout = ops.Layout(p.spatial_shapes, p.level_start_index, dev)
+    codes, scale = ops.quantize_fp8(p.feat.to(dev), layout)
+    loc, w = p.sampling_loc.to(dev), p.weights.to(dev)
+    out = torch.empty(p.batch, p.num_anchors, p.channels, device=dev)
+    fws = ops.forward_workspace_bytes(codes, layout, loc, w)
+    ws = torch.empty(fws + 256, dtype=torch.uint8, device=dev) if fws else None
+    for _ in range(warmup):
+        ops.forward(codes, layout, loc, w, level_scale=scale, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        ops.forward(codes, layout, loc, w, level_scale=scale, out=out, workspace=ws)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    return pct(times)
 
 
 def run_batched(torch, ops, synth, steps, warmup):
@@ -277,7 +350,8 @@ def main():
     S = p.samples
     print(f"# workload {p.name} {p.dims()} samples/step {S}", file=sys.stderr, flush=True)
 
-    bf = run_gpu(args, torch, ops, synth, p, torch.bfloat16, args.steps, args.warmup)
+    bf = run_gpu(args, torch, ops, synth, p, torch.bfloat16, args.steps, args.warmup,
+                 cold=not args.no_cold)
     print(f"# bf16 done: {bf}", file=sys.stderr, flush=True)
     ms_step = bf["total_s"] / args.steps * 1e3
     value = S * args.steps / bf["total_s"] / 1e9
@@ -321,6 +395,9 @@ def main():
                    "level_shapes": [list(map(int, s)) for s in p.spatial_shapes[0].tolist()],
                    "channels": C, "groups": G, "anchors": p.num_anchors, "keypoints": P,
                    "samples_per_step": S},
+        "step_ms": bf["step_ms"],
+        "fwd_ms": bf["fwd_ms"],
+        "bwd_ms": bf["bwd_ms"],
         "kernels_ms": {n: round(v["ms"], 4) for n, v in ks.items()},
         "alg_hbm_frac_fwd_bwd": round(S * (fwd_b + bwd_b) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "kernel": kern,
@@ -330,12 +407,22 @@ def main():
                      "traffic": traffic, "alg_bytes_per_launch": int(kbytes) if kbytes else None,
                      "avg_launch_ms": round(kms, 4)},
     }
+    if "cold_ms" in bf:
+        res["cold"] = {"ms_per_step": bf["cold_ms"],
+                       "value": round(S / (bf["cold_ms"]["median"] * 1e-3) / 1e9, 4),
+                       "note": "1 GiB written before each step, outside its events"}
     if fp is not None:
         fp_ms = fp["total_s"] / args.steps * 1e3
         res["fp32_ms_per_step"] = round(fp_ms, 4)
         res["fp32_value"] = round(S * args.steps / fp["total_s"] / 1e9, 4)
         res["bf16_speedup_vs_fp32"] = round(fp_ms / ms_step, 3)
         res["fp32_kernels_ms"] = {n: round(v["ms"], 4) for n, v in fp["kernels"].items()}
+        res["fp32_fwd_ms"] = fp["fwd_ms"]
+        res["fp32_bwd_ms"] = fp["bwd_ms"]
+    if not args.no_fp8:
+        f8 = run_fp8_forward(torch, ops, p, args.steps, args.warmup)
+        res["fp8_forward"] = {"ms": f8, "value": round(S / (f8["median"] * 1e-3) / 1e9, 4),
+                              "unit": "GSamples/s (forward only)"}
     if not args.no_batched:
         res["batched"] = run_batched(torch, ops, synth, args.steps, args.warmup)
         print(f"# batched done: {res['batched']}", file=sys.stderr, flush=True)
