@@ -23,6 +23,7 @@ Rows of a batch item are camera-major, then level, then row-major (y, x).
 from __future__ import annotations
 
 import dataclasses
+import math
 from typing import List, Optional, Sequence, Tuple
 
 import torch
@@ -206,6 +207,89 @@ def cam64(seed: int = 0, anchors: int = 900, cams: int = 64) -> Problem:
 
 
 BATCH_RESOLUTIONS = ((256, 448), (384, 640), (512, 896))
+
+
+# ---------------------------------------------------------------------------
+# Outside-in scene geometry: the inputs of the keypoint projection step.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SceneGeometry:
+    """Inputs of the projection step (all FP32, CPU):
+      anchors     [B, A, 10]   (x, y, z, w, l, h, yaw, vx, vy, vz), metres / rad / m/s
+      keypoints   [B, A, P, 3] box-frame offsets in units of (w, l, h)
+      dt          time offset of the motion compensation, seconds
+      projection  [B, N, 3, 4] camera projection matrices (pixels)
+      image_hw    [N, 2] int32 image height and width in pixels
+    """
+
+    anchors: torch.Tensor
+    keypoints: torch.Tensor
+    dt: float
+    projection: torch.Tensor
+    image_hw: torch.Tensor
+
+
+# 7 fixed keypoints: the box centre and its 6 face centres
+FIXED_KEYPOINTS = ((0.0, 0.0, 0.0), (0.5, 0.0, 0.0), (-0.5, 0.0, 0.0), (0.0, 0.5, 0.0),
+                   (0.0, -0.5, 0.0), (0.0, 0.0, 0.5), (0.0, 0.0, -0.5))
+
+
+def _camera_matrix(eye, target, hfov, img_hw):
+    """K [R | -R eye] of a pinhole camera at eye looking at target (z up in
+    the world; camera x right, y down, z forward)."""
+    eye = torch.as_tensor(eye, dtype=torch.float64)
+    fwd = torch.as_tensor(target, dtype=torch.float64) - eye
+    fwd = fwd / fwd.norm()
+    right = torch.linalg.cross(fwd, torch.tensor([0.0, 0.0, 1.0], dtype=torch.float64))
+    right = right / right.norm()
+    down = torch.linalg.cross(fwd, right)
+    R = torch.stack([right, down, fwd])
+    H, W = img_hw
+    f = (W / 2.0) / math.tan(hfov / 2.0)
+    K = torch.tensor([[f, 0.0, W / 2.0], [0.0, f, H / 2.0], [0.0, 0.0, 1.0]], dtype=torch.float64)
+    Rt = torch.cat([R, (-R @ eye)[:, None]], dim=1)
+    return (K @ Rt).float()
+
+
+def outside_in(seed: int = 0, B: int = 1, cams: int = 64, anchors: int = 900, P: int = 13,
+               img_hw=(256, 448), area: float = 30.0, radius: float = 35.0,
+               dt: float = 0.1) -> SceneGeometry:
+    """An outside-in camera network: cams cameras on a ring of the given
+    radius around a square area of half-width `area`, at heights U[5, 10] m,
+    each aimed at a ground point uniform over the area with a horizontal
+    field of view U[20, 40] degrees (at the defaults an anchor is seen by
+    about 15 of 64 cameras); anchors uniform over the area (z U[0, 1.5])
+    with sizes w U[0.5, 2], l U[0.5, 5], h U[1.5, 2.5], yaw U[0, 2 pi) and
+    velocities N(0, 1.5) m/s (vertical x 0.1); the 7 fixed keypoints plus
+    P - 7 learned offsets U[-0.5, 0.5]^3."""
+    gen = torch.Generator().manual_seed(seed)
+    u = lambda *shape: torch.rand(*shape, generator=gen, dtype=torch.float64)
+    proj = torch.zeros(B, cams, 3, 4)
+    for b in range(B):
+        for n in range(cams):
+            ang = 2 * math.pi * (n + float(u(1))) / cams
+            eye = (radius * math.cos(ang), radius * math.sin(ang), 5.0 + 5.0 * float(u(1)))
+            target = ((2 * float(u(1)) - 1) * area, (2 * float(u(1)) - 1) * area, 0.0)
+            hfov = math.radians(20.0 + 20.0 * float(u(1)))
+            proj[b, n] = _camera_matrix(eye, target, hfov, img_hw)
+    a = torch.zeros(B, anchors, 10, dtype=torch.float64)
+    a[..., 0] = (2 * u(B, anchors) - 1) * area
+    a[..., 1] = (2 * u(B, anchors) - 1) * area
+    a[..., 2] = 1.5 * u(B, anchors)
+    a[..., 3] = 0.5 + 1.5 * u(B, anchors)
+    a[..., 4] = 0.5 + 4.5 * u(B, anchors)
+    a[..., 5] = 1.5 + 1.0 * u(B, anchors)
+    a[..., 6] = 2 * math.pi * u(B, anchors)
+    a[..., 7:10] = torch.randn(B, anchors, 3, generator=gen, dtype=torch.float64) * 1.5
+    a[..., 9] *= 0.1
+    k = torch.zeros(B, anchors, P, 3, dtype=torch.float64)
+    nfix = min(P, len(FIXED_KEYPOINTS))
+    k[:, :, :nfix] = torch.tensor(FIXED_KEYPOINTS[:nfix], dtype=torch.float64)
+    if P > nfix:
+        k[:, :, nfix:] = u(B, anchors, P - nfix, 3) - 0.5
+    hw = torch.tensor([list(img_hw)] * cams, dtype=torch.int32)
+    return SceneGeometry(a.float(), k.float(), dt, proj, hw)
 
 
 def batched_scene_shapes(seed: int = 0, scenes: int = 12):
