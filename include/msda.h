@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define MSDA_ABI_VERSION 2
+#define MSDA_ABI_VERSION 3
 
 typedef enum msda_status {
     MSDA_OK = 0,
@@ -177,9 +177,64 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
                           size_t workspace_bytes, const msda_desc* desc, void* stream);
 
 /* Bytes of device workspace msda_backward needs for desc (0 if none): about
- * 20 bytes per (sample, corner) for the sorted form; B*R*C*4 for the atomic
- * form with BF16 features. */
+ * 24 bytes per sample plus 4 per bilinear cell for the sorted form; B*R*C*4
+ * for the atomic form with BF16 features. */
 size_t msda_backward_workspace_size(const msda_desc* desc);
+
+/*
+ * Keypoint projection with motion compensation (paper Sec. 3.1, Sec. 3.2):
+ * the step that produces MSDA's sampling locations. For each batch item b,
+ * anchor a, keypoint p and camera n:
+ *   world = (x, y, z) + Rz(yaw) (k_x w, k_y l, k_z h) + dt (vx, vy, vz)
+ *   (u', v', d) = M[b][n] (world, 1);  pixel = (u'/d, v'/d) when d > 1e-5
+ *   sampling_loc[b][a][p][n] = (pixel_x / W_img[n], pixel_y / H_img[n]),
+ *                              (-2, -2) when d <= 1e-5 (skipped by MSDA)
+ *   visible[b][a][n] = 1 if some keypoint has d > 1e-5 and a pixel inside
+ *                      [0, W_img) x [0, H_img), else 0
+ * anchors [B][A][10] (x, y, z, w, l, h, yaw, vx, vy, vz), FP32; keypoints
+ * [B][A][P][3] box-frame offsets in units of (w, l, h); projection
+ * [B][Ncam][3][4] (intrinsics times world-to-camera extrinsics, pixels);
+ * image_hw [Ncam][2] int32 (H, W). All device; outputs overwritten.
+ */
+typedef struct msda_projection_desc {
+    int32_t batch;       /* B >= 1    */
+    int32_t num_anchors; /* A >= 0    */
+    int32_t num_points;  /* P >= 1    */
+    int32_t num_cams;    /* Ncam >= 1 */
+    float dt;            /* seconds, the motion-compensation time offset */
+} msda_projection_desc;
+
+msda_status msda_project_keypoints(const float* anchors, const float* keypoints,
+                                   const float* projection, const int32_t* image_hw,
+                                   float* sampling_loc, uint8_t* visible,
+                                   const msda_projection_desc* desc, void* stream);
+
+/*
+ * Visible-view MSDA: the forward and backward restricted to the (batch item,
+ * anchor, camera) pairs with visible[b][a][n] != 0 (uint8 [B][A][Ncam],
+ * device; e.g. from msda_project_keypoints). Samples of other pairs are not
+ * read or computed: out sums over the visible pairs only, and their
+ * grad_sampling_loc and grad_weights are written as zero. The visible items
+ * are compacted camera-major on the device and processed in view order, so
+ * the work and the traffic scale with the number of visible pairs. The
+ * forward adds an anchor's cameras in camera order (deterministic); the
+ * backward has the sorted grad_feat form only. Same layouts, dtypes and
+ * limits as msda_forward / msda_backward; workspaces (device, 256-byte
+ * aligned) of at least the sizes below.
+ */
+msda_status msda_forward_visible(const void* feat, const int32_t* spatial_shapes,
+                                 const int32_t* level_start_index, const float* sampling_loc,
+                                 const float* weights, const uint8_t* visible, float* out,
+                                 void* workspace, size_t workspace_bytes, const msda_desc* desc,
+                                 void* stream);
+size_t msda_forward_visible_workspace_size(const msda_desc* desc);
+msda_status msda_backward_visible(const void* feat, const int32_t* spatial_shapes,
+                                  const int32_t* level_start_index, const float* sampling_loc,
+                                  const float* weights, const uint8_t* visible,
+                                  const float* grad_out, void* grad_feat,
+                                  float* grad_sampling_loc, float* grad_weights, void* workspace,
+                                  size_t workspace_bytes, const msda_desc* desc, void* stream);
+size_t msda_backward_visible_workspace_size(const msda_desc* desc);
 
 /*
  * Per-level FP8 quantisation of an FP32 feat (the precision form's storage):

@@ -25,12 +25,14 @@ MSDA_FP8_E4M3 = 2
 
 MSDA_DETERMINISTIC = 1
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 # Every symbol include/msda.h declares.
 EXPORTS = (
     "msda_forward", "msda_forward_ws", "msda_forward_workspace_size", "msda_backward",
-    "msda_backward_workspace_size", "msda_quantize_fp8",
+    "msda_backward_workspace_size", "msda_project_keypoints", "msda_forward_visible",
+    "msda_forward_visible_workspace_size", "msda_backward_visible",
+    "msda_backward_visible_workspace_size", "msda_quantize_fp8",
     "msda_quantize_workspace_size", "msda_batched_workspace_size", "msda_forward_batched",
     "msda_backward_batched", "msda_stream_copy", "msda_set_kernel_events",
     "msda_recorded_kernels", "msda_recorded_kernel_name", "msda_last_error", "msda_abi_version",
@@ -61,6 +63,12 @@ class MsdaDesc(ctypes.Structure):
         ("level_scale", ctypes.c_void_p), ("flags", ctypes.c_uint32),
         ("tile", ctypes.POINTER(MsdaTile)),
     ]
+
+
+class MsdaProjDesc(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("num_anchors", ctypes.c_int32),
+                ("num_points", ctypes.c_int32), ("num_cams", ctypes.c_int32),
+                ("dt", ctypes.c_float)]
 
 
 class MsdaScene(ctypes.Structure):
@@ -113,6 +121,16 @@ def load(path: str = LIB_PATH):
     lib.msda_forward_ws.restype = ctypes.c_int
     lib.msda_forward_workspace_size.argtypes = [dp]
     lib.msda_forward_workspace_size.restype = sz
+    lib.msda_project_keypoints.argtypes = [vp] * 6 + [ctypes.POINTER(MsdaProjDesc), vp]
+    lib.msda_project_keypoints.restype = ctypes.c_int
+    lib.msda_forward_visible.argtypes = [vp] * 8 + [sz, dp, vp]
+    lib.msda_forward_visible.restype = ctypes.c_int
+    lib.msda_forward_visible_workspace_size.argtypes = [dp]
+    lib.msda_forward_visible_workspace_size.restype = sz
+    lib.msda_backward_visible.argtypes = [vp] * 11 + [sz, dp, vp]
+    lib.msda_backward_visible.restype = ctypes.c_int
+    lib.msda_backward_visible_workspace_size.argtypes = [dp]
+    lib.msda_backward_visible_workspace_size.restype = sz
     lib.msda_backward.argtypes = [vp] * 10 + [sz, dp, vp]
     lib.msda_backward.restype = ctypes.c_int
     lib.msda_backward_workspace_size.argtypes = [dp]

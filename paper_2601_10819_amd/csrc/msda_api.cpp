@@ -419,6 +419,23 @@ static hipError_t launch_gather(const msda::OpArgs& a, int order, int dtype, int
     return msda::launch_backward(a, dtype, cpl, waves, msda::lds_bytes_for(a, waves), s);
 }
 
+// Extra workspace of the visible-view form: the scanned flags (V + 1 words),
+// the scan's scratch, the item list (V words) and the record count.
+struct VisibleWs {
+    size_t place, partial, items, rec_count, total;
+};
+
+VisibleWs visible_layout(const msda_desc* d, size_t at) {
+    const uint64_t V = (uint64_t)d->batch * d->num_cams * (uint64_t)(d->num_anchors > 0 ? d->num_anchors : 0);
+    VisibleWs w;
+    w.place = at;
+    w.partial = w.place + align256((V + 1) * 4);
+    w.items = w.partial + align256(msda::scan_scratch_words((uint32_t)(V + 1)) * 4);
+    w.rec_count = w.items + align256(V * 4 + 4);
+    w.total = w.rec_count + 256;
+    return w;
+}
+
 size_t msda_backward_workspace_size(const msda_desc* d) {
     if (!d || d->batch < 1 || d->rows < 1 || d->channels < 1 || d->num_anchors < 0) return 0;
     if (scatter_mode(d) == MSDA_SCATTER_ATOMIC) {
@@ -433,13 +450,17 @@ size_t msda_backward_workspace_size(const msda_desc* d) {
                          (uint64_t)d->num_cams * d->num_levels).total;
 }
 
-msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
-                          const int32_t* level_start_index, const float* sampling_loc,
-                          const float* weights, const float* grad_out, void* grad_feat,
-                          float* grad_sampling_loc, float* grad_weights, void* workspace,
-                          size_t workspace_bytes, const msda_desc* desc, void* stream) {
+// The backward, dense (visible == nullptr) or over the visible views only.
+static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes,
+                                 const int32_t* level_start_index, const float* sampling_loc,
+                                 const float* weights, const uint8_t* visible,
+                                 const float* grad_out, void* grad_feat, float* grad_sampling_loc,
+                                 float* grad_weights, void* workspace, size_t workspace_bytes,
+                                 const msda_desc* desc, void* stream) {
     if (!desc) return fail(MSDA_ERR_INVALID_ARGUMENT, "desc is NULL");
-    const int order = resolve_order(desc, true);
+    // the visible-view gathers walk a compacted item list in ranges per XCD,
+    // with the view order's launch shape
+    const int order = visible ? MSDA_ORDER_VIEW : resolve_order(desc, true);
     msda::OpArgs a = {};
     int cpl = 0, waves = 0;
     msda_status st = prepare(desc, order, &a, &cpl, &waves);
@@ -454,6 +475,10 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
     const int mode = scatter_mode(desc);
     if (mode != MSDA_SCATTER_SORTED && mode != MSDA_SCATTER_ATOMIC)
         return fail(MSDA_ERR_UNSUPPORTED, "unknown scatter mode %d", mode);
+    if (visible && mode != MSDA_SCATTER_SORTED)
+        return fail(MSDA_ERR_UNSUPPORTED, "the visible-view backward has the sorted form only");
+    if (visible && desc->tile && desc->tile->order == MSDA_ORDER_ANCHOR)
+        return fail(MSDA_ERR_UNSUPPORTED, "the visible-view form runs in view order only");
     if ((desc->flags & MSDA_DETERMINISTIC) && mode == MSDA_SCATTER_ATOMIC)
         return fail(MSDA_ERR_UNSUPPORTED, "MSDA_DETERMINISTIC excludes MSDA_SCATTER_ATOMIC");
     const uint64_t nrec = num_samples(desc);
@@ -481,7 +506,9 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
         if (rcpl == 4 && !aligned(grad_out, 16))
             return fail(MSDA_ERR_UNSUPPORTED, "grad_out must be 16-byte aligned");
     }
-    const size_t need = grad_feat ? msda_backward_workspace_size(desc) : 0;
+    const size_t sorted_need = grad_feat ? msda_backward_workspace_size(desc) : 0;
+    const VisibleWs VW = visible_layout(desc, align256(sorted_need));
+    const size_t need = visible && a.A > 0 ? VW.total : sorted_need;
     if (need) {
         if (!workspace || workspace_bytes < need)
             return fail(MSDA_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
@@ -543,9 +570,37 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
         if (!cover && (e = msda::launch_fill_zero(grad_feat, gf_bytes, s)) != hipSuccess)
             return hip_fail(e, "zero grad_feat");
     }
-    if (a.A > 0 && (grad_feat || grad_sampling_loc || grad_weights) &&
-        (e = launch_gather(a, order, desc->feat_dtype, cpl, waves, s)) != hipSuccess)
+    uint32_t* rec_count = nullptr;
+    if (visible) {
+        // invisible pairs take no part: their gradients are zero
+        if (a.A > 0 && grad_weights &&
+            (e = msda::launch_fill_zero(grad_weights, num_samples(desc) * a.G * sizeof(float),
+                                        s)) != hipSuccess)
+            return hip_fail(e, "zero grad_weights");
+        if (a.A > 0 && grad_sampling_loc &&
+            (e = msda::launch_fill_zero(grad_sampling_loc,
+                                        num_samples(desc) / a.L * 2 * sizeof(float), s)) !=
+                hipSuccess)
+            return hip_fail(e, "zero grad_sampling_loc");
+        if (a.A > 0 && (grad_feat || grad_sampling_loc || grad_weights)) {
+            uint32_t* place = reinterpret_cast<uint32_t*>(ws + VW.place);
+            uint32_t* items = reinterpret_cast<uint32_t*>(ws + VW.items);
+            rec_count = reinterpret_cast<uint32_t*>(ws + VW.rec_count);
+            const size_t V = (size_t)a.B * a.N * a.A;
+            if ((e = msda::launch_visible_items(visible, a.B, a.N, a.A, (uint32_t)(a.P * a.L),
+                                                place, items, rec_count,
+                                                reinterpret_cast<uint32_t*>(ws + VW.partial),
+                                                s)) != hipSuccess ||
+                (e = msda::launch_backward_visible(
+                     a, desc->feat_dtype, cpl, waves, msda::lds_bytes_view(a, waves), items,
+                     place + V, grad_feat ? reinterpret_cast<uint32_t*>(ws + W.vals_a) : nullptr,
+                     s)) != hipSuccess)
+                return hip_fail(e, "msda_backward_visible launch");
+        }
+    } else if (a.A > 0 && (grad_feat || grad_sampling_loc || grad_weights) &&
+               (e = launch_gather(a, order, desc->feat_dtype, cpl, waves, s)) != hipSuccess) {
         return hip_fail(e, "msda_backward launch");
+    }
     if (!grad_feat) return ok();
 
     uint32_t* sorted = nullptr;
@@ -555,7 +610,7 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
                                   reinterpret_cast<uint32_t*>(ws + W.vals_a),
                                   reinterpret_cast<uint32_t*>(ws + W.vals_b), (uint32_t)nrec,
                                   (uint32_t)ncells, reinterpret_cast<uint32_t*>(ws + W.scratch),
-                                  off, &sorted, s);
+                                  off, &sorted, s, rec_count, rec_count != nullptr);
     if (e != hipSuccess) return hip_fail(e, "sort grad_feat records");
     msda::TileArgs t = {};
     t.vals = sorted ? sorted : reinterpret_cast<uint32_t*>(ws + W.vals_a);
@@ -592,6 +647,129 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
             (e = msda::launch_gfeat_tiles(t, desc->feat_dtype, rcpl, s)) != hipSuccess)
             return hip_fail(e, "grad_feat tile reduction");
     }
+    return ok();
+}
+
+msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
+                          const int32_t* level_start_index, const float* sampling_loc,
+                          const float* weights, const float* grad_out, void* grad_feat,
+                          float* grad_sampling_loc, float* grad_weights, void* workspace,
+                          size_t workspace_bytes, const msda_desc* desc, void* stream) {
+    return backward_impl(feat, spatial_shapes, level_start_index, sampling_loc, weights, nullptr,
+                         grad_out, grad_feat, grad_sampling_loc, grad_weights, workspace,
+                         workspace_bytes, desc, stream);
+}
+
+msda_status msda_backward_visible(const void* feat, const int32_t* spatial_shapes,
+                                  const int32_t* level_start_index, const float* sampling_loc,
+                                  const float* weights, const uint8_t* visible,
+                                  const float* grad_out, void* grad_feat,
+                                  float* grad_sampling_loc, float* grad_weights, void* workspace,
+                                  size_t workspace_bytes, const msda_desc* desc, void* stream) {
+    if (!visible && desc && desc->num_anchors > 0)
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "visible is NULL");
+    static const uint8_t none = 0;
+    return backward_impl(feat, spatial_shapes, level_start_index, sampling_loc, weights,
+                         visible ? visible : &none, grad_out, grad_feat, grad_sampling_loc,
+                         grad_weights, workspace, workspace_bytes, desc, stream);
+}
+
+size_t msda_backward_visible_workspace_size(const msda_desc* d) {
+    if (!d || d->batch < 1 || d->rows < 1 || d->channels < 1 || d->num_anchors < 0) return 0;
+    return visible_layout(d, align256(msda_backward_workspace_size(d))).total;
+}
+
+// The visible-view forward's workspace: the compaction, then one partial
+// row per (batch item, camera, anchor) item.
+static size_t forward_visible_part(const msda_desc* d, size_t* part_off) {
+    const VisibleWs vw = visible_layout(d, 0);
+    *part_off = vw.total;
+    const uint64_t V = (uint64_t)d->batch * d->num_cams * (uint64_t)d->num_anchors;
+    return vw.total + align256(V * (uint64_t)d->channels * sizeof(float));
+}
+
+size_t msda_forward_visible_workspace_size(const msda_desc* d) {
+    if (!d || d->batch < 1 || d->num_cams < 1 || d->channels < 1 || d->num_anchors < 0) return 0;
+    size_t part_off;
+    return forward_visible_part(d, &part_off);
+}
+
+msda_status msda_forward_visible(const void* feat, const int32_t* spatial_shapes,
+                                 const int32_t* level_start_index, const float* sampling_loc,
+                                 const float* weights, const uint8_t* visible, float* out,
+                                 void* workspace, size_t workspace_bytes, const msda_desc* desc,
+                                 void* stream) {
+    if (!desc) return fail(MSDA_ERR_INVALID_ARGUMENT, "desc is NULL");
+    if (desc->tile && desc->tile->order == MSDA_ORDER_ANCHOR)
+        return fail(MSDA_ERR_UNSUPPORTED, "the visible-view form runs in view order only");
+    msda::OpArgs a = {};
+    int cpl = 0, waves = 0;
+    msda_status st = prepare(desc, MSDA_ORDER_VIEW, &a, &cpl, &waves);
+    if (st != MSDA_OK) return st;
+    if (!feat || !spatial_shapes || !level_start_index ||
+        (a.A > 0 && (!sampling_loc || !weights || !out || !visible)))
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "a required device pointer is NULL");
+    if (!aligned(feat, 16)) return fail(MSDA_ERR_UNSUPPORTED, "feat must be 16-byte aligned");
+    if ((uint64_t)a.B * a.N * (uint64_t)a.A >= (1ull << 31))
+        return fail(MSDA_ERR_UNSUPPORTED, "B * Ncam * A must be < 2^31");
+    size_t part_off = 0;
+    const size_t need = forward_visible_part(desc, &part_off);
+    if (a.A == 0) return ok();
+    if (!workspace || workspace_bytes < need || !aligned(workspace, 256))
+        return fail(MSDA_ERR_WORKSPACE, "forward workspace: need %zu bytes, 256-byte aligned "
+                                        "(got %zu at %p)", need, workspace_bytes, workspace);
+    a.feat = feat;
+    a.shapes = spatial_shapes;
+    a.starts = level_start_index;
+    a.loc = sampling_loc;
+    a.w = weights;
+    a.level_scale = desc->feat_dtype == MSDA_FP8_E4M3 ? desc->level_scale : nullptr;
+    a.out = out;
+    char* ws = static_cast<char*>(workspace);
+    const VisibleWs vw = visible_layout(desc, 0);
+    uint32_t* place = reinterpret_cast<uint32_t*>(ws + vw.place);
+    uint32_t* items = reinterpret_cast<uint32_t*>(ws + vw.items);
+    const size_t V = (size_t)a.B * a.N * a.A;
+    const hipStream_t s = (hipStream_t)stream;
+    hipError_t e = msda::launch_visible_items(visible, a.B, a.N, a.A, 0u, place, items, nullptr,
+                                              reinterpret_cast<uint32_t*>(ws + vw.partial), s);
+    if (e == hipSuccess)
+        e = msda::launch_forward_visible(a, desc->feat_dtype, cpl, waves,
+                                         msda::lds_bytes_view(a, waves), items, place + V, place,
+                                         visible, reinterpret_cast<float*>(ws + part_off), s);
+    if (e != hipSuccess) return hip_fail(e, "msda_forward_visible launch");
+    return ok();
+}
+
+msda_status msda_project_keypoints(const float* anchors, const float* keypoints,
+                                   const float* projection, const int32_t* image_hw,
+                                   float* sampling_loc, uint8_t* visible,
+                                   const msda_projection_desc* d, void* stream) {
+    if (!d) return fail(MSDA_ERR_INVALID_ARGUMENT, "desc is NULL");
+    if (d->batch < 1 || d->num_anchors < 0 || d->num_points < 1 || d->num_cams < 1)
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "sizes must be positive (B=%d A=%d P=%d Ncam=%d)",
+                    d->batch, d->num_anchors, d->num_points, d->num_cams);
+    if ((uint64_t)d->batch * d->num_anchors * (uint64_t)d->num_points * d->num_cams >=
+        (1ull << 31))
+        return fail(MSDA_ERR_UNSUPPORTED, "B * A * P * Ncam must be < 2^31");
+    if (!(d->dt == d->dt)) return fail(MSDA_ERR_INVALID_ARGUMENT, "dt is NaN");
+    if (d->num_anchors == 0) return ok();
+    if (!anchors || !keypoints || !projection || !image_hw || !sampling_loc || !visible)
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "a required device pointer is NULL");
+    msda::ProjArgs p = {};
+    p.anchors = anchors;
+    p.keypoints = keypoints;
+    p.projection = projection;
+    p.image_hw = image_hw;
+    p.loc = sampling_loc;
+    p.visible = visible;
+    p.B = d->batch;
+    p.A = d->num_anchors;
+    p.P = d->num_points;
+    p.N = d->num_cams;
+    p.dt = d->dt;
+    const hipError_t e = msda::launch_project_keypoints(p, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "msda_project_keypoints launch");
     return ok();
 }
 

@@ -297,14 +297,19 @@ struct ViewOrder {
 };
 
 // Where the backward writes its grad_feat records (key = bilinear cell,
-// frac = (lx, ly)) while staging: record of (pair src, level l) at
-// base + src*L + l. key == nullptr: none.
+// frac = (lx, ly)) while staging. The sample (pair src, level l) has the
+// index s = base + src*L + l; its fractions go to frac[s]. Dense records
+// (val == nullptr): the record is key[s] and its value is s. Compacted
+// records (the visible-view form): the k-th pair the wave processes writes
+// record r = cbase + k*L + l, key[r] and val[r] = s. key == nullptr: none.
 struct RecordSink {
     u32* key;
     float2* frac;
-    u32 base;            // first record of the anchor
+    u32 base;            // first sample of the anchor
     u32 cell_base;       // first cell of the batch item
     u32 no_cell;         // key of a sample outside its level
+    u32* val;            // compacted records' values, or nullptr
+    u32 cbase;           // compacted: first record of the wave's item
 };
 
 // Stages pairs [k0, k0 + nj) (in the wave's pair order) of the anchor whose
@@ -358,11 +363,19 @@ __device__ __forceinline__ void stage_chunk(const StageSlot& s, const Order& ord
         if constexpr (FRACS) {
             s.frac[i] = make_float2(cr.lx, cr.ly);
             if (rec.key) {
-                const u32 r = rec.base + src * (u32)L + (u32)l;
-                rec.key[r] = cr.valid ? rec.cell_base + gm.cstart +
-                                            (u32)(cr.y0 + 1) * (u32)(gm.W + 1) + (u32)(cr.x0 + 1)
-                                      : rec.no_cell;
-                rec.frac[r] = make_float2(cr.lx, cr.ly);
+                const u32 smp = rec.base + src * (u32)L + (u32)l;
+                const u32 key = cr.valid ? rec.cell_base + gm.cstart +
+                                               (u32)(cr.y0 + 1) * (u32)(gm.W + 1) +
+                                               (u32)(cr.x0 + 1)
+                                         : rec.no_cell;
+                if (rec.val) {
+                    const u32 r = rec.cbase + (u32)(k0 + jj) * (u32)L + (u32)l;
+                    rec.key[r] = key;
+                    rec.val[r] = smp;
+                } else {
+                    rec.key[smp] = key;
+                }
+                rec.frac[smp] = make_float2(cr.lx, cr.ly);
             }
         }
     }

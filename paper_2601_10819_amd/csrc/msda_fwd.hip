@@ -20,7 +20,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "msda_common.h"
+#include "msda_gather.h"
 
 namespace msda {
 
@@ -40,55 +40,6 @@ size_t lds_bytes_for(const OpArgs& a, int waves) {
 size_t lds_bytes_view(const OpArgs& a, int waves) {
     return (size_t)a.N * a.L * sizeof(Geo) +
            (size_t)waves * wave_stage_bytes(a.pairs_per_chunk, a.L, a.G);
-}
-
-// Adds the staged chunk's nj pairs into acc: each group of lanes takes a
-// pair and loads the 4 corners of 4 levels at a time (padded levels read
-// zeros without touching memory) before using them.
-template <class FT, int CPL>
-__device__ __forceinline__ void fwd_chunk(const StageSlot& st, int nj, int L, int G,
-                                          const Lanes& q, rsrc_t feat, float* acc) {
-    using RowT = Row<FT, CPL>;
-    const int LG = L * G, Lp = padded_levels(L);
-    for (int jj = q.sub; jj < nj; jj += q.spw) {
-        const float* wj = st.w + jj * LG + q.g;
-        const Taps* tj = st.taps + jj * Lp;
-        for (int l0 = 0; l0 < Lp; l0 += 4) {
-            u32 raw[4][4][RowT::kWords];
-            float cw[4][4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const Taps t = tj[l0 + k];
-                // a padded level has zero taps; any real weight keeps them zero
-                const float wl = wj[min(l0 + k, L - 1) * G];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    cw[k][c] = t.cw[c] * wl;
-                    load_words<RowT::kWords>(feat, t.off[c] + q.lane_off, raw[k][c]);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    float f[CPL];
-                    widen<FT, CPL>(raw[k][c], f);
-#pragma unroll
-                    for (int i = 0; i < CPL; ++i) acc[i] = fmaf(cw[k][c], f[i], acc[i]);
-                }
-            }
-        }
-    }
-}
-
-// Sums the per-sample partials of a wave's sub-waves (samples that share
-// channels): a butterfly over the sub-wave index.
-template <int CPL>
-__device__ __forceinline__ void reduce_subwaves(const Lanes& q, float* acc) {
-    for (int s = q.lps; s < 64; s <<= 1) {
-#pragma unroll
-        for (int i = 0; i < CPL; ++i) acc[i] += xor_shuffle(acc[i], s);
-    }
 }
 
 // The forward of one anchor (index ba = b*A + a of `a`) by the whole

@@ -1,0 +1,175 @@
+// The per-chunk work of the MSDA gathers, shared by every work order
+// (anchor order, view order, visible views): the forward's accumulation of
+// a staged chunk of (keypoint, camera) pairs, and the backward's gradients
+// of one. The staging itself (weights, corner taps, records) is in
+// msda_common.h.
+#pragma once
+
+#include "msda_common.h"
+
+namespace msda {
+
+// Adds the staged chunk's nj pairs into acc: each group of lanes takes a
+// pair and loads the 4 corners of 4 levels at a time (padded levels read
+// zeros without touching memory) before using them.
+template <class FT, int CPL>
+__device__ __forceinline__ void fwd_chunk(const StageSlot& st, int nj, int L, int G,
+                                          const Lanes& q, rsrc_t feat, float* acc) {
+    using RowT = Row<FT, CPL>;
+    const int LG = L * G, Lp = padded_levels(L);
+    for (int jj = q.sub; jj < nj; jj += q.spw) {
+        const float* wj = st.w + jj * LG + q.g;
+        const Taps* tj = st.taps + jj * Lp;
+        for (int l0 = 0; l0 < Lp; l0 += 4) {
+            u32 raw[4][4][RowT::kWords];
+            float cw[4][4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const Taps t = tj[l0 + k];
+                // a padded level has zero taps; any real weight keeps them zero
+                const float wl = wj[min(l0 + k, L - 1) * G];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    cw[k][c] = t.cw[c] * wl;
+                    load_words<RowT::kWords>(feat, t.off[c] + q.lane_off, raw[k][c]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    float f[CPL];
+                    widen<FT, CPL>(raw[k][c], f);
+#pragma unroll
+                    for (int i = 0; i < CPL; ++i) acc[i] = fmaf(cw[k][c], f[i], acc[i]);
+                }
+            }
+        }
+    }
+}
+
+// Sums the per-sample partials of a wave's sub-waves (samples that share
+// channels): a butterfly over the sub-wave index.
+template <int CPL>
+__device__ __forceinline__ void reduce_subwaves(const Lanes& q, float* acc) {
+    for (int s = q.lps; s < 64; s <<= 1) {
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) acc[i] += xor_shuffle(acc[i], s);
+    }
+}
+
+// Per-anchor context of the backward gather: grad_out row in registers and
+// the anchor's output and record bases.
+struct BwdAnchor {
+    const float* gw;       // weights of the anchor [P*N][L*G]
+    const float* gl;       // locations [P*N][2]
+    float* gwout;          // grad_weights of the anchor (or nullptr)
+    float* glout;          // grad_sampling_loc of the anchor (or nullptr)
+    float* gacc;           // atomic grad_feat: FP32 accumulator row base + c0 (or nullptr)
+    RecordSink rec;        // sorted grad_feat records
+    rsrc_t feat;
+};
+
+template <class FT, int CPL>
+__device__ __forceinline__ BwdAnchor bwd_anchor_ctx(const OpArgs& a, int ba, const Lanes& q,
+                                                    float* go) {
+    const int b = ba / a.A;
+    const int npairs = a.P * a.N;
+    const int LG = a.L * a.G;
+    BwdAnchor x;
+    x.gw = a.w + (size_t)ba * npairs * LG;
+    x.gl = a.loc + (size_t)ba * npairs * 2;
+    x.gwout = a.grad_w ? a.grad_w + (size_t)ba * npairs * LG : nullptr;
+    x.glout = a.grad_loc ? a.grad_loc + (size_t)ba * npairs * 2 : nullptr;
+    x.gacc = a.gfeat_acc ? a.gfeat_acc + (size_t)b * a.R * a.C + q.c0 : nullptr;
+    x.rec.key = a.rec_key;
+    x.rec.frac = a.rec_frac;
+    x.rec.base = a.sample_offset + (u32)ba * (u32)npairs * (u32)a.L;
+    x.rec.cell_base = a.cell_offset + (u32)b * a.cells_per_item;
+    x.rec.no_cell = a.no_cell;
+    x.rec.val = nullptr;
+    x.rec.cbase = 0u;
+    x.feat = make_rsrc(static_cast<const char*>(a.feat) + (size_t)b * a.batch_bytes,
+                       a.batch_bytes);
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) go[i] = a.grad_out[(size_t)ba * a.C + q.c0 + i];
+    return x;
+}
+
+// The gradients of one staged chunk of nj pairs. Per sample it re-gathers
+// the 4 corners and forms d[c] = <grad_out, corner c> over the lane's
+// channels; grad_w is a shuffle reduction over the group's lanes, grad_loc
+// one over the sample's lanes per pair; the atomic grad_feat form adds
+// w * cw * grad_out into the FP32 accumulator.
+template <class FT, int CPL>
+__device__ __forceinline__ void bwd_chunk(const OpArgs& a, const StageSlot& st, int nj,
+                                          const Geo* geo, const Lanes& q, const BwdAnchor& x,
+                                          const float* go) {
+    using RowT = Row<FT, CPL>;
+    const int L = a.L, G = a.G, LG = L * G;
+    const int lpg = (a.C / a.G) / CPL;             // lanes of one group (a power of two)
+    const bool need_vals = x.gwout || x.glout;
+    // byte offset of a row -> float offset in the FP32 accumulator
+    constexpr int kOffToAcc = FT::kBytes == 4 ? 2 : FT::kBytes == 2 ? 1 : 0;
+    for (int jj = q.sub; jj < nj; jj += q.spw) {
+        const u32 src = st.src[jj];
+        const int n = (int)st.cam[jj];
+        const float* wj = st.w + jj * LG + q.g;
+        const Taps* tj = st.taps + jj * padded_levels(L);
+        const float2* fj = st.frac + jj * padded_levels(L);
+        float gx = 0.f, gy = 0.f;
+        for (int l = 0; l < L; ++l) {
+            const Taps t = tj[l];
+            const float wl = wj[l * G];
+            if (x.gacc) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if (t.off[c] != kOOB) {
+                        float* dst = x.gacc + (t.off[c] >> kOffToAcc);
+                        const float cwl = t.cw[c] * wl;
+#pragma unroll
+                        for (int i = 0; i < CPL; ++i) unsafeAtomicAdd(dst + i, cwl * go[i]);
+                    }
+                }
+            }
+            if (!need_vals) continue;
+            u32 raw[4][RowT::kWords];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                load_words<RowT::kWords>(x.feat, t.off[c] + q.lane_off, raw[c]);
+            float d[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                float f[CPL];
+                widen<FT, CPL>(raw[c], f);
+                float sum = 0.f;
+#pragma unroll
+                for (int i = 0; i < CPL; ++i) sum = fmaf(go[i], f[i], sum);
+                d[c] = sum;
+            }
+            if (x.gwout) {
+                float tw = t.cw[0] * d[0] + t.cw[1] * d[1] + t.cw[2] * d[2] + t.cw[3] * d[3];
+                for (int sft = 1; sft < lpg; sft <<= 1) tw += xor_shuffle(tw, sft);
+                if ((q.lane & (lpg - 1)) == 0) x.gwout[(size_t)src * LG + l * G + q.g] = tw;
+            }
+            // d val / dx = hy (F01 - F00) + ly (F11 - F10); x = u W - 0.5
+            const Geo gm = geo[n * L + l];
+            const float2 fr = fj[l];
+            const float hx = 1.f - fr.x, hy = 1.f - fr.y;
+            gx += (float)gm.W * wl * (hy * (d[1] - d[0]) + fr.y * (d[3] - d[2]));
+            gy += (float)gm.H * wl * (hx * (d[2] - d[0]) + fr.x * (d[3] - d[1]));
+        }
+        if (x.glout) {
+            for (int s = 1; s < q.lps; s <<= 1) {
+                gx += xor_shuffle(gx, s);
+                gy += xor_shuffle(gy, s);
+            }
+            if ((q.lane & (q.lps - 1)) == 0) {
+                x.glout[(size_t)src * 2] = gx;
+                x.glout[(size_t)src * 2 + 1] = gy;
+            }
+        }
+    }
+}
+
+}  // namespace msda

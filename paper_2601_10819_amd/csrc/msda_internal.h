@@ -110,6 +110,18 @@ struct BatchArgs {
 
 enum FeatType { kF32 = 0, kBF16 = 1, kFP8 = 2 };
 
+// Keypoint projection (device pointers).
+struct ProjArgs {
+    const float* anchors;         // [B][A][10] x, y, z, w, l, h, yaw, vx, vy, vz
+    const float* keypoints;       // [B][A][P][3] box-frame offsets in units of (w, l, h)
+    const float* projection;      // [B][N][3][4]
+    const int32_t* image_hw;      // [N][2] (H, W) pixels
+    float* loc;                   // [B][A][P][N][2]
+    uint8_t* visible;             // [B][A][N]
+    int32_t B, A, P, N;
+    float dt;
+};
+
 // ---------------------------------------------------------------- view order
 //
 // In view order the work of a call -- every (view, anchor) item, a view
@@ -194,13 +206,35 @@ hipError_t launch_gfeat_tiles(const TileArgs& t, int out_dtype, int cpl, hipStre
 // cell_start[N*L], tile_start[N*L + 1] and tile_region[N*L] from the shapes.
 hipError_t launch_region_tables(const int32_t* shapes, int32_t N, int32_t L, uint32_t* cell_start,
                                 uint32_t* tile_start, uint32_t* tile_region, hipStream_t s);
-// Stable sort of the n record keys (keys_a, values = indices) by key in
-// [0, nrows]; *sorted_vals receives the sorted indices (in vals_a or vals_b)
-// and off[0..nrows] the segment starts. scratch: sort_scratch_words(n) words.
+// Stable sort of the n record keys (keys_a; values = the indices, or the
+// caller's in vals_a when vals_given) by key in [0, nrows]; *sorted_vals
+// receives the sorted values (in vals_a or vals_b) and off[0..nrows] the
+// segment starts. n_dev (or nullptr): a device count that caps n at run
+// time. scratch: sort_scratch_words(n) words.
 hipError_t launch_sort_records(uint32_t* keys_a, uint32_t* keys_b, uint32_t* vals_a,
                                uint32_t* vals_b, uint32_t n, uint32_t nrows, uint32_t* scratch,
-                               uint32_t* off, uint32_t** sorted_vals, hipStream_t s);
+                               uint32_t* off, uint32_t** sorted_vals, hipStream_t s,
+                               const uint32_t* n_dev = nullptr, bool vals_given = false);
 size_t sort_scratch_words(uint32_t n);
+// In-place exclusive scan of n words; partial: scan_scratch_words(n) words.
+hipError_t launch_exclusive_scan(uint32_t* x, uint32_t n, uint32_t* partial, hipStream_t s);
+size_t scan_scratch_words(uint32_t n);
+
+// Keypoint projection and the visible-view form (msda_vis.hip).
+hipError_t launch_project_keypoints(const ProjArgs& p, hipStream_t s);
+// place[0..V] = exclusive scan of the view-major visibility flags (place[V]
+// = the number of visible items), items[place[v]] = v, and *rec_count =
+// place[V] * per_item (or nothing when rec_count is nullptr).
+hipError_t launch_visible_items(const uint8_t* visible, int B, int N, int A, uint32_t per_item,
+                                uint32_t* place, uint32_t* items, uint32_t* rec_count,
+                                uint32_t* scan_partial, hipStream_t s);
+hipError_t launch_forward_visible(const OpArgs& a, int dtype, int cpl, int waves, size_t lds,
+                                  const uint32_t* items, const uint32_t* count,
+                                  const uint32_t* place, const uint8_t* visible, float* part,
+                                  hipStream_t s);
+hipError_t launch_backward_visible(const OpArgs& a, int dtype, int cpl, int waves, size_t lds,
+                                   const uint32_t* items, const uint32_t* count,
+                                   uint32_t* rec_val, hipStream_t s);
 int sort_passes(uint32_t max_key);
 
 hipError_t launch_batch_tables(const BatchArgs& b, bool backward, hipStream_t s);

@@ -29,9 +29,10 @@ constexpr int kMaxDigits = 1 << kMaxDigitBits;
 constexpr int kScanTile = 4096;                          // scan: 256 threads x 16
 
 __global__ void __launch_bounds__(kSortThreads)
-radix_hist_kernel(const u32* __restrict__ keys, u32 n, int shift, int bits,
+radix_hist_kernel(const u32* __restrict__ keys, u32 n, const u32* n_dev, int shift, int bits,
                   u32* __restrict__ table, u32 ntiles) {
     __shared__ u32 h[kMaxDigits];
+    if (n_dev) n = min(n, *n_dev);
     const int digits = 1 << bits;
     for (int d = threadIdx.x; d < digits; d += kSortThreads) h[d] = 0;
     __syncthreads();
@@ -109,14 +110,16 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(u32* x, u32 n,
 // of earlier waves + its rank. Only the entries a round sets are cleared.
 __global__ void __launch_bounds__(kSortThreads)
 radix_scatter_kernel(const u32* __restrict__ keys_in, const u32* __restrict__ vals_in,
-                     u32* __restrict__ keys_out, u32* __restrict__ vals_out, u32 n, int shift,
-                     int bits, const u32* __restrict__ table, u32 ntiles) {
+                     u32* __restrict__ keys_out, u32* __restrict__ vals_out, u32 n,
+                     const u32* n_dev, int shift, int bits, const u32* __restrict__ table,
+                     u32 ntiles) {
     __shared__ u32 base_off[kMaxDigits];
     __shared__ u32 running[kMaxDigits];
     __shared__ u32 wcount[kSortThreads / 64][kMaxDigits];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int digits = 1 << bits;
     const u32 mask = (u32)digits - 1u;
+    if (n_dev) n = min(n, *n_dev);
     for (int d = tid; d < digits; d += kSortThreads) {
         base_off[d] = table[(size_t)d * ntiles + blockIdx.x];
         running[d] = 0;
@@ -162,8 +165,9 @@ radix_scatter_kernel(const u32* __restrict__ keys_in, const u32* __restrict__ va
 
 // off[r] = first position whose key is >= r, for r in [0, nrows]; keys are
 // sorted and every key is <= nrows.
-__global__ void segment_bounds_kernel(const u32* __restrict__ keys, u32 n, u32 nrows,
-                                      u32* __restrict__ off) {
+__global__ void segment_bounds_kernel(const u32* __restrict__ keys, u32 n, const u32* n_dev,
+                                      u32 nrows, u32* __restrict__ off) {
+    if (n_dev) n = min(n, *n_dev);
     const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > n) return;
     const u32 lo = i == 0 ? 0u : min(keys[i - 1], nrows) + 1u;
@@ -171,7 +175,7 @@ __global__ void segment_bounds_kernel(const u32* __restrict__ keys, u32 n, u32 n
     for (u32 r = lo; r <= hi; ++r) off[r] = i;
 }
 
-static hipError_t launch_scan(u32* x, u32 n, u32* partial, hipStream_t s) {
+hipError_t launch_exclusive_scan(u32* x, u32 n, u32* partial, hipStream_t s) {
     const u32 tiles = (n + kScanTile - 1) / kScanTile;
     if (tiles == 0) return hipSuccess;
     mark_begin("scan_reduce", s);
@@ -185,6 +189,8 @@ static hipError_t launch_scan(u32* x, u32 n, u32* partial, hipStream_t s) {
     mark_end(s);
     return hipGetLastError();
 }
+
+size_t scan_scratch_words(u32 n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
 size_t sort_scratch_words(u32 n) {
     const u32 ntiles = (n + kSortTile - 1) / kSortTile;
@@ -211,39 +217,41 @@ int sort_passes(u32 max_key) {
 
 hipError_t launch_sort_records(u32* keys_a, u32* keys_b, u32* vals_a, u32* vals_b, u32 n,
                                u32 nrows, u32* scratch, u32* off, u32** sorted_vals,
-                               hipStream_t s) {
+                               hipStream_t s, const u32* n_dev, bool vals_given) {
     hipError_t e = hipSuccess;
     const u32 ntiles = (n + kSortTile - 1) / kSortTile;
     u32* table = scratch;
     u32* partial = scratch + (size_t)kMaxDigits * ntiles;
     u32* kin = keys_a;
     u32* kout = keys_b;
-    u32* vin = nullptr;       // first pass: values are the indices
-    u32* vout = vals_a;
+    // first pass: values are the indices, or the caller's (in vals_a)
+    u32* vin = vals_given ? vals_a : nullptr;
+    u32* vout = vals_given ? vals_b : vals_a;
     int passes, bits;
     sort_plan(nrows, &passes, &bits);
     for (int p = 0; p < passes && n > 0; ++p) {
         const int shift = bits * p;
         mark_begin("radix_hist", s);
         hipLaunchKernelGGL(radix_hist_kernel, dim3(ntiles), dim3(kSortThreads), 0, s, kin, n,
-                           shift, bits, table, ntiles);
+                           n_dev, shift, bits, table, ntiles);
         mark_end(s);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = launch_scan(table, (u32)(ntiles << bits), partial, s)) != hipSuccess) return e;
+        if ((e = launch_exclusive_scan(table, (u32)(ntiles << bits), partial, s)) != hipSuccess)
+            return e;
         mark_begin("radix_scatter", s);
         hipLaunchKernelGGL(radix_scatter_kernel, dim3(ntiles), dim3(kSortThreads), 0, s, kin, vin,
-                           kout, vout, n, shift, bits, table, ntiles);
+                           kout, vout, n, n_dev, shift, bits, table, ntiles);
         mark_end(s);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // next pass reads what this one wrote
         u32* t = kin; kin = kout; kout = t;
         vin = vout;
-        vout = (vout == vals_a) ? vals_b : vals_a;
+        vout = (vin == vals_a) ? vals_b : vals_a;
     }
-    *sorted_vals = vin;      // nullptr when n == 0
+    *sorted_vals = vin;      // nullptr when n == 0 and no values were given
     mark_begin("segment_bounds", s);
     hipLaunchKernelGGL(segment_bounds_kernel, dim3((n + 1 + 255) / 256), dim3(256), 0, s, kin, n,
-                       nrows, off);
+                       n_dev, nrows, off);
     mark_end(s);
     return hipGetLastError();
 }

@@ -209,6 +209,84 @@ def backward(feat, layout: Layout, sampling_loc, weights, grad_out,
     return gf, gl, gw
 
 
+def project_keypoints(anchors, keypoints, projection, image_hw, dt: float, stream=None):
+    """Keypoint projection with motion compensation on the device:
+    (sampling_loc [B, A, P, N, 2] FP32, visible [B, A, N] uint8). anchors
+    [B, A, 10], keypoints [B, A, P, 3], projection [B, N, 3, 4] FP32 and
+    image_hw [N, 2] int32, all on the device."""
+    lib = _lib.load()
+    _need_cuda_contig("anchors", anchors, torch.float32)
+    _need_cuda_contig("keypoints", keypoints, torch.float32)
+    _need_cuda_contig("projection", projection, torch.float32)
+    _need_cuda_contig("image_hw", image_hw, torch.int32)
+    B, A, P, three = keypoints.shape
+    N = projection.shape[1]
+    if three != 3 or anchors.shape != (B, A, 10) or projection.shape != (B, N, 3, 4) or \
+            image_hw.shape != (N, 2):
+        raise ValueError("anchors [B,A,10], keypoints [B,A,P,3], projection [B,N,3,4], "
+                         "image_hw [N,2]")
+    loc = torch.empty(B, A, P, N, 2, dtype=torch.float32, device=anchors.device)
+    vis = torch.empty(B, A, N, dtype=torch.uint8, device=anchors.device)
+    d = _lib.MsdaProjDesc(B, A, P, N, float(dt))
+    _lib.check(lib.msda_project_keypoints(_ptr(anchors), _ptr(keypoints), _ptr(projection),
+                                          _ptr(image_hw), _ptr(loc), _ptr(vis), ctypes.byref(d),
+                                          _stream(stream)))
+    return loc, vis
+
+
+def _need_visible(visible, sampling_loc):
+    _need_cuda_contig("visible", visible, torch.uint8)
+    B, A, _, N, _ = sampling_loc.shape
+    if visible.shape != (B, A, N):
+        raise ValueError(f"visible must be [B, A, Ncam] = {(B, A, N)}, got {tuple(visible.shape)}")
+
+
+def forward_visible(feat, layout: Layout, sampling_loc, weights, visible, level_scale=None,
+                    tile=None, out: Optional[torch.Tensor] = None,
+                    workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """out [B, A, C] = MSDA over the visible (anchor, camera) pairs only."""
+    lib = _lib.load()
+    _need_cuda_contig("feat", feat)
+    _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
+    _need_cuda_contig("weights", weights, torch.float32)
+    _need_visible(visible, sampling_loc)
+    d = make_desc(feat, layout, sampling_loc, weights, level_scale, tile=tile)
+    if out is None:
+        out = torch.empty(d.batch, d.num_anchors, d.channels, device=feat.device,
+                          dtype=torch.float32)
+    ws_ptr, ws_len, workspace = _workspace(
+        int(lib.msda_forward_visible_workspace_size(ctypes.byref(d))), workspace, feat.device)
+    _lib.check(lib.msda_forward_visible(_ptr(feat), _ptr(layout.shapes), _ptr(layout.starts),
+                                        _ptr(sampling_loc), _ptr(weights), _ptr(visible),
+                                        _ptr(out), ws_ptr, ws_len, ctypes.byref(d),
+                                        _stream(stream)))
+    return out
+
+
+def backward_visible(feat, layout: Layout, sampling_loc, weights, visible, grad_out,
+                     need_feat=True, need_loc=True, need_w=True, tile=None,
+                     workspace: Optional[torch.Tensor] = None, stream=None):
+    """(grad_feat, grad_sampling_loc, grad_weights) of the visible-view form;
+    the gradients of invisible pairs are zero."""
+    lib = _lib.load()
+    _need_cuda_contig("feat", feat)
+    _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
+    _need_cuda_contig("weights", weights, torch.float32)
+    _need_cuda_contig("grad_out", grad_out, torch.float32)
+    _need_visible(visible, sampling_loc)
+    d = make_desc(feat, layout, sampling_loc, weights, tile=tile)
+    gf = torch.empty_like(feat) if need_feat else None
+    gl = torch.empty_like(sampling_loc) if need_loc else None
+    gw = torch.empty_like(weights) if need_w else None
+    ws_ptr, ws_len, workspace = _workspace(
+        int(lib.msda_backward_visible_workspace_size(ctypes.byref(d))), workspace, feat.device)
+    _lib.check(lib.msda_backward_visible(_ptr(feat), _ptr(layout.shapes), _ptr(layout.starts),
+                                         _ptr(sampling_loc), _ptr(weights), _ptr(visible),
+                                         _ptr(grad_out), _ptr(gf), _ptr(gl), _ptr(gw), ws_ptr,
+                                         ws_len, ctypes.byref(d), _stream(stream)))
+    return gf, gl, gw
+
+
 def quantize_fp8(feat_f32: torch.Tensor, layout: Layout, stream=None):
     """Per-level FP8 e4m3 quantisation on the device: (codes uint8 [B,R,C],
     level_scale float32 [L]) with scale_l = amax_l / 448."""

@@ -332,3 +332,52 @@ def test_view_partition_covers_every_item_once():
                     seen.add((b, a, n))
         assert len(seen) == B * N * A
         assert max(sizes) - min(sizes) <= 1
+
+
+def test_projection_validation(lib):
+    d = _lib.MsdaProjDesc(1, 4, 3, 2, 0.1)
+    expect(lib, lib.msda_project_keypoints(FAKE, FAKE, FAKE, FAKE, FAKE, None, ctypes.byref(d),
+                                           None), INV, "NULL")
+    bad = _lib.MsdaProjDesc(1, 4, 0, 2, 0.1)
+    expect(lib, lib.msda_project_keypoints(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(bad),
+                                           None), INV, "positive")
+    nan = _lib.MsdaProjDesc(1, 4, 3, 2, float("nan"))
+    expect(lib, lib.msda_project_keypoints(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(nan),
+                                           None), INV, "NaN")
+    big = _lib.MsdaProjDesc(1 << 10, 1 << 12, 13, 64, 0.0)
+    expect(lib, lib.msda_project_keypoints(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(big),
+                                           None), UNS, "2^31")
+    empty = _lib.MsdaProjDesc(1, 0, 3, 2, 0.0)
+    assert lib.msda_project_keypoints(None, None, None, None, None, None, ctypes.byref(empty),
+                                      None) == _lib.MSDA_OK
+
+
+def test_visible_form_validation(lib):
+    d = desc(Geo(), B=2, A=4, C=32)
+    need_f = lib.msda_forward_visible_workspace_size(ctypes.byref(d))
+    need_b = lib.msda_backward_visible_workspace_size(ctypes.byref(d))
+    # compaction + one partial row per (batch item, camera, anchor)
+    assert need_f >= 2 * 2 * 4 * 32 * 4
+    assert need_b > lib.msda_backward_workspace_size(ctypes.byref(d))
+    fwdv = lambda vis, ws, n: lib.msda_forward_visible(FAKE, FAKE, FAKE, FAKE, FAKE, vis,
+                                                       FAKE + 4096, ws, n, ctypes.byref(d), None)
+    expect(lib, fwdv(None, FAKE + (1 << 20), need_f), INV, "NULL")
+    expect(lib, fwdv(FAKE, None, 0), WS, "workspace")
+    expect(lib, fwdv(FAKE, FAKE + (1 << 20), need_f - 1), WS)
+    bwdv = lambda vis, ws, n: lib.msda_backward_visible(FAKE, FAKE, FAKE, FAKE, FAKE, vis, FAKE,
+                                                        FAKE + 8192, FAKE, FAKE, ws, n,
+                                                        ctypes.byref(d), None)
+    expect(lib, bwdv(None, FAKE + (1 << 20), need_b), INV, "visible")
+    expect(lib, bwdv(FAKE, FAKE + (1 << 20), need_b - 1), WS)
+    # anchor order cannot serve the visible-view form; nor can atomic grad_feat
+    da = desc(Geo(), B=2, A=4, C=32, tile=(0, 0, _lib.MSDA_ORDER_ANCHOR, 0))
+    expect(lib, lib.msda_forward_visible(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
+                                         1 << 30, ctypes.byref(da), None), UNS, "view order")
+    dt = desc(Geo(), B=2, A=4, C=32, tile=(0, 0, 0, _lib.MSDA_SCATTER_ATOMIC))
+    expect(lib, lib.msda_backward_visible(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
+                                          FAKE, FAKE, 1 << 30, ctypes.byref(dt), None), UNS,
+           "sorted")
+    # no anchors: nothing to do
+    d0 = desc(Geo(), B=2, A=0, C=32)
+    assert lib.msda_forward_visible(FAKE, FAKE, FAKE, None, None, None, None, None, 0,
+                                    ctypes.byref(d0), None) == _lib.MSDA_OK
