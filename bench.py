@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cold", action="store_true",
                     help="skip the cold-cache steps (1 GiB write before each step)")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 forward")
+    ap.add_argument("--no-visible", action="store_true",
+                    help="skip the projection + visible-view steps (outside-in camera network)")
     ap.add_argument("--cpu-anchors", type=int, default=0,
                     help="anchors in the oracle's timed sample (0 = all of them)")
     return ap.parse_args()
@@ -293,6 +295,72 @@ def run_batched(torch, ops, synth, steps, warmup):
     }
 
 
+def run_visible(torch, ops, synth, p, steps, warmup):
+    """The 64-camera pyramid (BF16) with the sampling locations produced by
+    the projection step from an outside-in camera network (anchors seen by
+    a fraction of the cameras): one step = projection + visible-view forward
+    + backward, each kernel timed with the library's HIP-event hook."""
+    lib = ops._lib.load()
+    dev = "cuda"
+    g = synth.outside_in(seed=0, cams=p.num_cams, anchors=p.num_anchors, P=p.num_points)
+    anchors, keypoints = g.anchors.to(dev), g.keypoints.to(dev)
+    projection, image_hw = g.projection.to(dev), g.image_hw.to(dev)
+    feat = p.feat.to(torch.bfloat16).to(dev)
+    layout = ops.Layout(p.spatial_shapes, p.level_start_index, dev)
+    w = p.weights.to(dev)
+    go = synth.grad_out_like(p, seed=1).to(dev)
+    out = torch.empty(p.batch, p.num_anchors, p.channels, device=dev)
+    loc, vis = ops.project_keypoints(anchors, keypoints, projection, image_hw, g.dt)
+    d = ops.make_desc(feat, layout, loc, w)
+    fws = torch.empty(int(lib.msda_forward_visible_workspace_size(ctypes.byref(d))) + 256,
+                      dtype=torch.uint8, device=dev)
+    bws = torch.empty(int(lib.msda_backward_visible_workspace_size(ctypes.byref(d))) + 256,
+                      dtype=torch.uint8, device=dev)
+
+    def step():
+        l, v = ops.project_keypoints(anchors, keypoints, projection, image_hw, g.dt)
+        ops.forward_visible(feat, layout, l, w, v, out=out, workspace=fws)
+        ops.backward_visible(feat, layout, l, w, v, go, workspace=bws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = HipEvents()
+    cap = 40
+    per_kernel, steps_ms = {}, []
+    arr = (ctypes.c_void_p * (2 * cap))()
+    for i in range(2 * cap):
+        arr[i] = ev.create()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ops._lib.check(lib.msda_set_kernel_events(arr, cap))
+        step()
+        k = lib.msda_recorded_kernels()
+        names = [lib.msda_recorded_kernel_name(j).decode() for j in range(k)]
+        ops._lib.check(lib.msda_set_kernel_events(None, 0))
+        torch.cuda.synchronize()
+        for j, name in enumerate(names):
+            per_kernel.setdefault(name, []).append(ev.elapsed_ms(arr[2 * j], arr[2 * j + 1]))
+        steps_ms.append(ev.elapsed_ms(arr[0], arr[2 * k - 1]))
+    t1 = time.perf_counter()
+    for e in arr:
+        ev.destroy(e)
+    frac = float(vis.float().mean())
+    S = p.samples
+    st = pct(steps_ms)
+    return {
+        "workload": "scene_64cam_outside_in",
+        "visible_pair_fraction": round(frac, 4),
+        "visible_samples_per_step": int(round(S * frac)),
+        "step_ms": st,
+        "wall_ms_per_step": round((t1 - t0) / steps * 1e3, 4),
+        "value_visible": round(S * frac / (st["median"] * 1e-3) / 1e9, 4),
+        "value_nominal": round(S / (st["median"] * 1e-3) / 1e9, 4),
+        "unit": "GSamples/s (visible samples / nominal B*A*P*N*L samples per step time)",
+        "kernels_ms": {n: round(sum(v) / len(v), 4) for n, v in per_kernel.items()},
+    }
+
+
 def copy_bandwidth(torch, ops, nbytes=1 << 30, reps=10):
     """Achievable streaming bandwidth (read + write) of the library's copy kernel."""
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -423,6 +491,9 @@ def main():
         f8 = run_fp8_forward(torch, ops, p, args.steps, args.warmup)
         res["fp8_forward"] = {"ms": f8, "value": round(S / (f8["median"] * 1e-3) / 1e9, 4),
                               "unit": "GSamples/s (forward only)"}
+    if not args.no_visible:
+        res["visible"] = run_visible(torch, ops, synth, p, args.steps, args.warmup)
+        print(f"# visible done: {res['visible']}", file=sys.stderr, flush=True)
     if not args.no_batched:
         res["batched"] = run_batched(torch, ops, synth, args.steps, args.warmup)
         print(f"# batched done: {res['batched']}", file=sys.stderr, flush=True)

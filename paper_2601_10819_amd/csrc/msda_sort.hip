@@ -175,6 +175,23 @@ __global__ void segment_bounds_kernel(const u32* __restrict__ keys, u32 n, const
     for (u32 r = lo; r <= hi; ++r) off[r] = i;
 }
 
+// The same bounds by a binary search per cell: used when n is a device
+// count (the visible-view form), where the records cover few cells and the
+// per-record form would leave a thread to fill a long run of empty cells.
+__global__ void segment_bounds_search_kernel(const u32* __restrict__ keys, u32 n,
+                                             const u32* n_dev, u32 nrows,
+                                             u32* __restrict__ off) {
+    const u32 r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > nrows) return;
+    if (n_dev) n = min(n, *n_dev);
+    u32 lo = 0, hi = n;                       // first position with key >= r
+    while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (keys[mid] < r) lo = mid + 1; else hi = mid;
+    }
+    off[r] = lo;
+}
+
 hipError_t launch_exclusive_scan(u32* x, u32 n, u32* partial, hipStream_t s) {
     const u32 tiles = (n + kScanTile - 1) / kScanTile;
     if (tiles == 0) return hipSuccess;
@@ -250,8 +267,12 @@ hipError_t launch_sort_records(u32* keys_a, u32* keys_b, u32* vals_a, u32* vals_
     }
     *sorted_vals = vin;      // nullptr when n == 0 and no values were given
     mark_begin("segment_bounds", s);
-    hipLaunchKernelGGL(segment_bounds_kernel, dim3((n + 1 + 255) / 256), dim3(256), 0, s, kin, n,
-                       n_dev, nrows, off);
+    if (n_dev)
+        hipLaunchKernelGGL(segment_bounds_search_kernel, dim3((nrows + 1 + 255) / 256), dim3(256),
+                           0, s, kin, n, n_dev, nrows, off);
+    else
+        hipLaunchKernelGGL(segment_bounds_kernel, dim3((n + 1 + 255) / 256), dim3(256), 0, s, kin,
+                           n, n_dev, nrows, off);
     mark_end(s);
     return hipGetLastError();
 }
