@@ -124,3 +124,60 @@ def backward_visible(feat, spatial_shapes, level_start_index, sampling_loc, weig
     gl = gl * vis[:, :, None, :, None]
     gw = gw * vis[:, :, None, :, None, None]
     return gf, gl, gw
+
+
+def _scores(view_score, visible):
+    s = np.asarray(view_score.numpy() if hasattr(view_score, "numpy") else view_score,
+                   dtype=np.float64)
+    return s * np.asarray(visible, dtype=bool)
+
+
+def forward_fused(feat, spatial_shapes, level_start_index, sampling_loc, weights, visible,
+                  view_score):
+    """Visibility-weighted fusion (Sec. 3.2, Eq. 2): f = sum_n v_n g_n / sum_n
+    v_n over the visible cameras, g_n the anchor's aggregated feature in
+    camera n alone (the visible-view sum restricted to camera n); f = 0 when
+    the scores of the visible cameras sum to 0. Also returns the per-camera
+    features g [B, A, N, C]."""
+    vis = np.asarray(visible, dtype=bool)
+    B, A, N = vis.shape
+    g = []
+    for n in range(N):
+        only = np.zeros_like(vis)
+        only[:, :, n] = vis[:, :, n]
+        g.append(forward_visible(feat, spatial_shapes, level_start_index, sampling_loc, weights,
+                                 only))
+    g = np.stack(g, axis=2)                                  # [B, A, N, C]
+    v = _scores(view_score, vis)
+    V = v.sum(axis=2)                                       # [B, A]
+    safe = np.where(V > 0, V, 1.0)
+    f = (v[..., None] * g).sum(axis=2) / safe[..., None]
+    f[V <= 0] = 0.0
+    return f, g
+
+
+def backward_fused(feat, spatial_shapes, level_start_index, sampling_loc, weights, visible,
+                   view_score, grad_out):
+    """Gradients of forward_fused: the visible-view gradients with grad_out
+    scaled per camera by v_n / V (grad_feat, grad_loc, grad_weights), and
+    grad_score[b, a, n] = <grad_out, g_n - f> / V for visible cameras (0
+    otherwise, and 0 when V = 0)."""
+    vis = np.asarray(visible, dtype=bool)
+    v = _scores(view_score, vis)
+    V = v.sum(axis=2)
+    vt = np.where(V[..., None] > 0, v / np.where(V > 0, V, 1.0)[..., None], 0.0)   # [B, A, N]
+    # the fused output is the visible-view operator with weights w * vt
+    w = np.asarray(weights.numpy() if hasattr(weights, "numpy") else weights, dtype=np.float64)
+    w_eff = w * vt[:, :, None, :, None, None]
+    gf, gl, gw_eff = backward_visible(feat, spatial_shapes, level_start_index, sampling_loc,
+                                      w_eff, vis, grad_out)
+    # d f / d w = vt * (d out_visible / d w_eff): grad_w = vt * raw grad_w
+    _, _, gw_raw = backward_visible(feat, spatial_shapes, level_start_index, sampling_loc, w,
+                                    vis, grad_out)
+    gw = gw_raw * vt[:, :, None, :, None, None]
+    f, g = forward_fused(feat, spatial_shapes, level_start_index, sampling_loc, weights, vis,
+                         view_score)
+    go = np.asarray(grad_out, dtype=np.float64)
+    dots = np.einsum("bac,banc->ban", go, g) - np.einsum("bac,bac->ba", go, f)[..., None]
+    gs = np.where(vis & (V[..., None] > 0), dots / np.where(V > 0, V, 1.0)[..., None], 0.0)
+    return gf, gl, gw, gs

@@ -144,3 +144,74 @@ def test_sparse_backward_zero_for_invisible_pairs(oracle_mod):
     e = float((out * go).sum())
     assert abs(float((gw * p.weights.numpy()).sum()) - e) <= 1e-12 * max(1.0, abs(e))
     assert abs(float((gf * p.feat.numpy()).sum()) - e) <= 1e-12 * max(1.0, abs(e))
+
+
+def fused_case():
+    p = synth.small(seed=23, B=2, cams=4, levels=((6, 7), (3, 4)), C=8, G=2, A=5, P=3)
+    rng = np.random.default_rng(8)
+    vis = rng.random((2, 5, 4)) < 0.7
+    vis[0, 0] = False                                        # an anchor no camera sees
+    score = rng.random((2, 5, 4))
+    return p, vis, score
+
+
+def test_fused_special_cases(oracle_mod):
+    p, vis, score = fused_case()
+    f, g = proj.forward_fused(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                              p.weights, vis, score)
+    assert np.all(f[0, 0] == 0)
+    # equal scores: the mean of the visible cameras' features
+    ones = np.ones_like(score)
+    f1, _ = proj.forward_fused(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                               p.weights, vis, ones)
+    sv = proj.forward_visible(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                              p.weights, vis)
+    cnt = vis.sum(-1)
+    np.testing.assert_allclose(f1[cnt > 0], (sv / np.maximum(cnt, 1)[..., None])[cnt > 0],
+                               rtol=1e-12, atol=1e-13)
+    # a one-hot score picks that camera's feature
+    hot = np.zeros_like(score)
+    hot[1, 2, 3] = 0.4
+    vis2 = vis.copy()
+    vis2[1, 2, 3] = True
+    fh, gh = proj.forward_fused(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                                p.weights, vis2, hot)
+    np.testing.assert_allclose(fh[1, 2], gh[1, 2, 3], rtol=1e-14)
+    # scaling every score of an anchor leaves the fusion unchanged
+    f2, _ = proj.forward_fused(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                               p.weights, vis, 3.5 * score)
+    np.testing.assert_allclose(f2, f, rtol=1e-12, atol=1e-14)
+
+
+def test_fused_gradients_by_finite_differences(oracle_mod):
+    """grad_score and grad_w of the fusion against central differences of
+    <grad_out, f> in FP64."""
+    p, vis, score = fused_case()
+    go = synth.grad_out_like(p, seed=6).numpy().astype(np.float64)
+    gf, gl, gw, gs = proj.backward_fused(p.feat, p.spatial_shapes, p.level_start_index,
+                                         p.sampling_loc, p.weights, vis, score, go)
+
+    def loss(sc=score, w=p.weights.numpy()):
+        f, _ = proj.forward_fused(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                                  w, vis, sc)
+        return float((f * go).sum())
+
+    h = 1e-6
+    for (b, a, n) in [(1, 2, 1), (0, 3, 2), (1, 4, 0), (0, 1, 3)]:
+        d = np.zeros_like(score)
+        d[b, a, n] = h
+        fd = (loss(score + d) - loss(score - d)) / (2 * h)
+        assert abs(fd - gs[b, a, n]) <= 1e-7 * max(1.0, abs(fd)), (b, a, n, fd, gs[b, a, n])
+        if not vis[b, a, n]:
+            assert gs[b, a, n] == 0.0
+    w0 = p.weights.numpy().astype(np.float64)
+    for idx in [(1, 2, 0, 1, 0, 1), (0, 3, 2, 2, 1, 0)]:
+        d = np.zeros_like(w0)
+        d[idx] = h
+        fd = (loss(w=w0 + d) - loss(w=w0 - d)) / (2 * h)
+        assert abs(fd - gw[idx]) <= 1e-7 * max(1.0, abs(fd)), (idx, fd, gw[idx])
+    # the Euler identity in the features: f is linear in feat
+    f, _ = proj.forward_fused(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                              p.weights, vis, score)
+    e = float((f * go).sum())
+    assert abs(float((gf * p.feat.numpy()).sum()) - e) <= 1e-12 * max(1.0, abs(e))
