@@ -295,11 +295,13 @@ def run_batched(torch, ops, synth, steps, warmup):
     }
 
 
-def run_visible(torch, ops, synth, p, steps, warmup):
+def run_visible(torch, ops, synth, p, steps, warmup, fused=False):
     """The 64-camera pyramid (BF16) with the sampling locations produced by
     the projection step from an outside-in camera network (anchors seen by
     a fraction of the cameras): one step = projection + visible-view forward
-    + backward, each kernel timed with the library's HIP-event hook."""
+    + backward, each kernel timed with the library's HIP-event hook. fused:
+    the visibility-weighted fusion form (seeded positive view scores), with
+    the score gradient."""
     lib = ops._lib.load()
     dev = "cuda"
     g = synth.outside_in(seed=0, cams=p.num_cams, anchors=p.num_anchors, P=p.num_points)
@@ -316,11 +318,17 @@ def run_visible(torch, ops, synth, p, steps, warmup):
                       dtype=torch.uint8, device=dev)
     bws = torch.empty(int(lib.msda_backward_visible_workspace_size(ctypes.byref(d))) + 256,
                       dtype=torch.uint8, device=dev)
+    gen = torch.Generator().manual_seed(2)
+    score = (torch.rand(vis.shape, generator=gen) + 0.05).to(dev)
 
     def step():
         l, v = ops.project_keypoints(anchors, keypoints, projection, image_hw, g.dt)
-        ops.forward_visible(feat, layout, l, w, v, out=out, workspace=fws)
-        ops.backward_visible(feat, layout, l, w, v, go, workspace=bws)
+        if fused:
+            ops.forward_fused(feat, layout, l, w, v, score, out=out, workspace=fws)
+            ops.backward_fused(feat, layout, l, w, v, score, out, go, workspace=bws)
+        else:
+            ops.forward_visible(feat, layout, l, w, v, out=out, workspace=fws)
+            ops.backward_visible(feat, layout, l, w, v, go, workspace=bws)
 
     for _ in range(warmup):
         step()
@@ -349,7 +357,7 @@ def run_visible(torch, ops, synth, p, steps, warmup):
     S = p.samples
     st = pct(steps_ms)
     return {
-        "workload": "scene_64cam_outside_in",
+        "workload": "scene_64cam_outside_in" + ("_fused" if fused else ""),
         "visible_pair_fraction": round(frac, 4),
         "visible_samples_per_step": int(round(S * frac)),
         "step_ms": st,
@@ -494,6 +502,9 @@ def main():
     if not args.no_visible:
         res["visible"] = run_visible(torch, ops, synth, p, args.steps, args.warmup)
         print(f"# visible done: {res['visible']}", file=sys.stderr, flush=True)
+        res["visible_fused"] = run_visible(torch, ops, synth, p, args.steps, args.warmup,
+                                           fused=True)
+        print(f"# fused done: {res['visible_fused']}", file=sys.stderr, flush=True)
     if not args.no_batched:
         res["batched"] = run_batched(torch, ops, synth, args.steps, args.warmup)
         print(f"# batched done: {res['batched']}", file=sys.stderr, flush=True)

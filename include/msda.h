@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define MSDA_ABI_VERSION 3
+#define MSDA_ABI_VERSION 4
 
 typedef enum msda_status {
     MSDA_OK = 0,
@@ -235,6 +235,39 @@ msda_status msda_backward_visible(const void* feat, const int32_t* spatial_shape
                                   float* grad_sampling_loc, float* grad_weights, void* workspace,
                                   size_t workspace_bytes, const msda_desc* desc, void* stream);
 size_t msda_backward_visible_workspace_size(const msda_desc* desc);
+
+/*
+ * Visibility-weighted fusion over the visible views (paper Sec. 3.2, Eq. 2):
+ * the anchor's feature in camera n alone, g_n = the visible-view sum over
+ * camera n's samples, is weighted by the camera's visibility score,
+ *   V[b][a] = sum over visible n of view_score[b][a][n]
+ *   out[b][a] = sum over visible n of view_score[b][a][n] / V * g_n
+ * (out = 0 when V <= 0). view_score: FP32 [B][A][Ncam], device (scores of
+ * invisible cameras are ignored). The backward returns the visible-view
+ * gradients with grad_out scaled per camera by view_score / V, and
+ *   grad_score[b][a][n] = (<grad_out, g_n> - <grad_out, out>) / V
+ * for visible cameras (0 otherwise and when V <= 0); it needs the forward's
+ * out [B][A][C] (FP32, device) when grad_score is requested; any of
+ * grad_feat, grad_sampling_loc, grad_weights, grad_score may be NULL. Cameras
+ * are added in camera order in both passes (deterministic). Layouts, dtypes,
+ * limits and errors as msda_forward_visible / msda_backward_visible;
+ * workspaces (device, 256-byte aligned) of at least the sizes below.
+ */
+msda_status msda_forward_fused(const void* feat, const int32_t* spatial_shapes,
+                               const int32_t* level_start_index, const float* sampling_loc,
+                               const float* weights, const uint8_t* visible,
+                               const float* view_score, float* out, void* workspace,
+                               size_t workspace_bytes, const msda_desc* desc, void* stream);
+size_t msda_forward_fused_workspace_size(const msda_desc* desc);
+msda_status msda_backward_fused(const void* feat, const int32_t* spatial_shapes,
+                                const int32_t* level_start_index, const float* sampling_loc,
+                                const float* weights, const uint8_t* visible,
+                                const float* view_score, const float* out,
+                                const float* grad_out, void* grad_feat,
+                                float* grad_sampling_loc, float* grad_weights,
+                                float* grad_score, void* workspace, size_t workspace_bytes,
+                                const msda_desc* desc, void* stream);
+size_t msda_backward_fused_workspace_size(const msda_desc* desc);
 
 /*
  * Per-level FP8 quantisation of an FP32 feat (the precision form's storage):

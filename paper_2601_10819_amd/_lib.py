@@ -25,14 +25,16 @@ MSDA_FP8_E4M3 = 2
 
 MSDA_DETERMINISTIC = 1
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 # Every symbol include/msda.h declares.
 EXPORTS = (
     "msda_forward", "msda_forward_ws", "msda_forward_workspace_size", "msda_backward",
     "msda_backward_workspace_size", "msda_project_keypoints", "msda_forward_visible",
     "msda_forward_visible_workspace_size", "msda_backward_visible",
-    "msda_backward_visible_workspace_size", "msda_quantize_fp8",
+    "msda_backward_visible_workspace_size", "msda_forward_fused",
+    "msda_forward_fused_workspace_size", "msda_backward_fused",
+    "msda_backward_fused_workspace_size", "msda_quantize_fp8",
     "msda_quantize_workspace_size", "msda_batched_workspace_size", "msda_forward_batched",
     "msda_backward_batched", "msda_stream_copy", "msda_set_kernel_events",
     "msda_recorded_kernels", "msda_recorded_kernel_name", "msda_last_error", "msda_abi_version",
@@ -131,6 +133,14 @@ def load(path: str = LIB_PATH):
     lib.msda_backward_visible.restype = ctypes.c_int
     lib.msda_backward_visible_workspace_size.argtypes = [dp]
     lib.msda_backward_visible_workspace_size.restype = sz
+    lib.msda_forward_fused.argtypes = [vp] * 9 + [sz, dp, vp]
+    lib.msda_forward_fused.restype = ctypes.c_int
+    lib.msda_forward_fused_workspace_size.argtypes = [dp]
+    lib.msda_forward_fused_workspace_size.restype = sz
+    lib.msda_backward_fused.argtypes = [vp] * 14 + [sz, dp, vp]
+    lib.msda_backward_fused.restype = ctypes.c_int
+    lib.msda_backward_fused_workspace_size.argtypes = [dp]
+    lib.msda_backward_fused_workspace_size.restype = sz
     lib.msda_backward.argtypes = [vp] * 10 + [sz, dp, vp]
     lib.msda_backward.restype = ctypes.c_int
     lib.msda_backward_workspace_size.argtypes = [dp]

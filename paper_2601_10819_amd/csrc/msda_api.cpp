@@ -422,7 +422,7 @@ static hipError_t launch_gather(const msda::OpArgs& a, int order, int dtype, int
 // Extra workspace of the visible-view form: the scanned flags (V + 1 words),
 // the scan's scratch, the item list (V words) and the record count.
 struct VisibleWs {
-    size_t place, partial, items, rec_count, total;
+    size_t place, partial, items, rec_count, vt, dot, total;
 };
 
 VisibleWs visible_layout(const msda_desc* d, size_t at) {
@@ -432,7 +432,9 @@ VisibleWs visible_layout(const msda_desc* d, size_t at) {
     w.partial = w.place + align256((V + 1) * 4);
     w.items = w.partial + align256(msda::scan_scratch_words((uint32_t)(V + 1)) * 4);
     w.rec_count = w.items + align256(V * 4 + 4);
-    w.total = w.rec_count + 256;
+    w.vt = w.rec_count + 256;                 // the fused form's per-view weights
+    w.dot = w.vt + align256(V * 4);           // and its per-item score products
+    w.total = w.dot + align256(V * 4);
     return w;
 }
 
@@ -451,12 +453,19 @@ size_t msda_backward_workspace_size(const msda_desc* d) {
 }
 
 // The backward, dense (visible == nullptr) or over the visible views only.
+// The fused form's extra operands (visibility-weighted fusion, Eq. 2).
+struct Fusion {
+    const float* score;     // [B][A][N]
+    const float* out;       // the fused forward output [B][A][C] (for grad_score)
+    float* grad_score;      // [B][A][N], or nullptr
+};
+
 static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes,
                                  const int32_t* level_start_index, const float* sampling_loc,
                                  const float* weights, const uint8_t* visible,
-                                 const float* grad_out, void* grad_feat, float* grad_sampling_loc,
-                                 float* grad_weights, void* workspace, size_t workspace_bytes,
-                                 const msda_desc* desc, void* stream) {
+                                 const Fusion* fuse, const float* grad_out, void* grad_feat,
+                                 float* grad_sampling_loc, float* grad_weights, void* workspace,
+                                 size_t workspace_bytes, const msda_desc* desc, void* stream) {
     if (!desc) return fail(MSDA_ERR_INVALID_ARGUMENT, "desc is NULL");
     // the visible-view gathers walk a compacted item list in ranges per XCD,
     // with the view order's launch shape
@@ -469,6 +478,9 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
     if (!feat || !spatial_shapes || !level_start_index ||
         (a.A > 0 && (!sampling_loc || !weights || !grad_out)))
         return fail(MSDA_ERR_INVALID_ARGUMENT, "a required device pointer is NULL");
+    if (fuse && a.A > 0 && (!fuse->score || (fuse->grad_score && !fuse->out)))
+        return fail(MSDA_ERR_INVALID_ARGUMENT,
+                    "view_score, and out when grad_score is requested, must not be NULL");
     if (!aligned(feat, 16)) return fail(MSDA_ERR_UNSUPPORTED, "feat must be 16-byte aligned");
     if (desc->feat_dtype == MSDA_FP8_E4M3)
         return fail(MSDA_ERR_UNSUPPORTED, "the backward takes FP32 or BF16 features (not FP8)");
@@ -571,6 +583,7 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
             return hip_fail(e, "zero grad_feat");
     }
     uint32_t* rec_count = nullptr;
+    float* vt = nullptr;
     if (visible) {
         // invisible pairs take no part: their gradients are zero
         if (a.A > 0 && grad_weights &&
@@ -582,11 +595,19 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
                                         num_samples(desc) / a.L * 2 * sizeof(float), s)) !=
                 hipSuccess)
             return hip_fail(e, "zero grad_sampling_loc");
-        if (a.A > 0 && (grad_feat || grad_sampling_loc || grad_weights)) {
+        float* grad_score = fuse ? fuse->grad_score : nullptr;   // written whole below
+        if (a.A > 0 && (grad_feat || grad_sampling_loc || grad_weights || grad_score)) {
             uint32_t* place = reinterpret_cast<uint32_t*>(ws + VW.place);
             uint32_t* items = reinterpret_cast<uint32_t*>(ws + VW.items);
             rec_count = reinterpret_cast<uint32_t*>(ws + VW.rec_count);
             const size_t V = (size_t)a.B * a.N * a.A;
+            if (fuse) {
+                vt = reinterpret_cast<float*>(ws + VW.vt);
+                if ((e = msda::launch_view_scale(visible, fuse->score, a.B * a.A, a.N, vt, s)) !=
+                    hipSuccess)
+                    return hip_fail(e, "fused view weights");
+            }
+            float* item_dot = grad_score ? reinterpret_cast<float*>(ws + VW.dot) : nullptr;
             if ((e = msda::launch_visible_items(visible, a.B, a.N, a.A, (uint32_t)(a.P * a.L),
                                                 place, items, rec_count,
                                                 reinterpret_cast<uint32_t*>(ws + VW.partial),
@@ -594,8 +615,13 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
                 (e = msda::launch_backward_visible(
                      a, desc->feat_dtype, cpl, waves, msda::lds_bytes_view(a, waves), items,
                      place + V, grad_feat ? reinterpret_cast<uint32_t*>(ws + W.vals_a) : nullptr,
-                     s)) != hipSuccess)
+                     vt, item_dot, s)) != hipSuccess)
                 return hip_fail(e, "msda_backward_visible launch");
+            if (grad_score &&
+                (e = msda::launch_grad_score(grad_out, fuse->out, visible, fuse->score, place,
+                                             item_dot, a.B, a.A, a.N, a.C, grad_score, s)) !=
+                    hipSuccess)
+                return hip_fail(e, "grad_score");
         }
     } else if (a.A > 0 && (grad_feat || grad_sampling_loc || grad_weights) &&
                (e = launch_gather(a, order, desc->feat_dtype, cpl, waves, s)) != hipSuccess) {
@@ -632,6 +658,9 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
     t.C = a.C;
     t.G = a.G;
     t.R = a.R;
+    t.view_scale = vt;
+    t.N = a.N;
+    t.L = a.L;
     t.lps_shift = log2i(a.C / rcpl);
     divmagic((uint32_t)a.P * (uint32_t)a.N * (uint32_t)a.L, &t.magic, &t.magic_shift);
     // Tiles of coarse levels collect many more samples per pixel: they come
@@ -656,7 +685,7 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
                           float* grad_sampling_loc, float* grad_weights, void* workspace,
                           size_t workspace_bytes, const msda_desc* desc, void* stream) {
     return backward_impl(feat, spatial_shapes, level_start_index, sampling_loc, weights, nullptr,
-                         grad_out, grad_feat, grad_sampling_loc, grad_weights, workspace,
+                         nullptr, grad_out, grad_feat, grad_sampling_loc, grad_weights, workspace,
                          workspace_bytes, desc, stream);
 }
 
@@ -670,8 +699,31 @@ msda_status msda_backward_visible(const void* feat, const int32_t* spatial_shape
         return fail(MSDA_ERR_INVALID_ARGUMENT, "visible is NULL");
     static const uint8_t none = 0;
     return backward_impl(feat, spatial_shapes, level_start_index, sampling_loc, weights,
-                         visible ? visible : &none, grad_out, grad_feat, grad_sampling_loc,
-                         grad_weights, workspace, workspace_bytes, desc, stream);
+                         visible ? visible : &none, nullptr, grad_out, grad_feat,
+                         grad_sampling_loc, grad_weights, workspace, workspace_bytes, desc,
+                         stream);
+}
+
+msda_status msda_backward_fused(const void* feat, const int32_t* spatial_shapes,
+                                const int32_t* level_start_index, const float* sampling_loc,
+                                const float* weights, const uint8_t* visible,
+                                const float* view_score, const float* out,
+                                const float* grad_out, void* grad_feat,
+                                float* grad_sampling_loc, float* grad_weights,
+                                float* grad_score, void* workspace, size_t workspace_bytes,
+                                const msda_desc* desc, void* stream) {
+    if (!visible && desc && desc->num_anchors > 0)
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "visible is NULL");
+    static const uint8_t none = 0;
+    const Fusion fuse{view_score, out, grad_score};
+    return backward_impl(feat, spatial_shapes, level_start_index, sampling_loc, weights,
+                         visible ? visible : &none, &fuse, grad_out, grad_feat,
+                         grad_sampling_loc, grad_weights, workspace, workspace_bytes, desc,
+                         stream);
+}
+
+size_t msda_backward_fused_workspace_size(const msda_desc* d) {
+    return msda_backward_visible_workspace_size(d);
 }
 
 size_t msda_backward_visible_workspace_size(const msda_desc* d) {
@@ -694,11 +746,12 @@ size_t msda_forward_visible_workspace_size(const msda_desc* d) {
     return forward_visible_part(d, &part_off);
 }
 
-msda_status msda_forward_visible(const void* feat, const int32_t* spatial_shapes,
-                                 const int32_t* level_start_index, const float* sampling_loc,
-                                 const float* weights, const uint8_t* visible, float* out,
-                                 void* workspace, size_t workspace_bytes, const msda_desc* desc,
-                                 void* stream) {
+static msda_status forward_visible_impl(const void* feat, const int32_t* spatial_shapes,
+                                        const int32_t* level_start_index,
+                                        const float* sampling_loc, const float* weights,
+                                        const uint8_t* visible, bool fused, const float* score,
+                                        float* out, void* workspace, size_t workspace_bytes,
+                                        const msda_desc* desc, void* stream) {
     if (!desc) return fail(MSDA_ERR_INVALID_ARGUMENT, "desc is NULL");
     if (desc->tile && desc->tile->order == MSDA_ORDER_ANCHOR)
         return fail(MSDA_ERR_UNSUPPORTED, "the visible-view form runs in view order only");
@@ -707,7 +760,7 @@ msda_status msda_forward_visible(const void* feat, const int32_t* spatial_shapes
     msda_status st = prepare(desc, MSDA_ORDER_VIEW, &a, &cpl, &waves);
     if (st != MSDA_OK) return st;
     if (!feat || !spatial_shapes || !level_start_index ||
-        (a.A > 0 && (!sampling_loc || !weights || !out || !visible)))
+        (a.A > 0 && (!sampling_loc || !weights || !out || !visible || (fused && !score))))
         return fail(MSDA_ERR_INVALID_ARGUMENT, "a required device pointer is NULL");
     if (!aligned(feat, 16)) return fail(MSDA_ERR_UNSUPPORTED, "feat must be 16-byte aligned");
     if ((uint64_t)a.B * a.N * (uint64_t)a.A >= (1ull << 31))
@@ -731,14 +784,40 @@ msda_status msda_forward_visible(const void* feat, const int32_t* spatial_shapes
     uint32_t* items = reinterpret_cast<uint32_t*>(ws + vw.items);
     const size_t V = (size_t)a.B * a.N * a.A;
     const hipStream_t s = (hipStream_t)stream;
+    float* vt = fused ? reinterpret_cast<float*>(ws + vw.vt) : nullptr;
     hipError_t e = msda::launch_visible_items(visible, a.B, a.N, a.A, 0u, place, items, nullptr,
                                               reinterpret_cast<uint32_t*>(ws + vw.partial), s);
+    if (e == hipSuccess && fused) e = msda::launch_view_scale(visible, score, a.B * a.A, a.N, vt, s);
     if (e == hipSuccess)
         e = msda::launch_forward_visible(a, desc->feat_dtype, cpl, waves,
                                          msda::lds_bytes_view(a, waves), items, place + V, place,
-                                         visible, reinterpret_cast<float*>(ws + part_off), s);
+                                         visible, vt, reinterpret_cast<float*>(ws + part_off), s);
     if (e != hipSuccess) return hip_fail(e, "msda_forward_visible launch");
     return ok();
+}
+
+msda_status msda_forward_visible(const void* feat, const int32_t* spatial_shapes,
+                                 const int32_t* level_start_index, const float* sampling_loc,
+                                 const float* weights, const uint8_t* visible, float* out,
+                                 void* workspace, size_t workspace_bytes, const msda_desc* desc,
+                                 void* stream) {
+    return forward_visible_impl(feat, spatial_shapes, level_start_index, sampling_loc, weights,
+                                visible, false, nullptr, out, workspace, workspace_bytes, desc,
+                                stream);
+}
+
+msda_status msda_forward_fused(const void* feat, const int32_t* spatial_shapes,
+                               const int32_t* level_start_index, const float* sampling_loc,
+                               const float* weights, const uint8_t* visible,
+                               const float* view_score, float* out, void* workspace,
+                               size_t workspace_bytes, const msda_desc* desc, void* stream) {
+    return forward_visible_impl(feat, spatial_shapes, level_start_index, sampling_loc, weights,
+                                visible, true, view_score, out, workspace, workspace_bytes, desc,
+                                stream);
+}
+
+size_t msda_forward_fused_workspace_size(const msda_desc* d) {
+    return msda_forward_visible_workspace_size(d);
 }
 
 msda_status msda_project_keypoints(const float* anchors, const float* keypoints,

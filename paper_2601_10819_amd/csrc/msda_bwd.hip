@@ -292,6 +292,8 @@ struct TileView {
     int C, G;
     u64 magic;                  // scene-local sample -> anchor
     int magic_shift;
+    const float* vscale;        // [anchor][N] per-view weight factor, or nullptr
+    int N, L;
     bool active;
 };
 
@@ -375,10 +377,18 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
             // sort could only give wrong sums, never a read outside it)
             const u32 ls = s - v.sample_offset < v.sample_count ? s - v.sample_offset : 0u;
             const float* ws = v.w + (size_t)ls * v.G;
-            for (int k = 0; k < v.G; ++k) ent[k] = ws[k];
+            const u32 an = fast_div(ls, v.magic, v.magic_shift);
+            if (v.vscale) {
+                // the fused form: the sample's weights times its view's factor
+                const u32 n = (ls / (u32)v.L) % (u32)v.N;
+                const float sc = v.vscale[(size_t)an * v.N + n];
+                for (int k = 0; k < v.G; ++k) ent[k] = ws[k] * sc;
+            } else {
+                for (int k = 0; k < v.G; ++k) ent[k] = ws[k];
+            }
             ent[v.G] = fr.x;
             ent[v.G + 1] = fr.y;
-            ent[v.G + 2] = __uint_as_float(fast_div(ls, v.magic, v.magic_shift));
+            ent[v.G + 2] = __uint_as_float(an);
             ent[v.G + 3] = __int_as_float(dy * (TW + 1) + dx);
         }
         // LDS accesses of one wave are performed in order; keep the compiler
@@ -511,6 +521,9 @@ __global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
     v.G = t.G;
     v.magic = t.magic;
     v.magic_shift = t.magic_shift;
+    v.vscale = t.view_scale;
+    v.N = t.N;
+    v.L = t.L;
     tile_reduce<OT, CPL, WHOLE_WAVE>(v, lps, spw, grp, sl, t.waves, bnd_lds, work);
 }
 
@@ -557,6 +570,9 @@ __global__ void __launch_bounds__(256) gfeat_tile_batched_kernel(BatchArgs b) {
     v.G = b.G;
     v.magic = b.t.magic[s];
     v.magic_shift = (int)b.t.magic_shift[s];
+    v.vscale = nullptr;
+    v.N = 1;
+    v.L = 1;
     tile_reduce<OT, CPL, WHOLE_WAVE>(v, lps, spw, grp, sl, b.waves, bnd_lds, work);
 }
 

@@ -101,14 +101,21 @@ __device__ __forceinline__ BwdAnchor bwd_anchor_ctx(const OpArgs& a, int ba, con
 // channels; grad_w is a shuffle reduction over the group's lanes, grad_loc
 // one over the sample's lanes per pair; the atomic grad_feat form adds
 // w * cw * grad_out into the FP32 accumulator.
+//
+// out_scale multiplies the grad_w and grad_loc written (the fused form's
+// per-view weight; 1 otherwise). dot (or nullptr) accumulates, on each
+// group's first lane, sum of w * (sum over the group's channels of grad_out
+// * value) -- <grad_out, the anchor's feature in this view> -- for the
+// fused form's score gradient.
 template <class FT, int CPL>
 __device__ __forceinline__ void bwd_chunk(const OpArgs& a, const StageSlot& st, int nj,
                                           const Geo* geo, const Lanes& q, const BwdAnchor& x,
-                                          const float* go) {
+                                          const float* go, float out_scale = 1.f,
+                                          float* dot = nullptr) {
     using RowT = Row<FT, CPL>;
     const int L = a.L, G = a.G, LG = L * G;
     const int lpg = (a.C / a.G) / CPL;             // lanes of one group (a power of two)
-    const bool need_vals = x.gwout || x.glout;
+    const bool need_vals = x.gwout || x.glout || dot;
     // byte offset of a row -> float offset in the FP32 accumulator
     constexpr int kOffToAcc = FT::kBytes == 4 ? 2 : FT::kBytes == 2 ? 1 : 0;
     for (int jj = q.sub; jj < nj; jj += q.spw) {
@@ -147,10 +154,13 @@ __device__ __forceinline__ void bwd_chunk(const OpArgs& a, const StageSlot& st, 
                 for (int i = 0; i < CPL; ++i) sum = fmaf(go[i], f[i], sum);
                 d[c] = sum;
             }
-            if (x.gwout) {
+            if (x.gwout || dot) {
                 float tw = t.cw[0] * d[0] + t.cw[1] * d[1] + t.cw[2] * d[2] + t.cw[3] * d[3];
                 for (int sft = 1; sft < lpg; sft <<= 1) tw += xor_shuffle(tw, sft);
-                if ((q.lane & (lpg - 1)) == 0) x.gwout[(size_t)src * LG + l * G + q.g] = tw;
+                if ((q.lane & (lpg - 1)) == 0) {
+                    if (x.gwout) x.gwout[(size_t)src * LG + l * G + q.g] = tw * out_scale;
+                    if (dot) *dot = fmaf(wl, tw, *dot);
+                }
             }
             // d val / dx = hy (F01 - F00) + ly (F11 - F10); x = u W - 0.5
             const Geo gm = geo[n * L + l];
@@ -165,8 +175,8 @@ __device__ __forceinline__ void bwd_chunk(const OpArgs& a, const StageSlot& st, 
                 gy += xor_shuffle(gy, s);
             }
             if ((q.lane & (q.lps - 1)) == 0) {
-                x.glout[(size_t)src * 2] = gx;
-                x.glout[(size_t)src * 2 + 1] = gy;
+                x.glout[(size_t)src * 2] = gx * out_scale;
+                x.glout[(size_t)src * 2 + 1] = gy * out_scale;
             }
         }
     }

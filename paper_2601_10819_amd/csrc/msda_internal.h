@@ -55,6 +55,8 @@ struct TileArgs {
     const uint32_t* cell_start;   // [N*L]
     const uint32_t* tile_start;   // [N*L + 1], by processing slot
     const uint32_t* tile_region;  // [N*L], region of each processing slot
+    const float* view_scale;      // [B*A][N] per-view weight factor (fused form), or nullptr
+    int32_t N, L;                 // cameras and levels (to find a sample's view)
     uint32_t tiles_per_item;
     uint32_t tile_begin, tile_end;  // this launch's tiles of each batch item (slot order)
     uint32_t cells_per_item;
@@ -228,13 +230,21 @@ hipError_t launch_project_keypoints(const ProjArgs& p, hipStream_t s);
 hipError_t launch_visible_items(const uint8_t* visible, int B, int N, int A, uint32_t per_item,
                                 uint32_t* place, uint32_t* items, uint32_t* rec_count,
                                 uint32_t* scan_partial, hipStream_t s);
+// vt (or nullptr): the fused form's per-view weights [B][A][N].
 hipError_t launch_forward_visible(const OpArgs& a, int dtype, int cpl, int waves, size_t lds,
                                   const uint32_t* items, const uint32_t* count,
-                                  const uint32_t* place, const uint8_t* visible, float* part,
-                                  hipStream_t s);
+                                  const uint32_t* place, const uint8_t* visible, const float* vt,
+                                  float* part, hipStream_t s);
+// item_dot (or nullptr): per item, <grad_out, the anchor's feature in the view>.
 hipError_t launch_backward_visible(const OpArgs& a, int dtype, int cpl, int waves, size_t lds,
                                    const uint32_t* items, const uint32_t* count,
-                                   uint32_t* rec_val, hipStream_t s);
+                                   uint32_t* rec_val, const float* vt, float* item_dot,
+                                   hipStream_t s);
+hipError_t launch_view_scale(const uint8_t* visible, const float* score, int BA, int N,
+                             float* vt, hipStream_t s);
+hipError_t launch_grad_score(const float* grad_out, const float* out, const uint8_t* visible,
+                             const float* score, const uint32_t* place, const float* item_dot,
+                             int B, int A, int N, int C, float* grad_score, hipStream_t s);
 int sort_passes(uint32_t max_key);
 
 hipError_t launch_batch_tables(const BatchArgs& b, bool backward, hipStream_t s);

@@ -116,6 +116,51 @@ __global__ void __launch_bounds__(256) visible_items_kernel(const uint8_t* __res
     if (visible[((size_t)b * A + a) * N + n]) items[place[v]] = (u32)v;
 }
 
+// Visibility-weighted fusion (Sec. 3.2, Eq. 2): vt[b][a][n] = score / sum of
+// the anchor's visible cameras' scores (0 for an invisible camera, and for
+// every camera when that sum is 0). One thread per (batch item, anchor).
+__global__ void __launch_bounds__(256) view_scale_kernel(const uint8_t* __restrict__ visible,
+                                                         const float* __restrict__ score,
+                                                         int BA, int N, float* __restrict__ vt) {
+    const int ba = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ba >= BA) return;
+    const size_t o = (size_t)ba * N;
+    float V = 0.f;
+    for (int n = 0; n < N; ++n)
+        if (visible[o + n]) V += score[o + n];
+    for (int n = 0; n < N; ++n) vt[o + n] = visible[o + n] && V > 0.f ? score[o + n] / V : 0.f;
+}
+
+// grad_score[b][a][n] = (<grad_out, g_n> - <grad_out, f>) / V for visible
+// cameras (0 otherwise, and when V = 0): g_n's product with grad_out comes
+// from the backward gather (dot per item), f is the fused forward output.
+__global__ void __launch_bounds__(256) grad_score_kernel(const float* __restrict__ grad_out,
+                                                         const float* __restrict__ out,
+                                                         const uint8_t* __restrict__ visible,
+                                                         const float* __restrict__ score,
+                                                         const u32* __restrict__ place,
+                                                         const float* __restrict__ item_dot,
+                                                         int B, int A, int N, int C,
+                                                         float* __restrict__ grad_score) {
+    const int ba = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ba >= B * A) return;
+    const int b = ba / A, an = ba - b * A;
+    const size_t o = (size_t)ba * N;
+    float V = 0.f;
+    for (int n = 0; n < N; ++n)
+        if (visible[o + n]) V += score[o + n];
+    float fdot = 0.f;
+    for (int c = 0; c < C; ++c) fdot = fmaf(grad_out[(size_t)ba * C + c], out[(size_t)ba * C + c], fdot);
+    for (int n = 0; n < N; ++n) {
+        float gs = 0.f;
+        if (visible[o + n] && V > 0.f) {
+            const u32 i = place[((size_t)b * N + n) * A + an];
+            gs = (item_dot[i] - fdot) / V;
+        }
+        grad_score[o + n] = gs;
+    }
+}
+
 // The persistent walk over the visible items: workgroup w serves range
 // w % kSlots of the item list; its waves take consecutive items, then move
 // on by the slot's wave count. Calls f(item index, b, a, n) per item.
@@ -180,10 +225,12 @@ __global__ void __launch_bounds__(512) msda_fwd_visible_kernel(OpArgs a, const u
 }
 
 // out[b, a, :] = sum over the anchor's visible cameras, in camera order, of
-// the items' partial rows (zero when no camera sees the anchor).
+// the items' partial rows, each times vt (the fused form's per-view weight)
+// when vt is given; zero when no camera sees the anchor.
 __global__ void __launch_bounds__(256) fwd_visible_reduce(const float* __restrict__ part,
                                                           const uint8_t* __restrict__ visible,
-                                                          const u32* __restrict__ place, int B,
+                                                          const u32* __restrict__ place,
+                                                          const float* __restrict__ vt, int B,
                                                           int N, int A, int C,
                                                           float* __restrict__ out) {
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -196,7 +243,8 @@ __global__ void __launch_bounds__(256) fwd_visible_reduce(const float* __restric
     for (int n = 0; n < N; ++n) {
         if (!visible[ba * N + n]) continue;
         const u32 i = place[((size_t)b * N + n) * A + an];
-        s += part[(size_t)i * C + c];
+        const float g = part[(size_t)i * C + c];
+        s = vt ? fmaf(vt[ba * N + n], g, s) : s + g;
     }
     out[t] = s;
 }
@@ -204,7 +252,8 @@ __global__ void __launch_bounds__(256) fwd_visible_reduce(const float* __restric
 template <class FT, int CPL>
 __global__ void __launch_bounds__(512) msda_bwd_visible_kernel(OpArgs a, const u32* items,
                                                                const u32* count,
-                                                               u32* rec_val) {
+                                                               u32* rec_val, const float* vt,
+                                                               float* item_dot) {
     extern __shared__ __align__(16) unsigned char smem[];
     Geo* geo = reinterpret_cast<Geo*>(smem);
     unsigned char* work = smem + (size_t)a.N * a.L * sizeof(Geo);
@@ -220,12 +269,18 @@ __global__ void __launch_bounds__(512) msda_bwd_visible_kernel(OpArgs a, const u
         x.rec.val = rec_val;
         x.rec.cbase = i * (u32)(a.P * a.L);
         const ViewOrder order{a.N, a.P, n};
+        const float scale = vt ? vt[((size_t)b * a.A + an) * a.N + n] : 1.f;
+        float dot = 0.f;
         for (int k0 = 0; k0 < a.P; k0 += J) {
             const int nj = min(J, a.P - k0);
             stage_chunk<false, true>(st, order, k0, nj, x.gw, x.gl, geo, a.L, a.L * a.G,
                                      (u32)a.C * FT::kBytes, q.lane, x.rec);
-            bwd_chunk<FT, CPL>(a, st, nj, geo, q, x, go);
+            bwd_chunk<FT, CPL>(a, st, nj, geo, q, x, go, scale, item_dot ? &dot : nullptr);
             end_chunk();
+        }
+        if (item_dot) {
+            for (int sft = 1; sft < 64; sft <<= 1) dot += xor_shuffle(dot, sft);
+            if (q.lane == 0) item_dot[i] = dot;
         }
     });
 }
@@ -240,7 +295,7 @@ static unsigned visible_blocks(int waves) {
 template <class FT, int CPL>
 static hipError_t fwd_visible_launch(const OpArgs& a, int waves, size_t lds, const u32* items,
                                      const u32* count, const u32* place, const uint8_t* visible,
-                                     float* part, hipStream_t s) {
+                                     const float* vt, float* part, hipStream_t s) {
     mark_begin("msda_fwd_visible_kernel", s);
     hipLaunchKernelGGL((msda_fwd_visible_kernel<FT, CPL>), dim3(visible_blocks(waves)),
                        dim3(64 * waves), lds, s, a, items, count, part);
@@ -250,17 +305,18 @@ static hipError_t fwd_visible_launch(const OpArgs& a, int waves, size_t lds, con
     const size_t total = (size_t)a.B * a.A * a.C;
     mark_begin("fwd_visible_reduce", s);
     hipLaunchKernelGGL(fwd_visible_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                       part, visible, place, a.B, a.N, a.A, a.C, a.out);
+                       part, visible, place, vt, a.B, a.N, a.A, a.C, a.out);
     mark_end(s);
     return hipGetLastError();
 }
 
 template <class FT, int CPL>
 static hipError_t bwd_visible_launch(const OpArgs& a, int waves, size_t lds, const u32* items,
-                                     const u32* count, u32* rec_val, hipStream_t s) {
+                                     const u32* count, u32* rec_val, const float* vt,
+                                     float* item_dot, hipStream_t s) {
     mark_begin("msda_bwd_visible_kernel", s);
     hipLaunchKernelGGL((msda_bwd_visible_kernel<FT, CPL>), dim3(visible_blocks(waves)),
-                       dim3(64 * waves), lds, s, a, items, count, rec_val);
+                       dim3(64 * waves), lds, s, a, items, count, rec_val, vt, item_dot);
     mark_end(s);
     return hipGetLastError();
 }
@@ -285,11 +341,13 @@ hipError_t launch_visible_items(const uint8_t* visible, int B, int N, int A, u32
 
 hipError_t launch_forward_visible(const OpArgs& a, int dtype, int cpl, int waves, size_t lds,
                                   const u32* items, const u32* count, const u32* place,
-                                  const uint8_t* visible, float* part, hipStream_t s) {
+                                  const uint8_t* visible, const float* vt, float* part,
+                                  hipStream_t s) {
     switch (dtype * 100 + cpl) {
 #define MSDA_CASE(D, T, K) \
         case D * 100 + K: \
-            return fwd_visible_launch<T, K>(a, waves, lds, items, count, place, visible, part, s);
+            return fwd_visible_launch<T, K>(a, waves, lds, items, count, place, visible, vt, \
+                                            part, s);
         MSDA_CASE(kF32, TF32, 1) MSDA_CASE(kF32, TF32, 2) MSDA_CASE(kF32, TF32, 4)
         MSDA_CASE(kBF16, TBF16, 2) MSDA_CASE(kBF16, TBF16, 4) MSDA_CASE(kBF16, TBF16, 8)
         MSDA_CASE(kFP8, TFP8, 4) MSDA_CASE(kFP8, TFP8, 8) MSDA_CASE(kFP8, TFP8, 16)
@@ -300,15 +358,37 @@ hipError_t launch_forward_visible(const OpArgs& a, int dtype, int cpl, int waves
 
 hipError_t launch_backward_visible(const OpArgs& a, int dtype, int cpl, int waves, size_t lds,
                                    const u32* items, const u32* count, u32* rec_val,
-                                   hipStream_t s) {
+                                   const float* vt, float* item_dot, hipStream_t s) {
     switch (dtype * 100 + cpl) {
 #define MSDA_CASE(D, T, K) \
-        case D * 100 + K: return bwd_visible_launch<T, K>(a, waves, lds, items, count, rec_val, s);
+        case D * 100 + K: \
+            return bwd_visible_launch<T, K>(a, waves, lds, items, count, rec_val, vt, item_dot, s);
         MSDA_CASE(kF32, TF32, 1) MSDA_CASE(kF32, TF32, 2) MSDA_CASE(kF32, TF32, 4)
         MSDA_CASE(kBF16, TBF16, 2) MSDA_CASE(kBF16, TBF16, 4) MSDA_CASE(kBF16, TBF16, 8)
 #undef MSDA_CASE
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_view_scale(const uint8_t* visible, const float* score, int BA, int N,
+                             float* vt, hipStream_t s) {
+    if (BA <= 0) return hipSuccess;
+    mark_begin("view_scale", s);
+    hipLaunchKernelGGL(view_scale_kernel, dim3((unsigned)((BA + 255) / 256)), dim3(256), 0, s,
+                       visible, score, BA, N, vt);
+    mark_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_score(const float* grad_out, const float* out, const uint8_t* visible,
+                             const float* score, const u32* place, const float* item_dot, int B,
+                             int A, int N, int C, float* grad_score, hipStream_t s) {
+    if (B * A <= 0) return hipSuccess;
+    mark_begin("grad_score", s);
+    hipLaunchKernelGGL(grad_score_kernel, dim3((unsigned)((B * A + 255) / 256)), dim3(256), 0, s,
+                       grad_out, out, visible, score, place, item_dot, B, A, N, C, grad_score);
+    mark_end(s);
+    return hipGetLastError();
 }
 
 }  // namespace msda

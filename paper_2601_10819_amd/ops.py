@@ -287,6 +287,69 @@ def backward_visible(feat, layout: Layout, sampling_loc, weights, visible, grad_
     return gf, gl, gw
 
 
+def _need_scores(view_score, visible):
+    _need_cuda_contig("view_score", view_score, torch.float32)
+    if view_score.shape != visible.shape:
+        raise ValueError(f"view_score must be [B, A, Ncam] = {tuple(visible.shape)}, "
+                         f"got {tuple(view_score.shape)}")
+
+
+def forward_fused(feat, layout: Layout, sampling_loc, weights, visible, view_score,
+                  level_scale=None, tile=None, out: Optional[torch.Tensor] = None,
+                  workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """out [B, A, C]: the visible views' features weighted by view_score over
+    the visible cameras' score sum (visibility-weighted fusion, Eq. 2)."""
+    lib = _lib.load()
+    _need_cuda_contig("feat", feat)
+    _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
+    _need_cuda_contig("weights", weights, torch.float32)
+    _need_visible(visible, sampling_loc)
+    _need_scores(view_score, visible)
+    d = make_desc(feat, layout, sampling_loc, weights, level_scale, tile=tile)
+    if out is None:
+        out = torch.empty(d.batch, d.num_anchors, d.channels, device=feat.device,
+                          dtype=torch.float32)
+    ws_ptr, ws_len, workspace = _workspace(
+        int(lib.msda_forward_fused_workspace_size(ctypes.byref(d))), workspace, feat.device)
+    _lib.check(lib.msda_forward_fused(_ptr(feat), _ptr(layout.shapes), _ptr(layout.starts),
+                                      _ptr(sampling_loc), _ptr(weights), _ptr(visible),
+                                      _ptr(view_score), _ptr(out), ws_ptr, ws_len,
+                                      ctypes.byref(d), _stream(stream)))
+    return out
+
+
+def backward_fused(feat, layout: Layout, sampling_loc, weights, visible, view_score, out,
+                   grad_out, need_feat=True, need_loc=True, need_w=True, need_score=True,
+                   tile=None, workspace: Optional[torch.Tensor] = None, stream=None):
+    """(grad_feat, grad_sampling_loc, grad_weights, grad_score) of
+    forward_fused; out is forward_fused's result (needed for grad_score)."""
+    lib = _lib.load()
+    _need_cuda_contig("feat", feat)
+    _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
+    _need_cuda_contig("weights", weights, torch.float32)
+    _need_cuda_contig("grad_out", grad_out, torch.float32)
+    _need_visible(visible, sampling_loc)
+    _need_scores(view_score, visible)
+    if need_score:
+        _need_cuda_contig("out", out, torch.float32)
+        if out.shape != grad_out.shape:
+            raise ValueError(f"out must match grad_out {tuple(grad_out.shape)}, "
+                             f"got {tuple(out.shape)}")
+    d = make_desc(feat, layout, sampling_loc, weights, tile=tile)
+    gf = torch.empty_like(feat) if need_feat else None
+    gl = torch.empty_like(sampling_loc) if need_loc else None
+    gw = torch.empty_like(weights) if need_w else None
+    gs = torch.empty_like(view_score) if need_score else None
+    ws_ptr, ws_len, workspace = _workspace(
+        int(lib.msda_backward_fused_workspace_size(ctypes.byref(d))), workspace, feat.device)
+    _lib.check(lib.msda_backward_fused(_ptr(feat), _ptr(layout.shapes), _ptr(layout.starts),
+                                       _ptr(sampling_loc), _ptr(weights), _ptr(visible),
+                                       _ptr(view_score), _ptr(out if need_score else None),
+                                       _ptr(grad_out), _ptr(gf), _ptr(gl), _ptr(gw), _ptr(gs),
+                                       ws_ptr, ws_len, ctypes.byref(d), _stream(stream)))
+    return gf, gl, gw, gs
+
+
 def quantize_fp8(feat_f32: torch.Tensor, layout: Layout, stream=None):
     """Per-level FP8 e4m3 quantisation on the device: (codes uint8 [B,R,C],
     level_scale float32 [L]) with scale_l = amax_l / 448."""
