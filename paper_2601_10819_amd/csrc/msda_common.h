@@ -217,6 +217,50 @@ __device__ __forceinline__ float xor_shuffle(float v, int mask) {
     return __shfl_xor(v, mask, 64);
 }
 
+// Cross-lane steps that stay in the VALU (no LDS round trip): DPP row
+// permutations and the gfx950 row / half-wave swaps. Callers keep every
+// lane of a group active together, so no step reads a disabled lane.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// v + v of the lane 16 (resp. 32) away: the swap pairs rows 0-1 and 2-3
+// (resp. the two halves); each lane ends with both values of its pair.
+__device__ __forceinline__ float swap16_sum(float v) {
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                    false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+
+__device__ __forceinline__ float swap32_sum(float v) {
+    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                    false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+
+// Sum over aligned groups of `width` lanes (a power of two <= 64, the same in
+// every lane): quad butterflies, then row half-mirror and mirror (pairing
+// the halves of 8 and of 16 lanes), then the swaps. Every lane of a group
+// ends with its group's sum, the same bits in each.
+__device__ __forceinline__ float group_sum(float v, int width) {
+    if (width > 1) v += dpp<0xB1>(v);     // quad_perm [1,0,3,2]
+    if (width > 2) v += dpp<0x4E>(v);     // quad_perm [2,3,0,1]
+    if (width > 4) v += dpp<0x141>(v);    // row_half_mirror
+    if (width > 8) v += dpp<0x140>(v);    // row_mirror
+    if (width > 16) v = swap16_sum(v);
+    if (width > 32) v = swap32_sum(v);
+    return v;
+}
+
+// v + v[lane ^ mask] for a power-of-two mask (the same in every lane).
+__device__ __forceinline__ float xor_sum(float v, int mask) {
+    if (mask == 32) return swap32_sum(v);
+    if (mask == 16) return swap16_sum(v);
+    if (mask == 8) return v + dpp<0x128>(v);   // row_ror:8
+    return v + xor_shuffle(v, mask);
+}
+
 // Per-lane registers' worth of weights staged per wave step.
 constexpr int kStageWords = 8;
 

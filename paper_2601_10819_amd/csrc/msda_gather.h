@@ -54,7 +54,7 @@ template <int CPL>
 __device__ __forceinline__ void reduce_subwaves(const Lanes& q, float* acc) {
     for (int s = q.lps; s < 64; s <<= 1) {
 #pragma unroll
-        for (int i = 0; i < CPL; ++i) acc[i] += xor_shuffle(acc[i], s);
+        for (int i = 0; i < CPL; ++i) acc[i] = xor_sum(acc[i], s);
     }
 }
 
@@ -156,7 +156,7 @@ __device__ __forceinline__ void bwd_chunk(const OpArgs& a, const StageSlot& st, 
             }
             if (x.gwout || dot) {
                 float tw = t.cw[0] * d[0] + t.cw[1] * d[1] + t.cw[2] * d[2] + t.cw[3] * d[3];
-                for (int sft = 1; sft < lpg; sft <<= 1) tw += xor_shuffle(tw, sft);
+                tw = group_sum(tw, lpg);
                 if ((q.lane & (lpg - 1)) == 0) {
                     if (x.gwout) x.gwout[(size_t)src * LG + l * G + q.g] = tw * out_scale;
                     if (dot) *dot = fmaf(wl, tw, *dot);
@@ -170,10 +170,8 @@ __device__ __forceinline__ void bwd_chunk(const OpArgs& a, const StageSlot& st, 
             gy += (float)gm.H * wl * (hx * (d[2] - d[0]) + fr.x * (d[3] - d[1]));
         }
         if (x.glout) {
-            for (int s = 1; s < q.lps; s <<= 1) {
-                gx += xor_shuffle(gx, s);
-                gy += xor_shuffle(gy, s);
-            }
+            gx = group_sum(gx, q.lps);
+            gy = group_sum(gy, q.lps);
             if ((q.lane & (q.lps - 1)) == 0) {
                 x.glout[(size_t)src * 2] = gx * out_scale;
                 x.glout[(size_t)src * 2 + 1] = gy * out_scale;

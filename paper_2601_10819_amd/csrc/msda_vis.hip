@@ -116,24 +116,33 @@ __global__ void __launch_bounds__(256) visible_items_kernel(const uint8_t* __res
     if (visible[((size_t)b * A + a) * N + n]) items[place[v]] = (u32)v;
 }
 
-// Visibility-weighted fusion (Sec. 3.2, Eq. 2): vt[b][a][n] = score / sum of
-// the anchor's visible cameras' scores (0 for an invisible camera, and for
-// every camera when that sum is 0). One thread per (batch item, anchor).
+// Visibility-weighted fusion (Sec. 3.2, Eq. 2). One wave per (batch item,
+// anchor); V = the sum of the scores of the anchor's visible cameras, added
+// lane-strided then by a fixed butterfly (the same order in every pass).
+__device__ __forceinline__ float wave_score_sum(const uint8_t* visible, const float* score,
+                                                size_t o, int N, int lane) {
+    float V = 0.f;
+    for (int n = lane; n < N; n += 64)
+        if (visible[o + n]) V += score[o + n];
+    return group_sum(V, 64);
+}
+
+// vt[b][a][n] = score / V for visible cameras; 0 for the others, and for
+// every camera when V <= 0.
 __global__ void __launch_bounds__(256) view_scale_kernel(const uint8_t* __restrict__ visible,
                                                          const float* __restrict__ score,
                                                          int BA, int N, float* __restrict__ vt) {
-    const int ba = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ba >= BA) return;
+    const int ba = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (ba >= BA) return;                     // whole waves
     const size_t o = (size_t)ba * N;
-    float V = 0.f;
-    for (int n = 0; n < N; ++n)
-        if (visible[o + n]) V += score[o + n];
-    for (int n = 0; n < N; ++n) vt[o + n] = visible[o + n] && V > 0.f ? score[o + n] / V : 0.f;
+    const float V = wave_score_sum(visible, score, o, N, lane);
+    for (int n = lane; n < N; n += 64)
+        vt[o + n] = visible[o + n] && V > 0.f ? score[o + n] / V : 0.f;
 }
 
 // grad_score[b][a][n] = (<grad_out, g_n> - <grad_out, f>) / V for visible
-// cameras (0 otherwise, and when V = 0): g_n's product with grad_out comes
-// from the backward gather (dot per item), f is the fused forward output.
+// cameras (0 otherwise, and when V <= 0): g_n's product with grad_out comes
+// from the backward gather (item_dot), f is the fused forward output.
 __global__ void __launch_bounds__(256) grad_score_kernel(const float* __restrict__ grad_out,
                                                          const float* __restrict__ out,
                                                          const uint8_t* __restrict__ visible,
@@ -142,16 +151,16 @@ __global__ void __launch_bounds__(256) grad_score_kernel(const float* __restrict
                                                          const float* __restrict__ item_dot,
                                                          int B, int A, int N, int C,
                                                          float* __restrict__ grad_score) {
-    const int ba = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ba >= B * A) return;
+    const int ba = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (ba >= B * A) return;                  // whole waves
     const int b = ba / A, an = ba - b * A;
     const size_t o = (size_t)ba * N;
-    float V = 0.f;
-    for (int n = 0; n < N; ++n)
-        if (visible[o + n]) V += score[o + n];
+    const float V = wave_score_sum(visible, score, o, N, lane);
     float fdot = 0.f;
-    for (int c = 0; c < C; ++c) fdot = fmaf(grad_out[(size_t)ba * C + c], out[(size_t)ba * C + c], fdot);
-    for (int n = 0; n < N; ++n) {
+    for (int c = lane; c < C; c += 64)
+        fdot = fmaf(grad_out[(size_t)ba * C + c], out[(size_t)ba * C + c], fdot);
+    fdot = group_sum(fdot, 64);
+    for (int n = lane; n < N; n += 64) {
         float gs = 0.f;
         if (visible[o + n] && V > 0.f) {
             const u32 i = place[((size_t)b * N + n) * A + an];
@@ -226,27 +235,61 @@ __global__ void __launch_bounds__(512) msda_fwd_visible_kernel(OpArgs a, const u
 
 // out[b, a, :] = sum over the anchor's visible cameras, in camera order, of
 // the items' partial rows, each times vt (the fused form's per-view weight)
-// when vt is given; zero when no camera sees the anchor.
+// when vt is given; zero when no camera sees the anchor. One wave per
+// anchor, 4 channels per lane per pass: a ballot of the visibility flags
+// of 64 cameras, then the items' rows 4 at a time (loads in flight
+// together, added in camera order).
 __global__ void __launch_bounds__(256) fwd_visible_reduce(const float* __restrict__ part,
                                                           const uint8_t* __restrict__ visible,
                                                           const u32* __restrict__ place,
                                                           const float* __restrict__ vt, int B,
                                                           int N, int A, int C,
                                                           float* __restrict__ out) {
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t total = (size_t)B * A * C;
-    if (t >= total) return;
-    const int c = (int)(t % (size_t)C);
-    const size_t ba = t / (size_t)C;
-    const int b = (int)(ba / (size_t)A), an = (int)(ba % (size_t)A);
-    float s = 0.f;
-    for (int n = 0; n < N; ++n) {
-        if (!visible[ba * N + n]) continue;
-        const u32 i = place[((size_t)b * N + n) * A + an];
-        const float g = part[(size_t)i * C + c];
-        s = vt ? fmaf(vt[ba * N + n], g, s) : s + g;
+    const int ba = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (ba >= B * A) return;                  // whole waves
+    const int b = ba / A, an = ba - b * A;
+    const size_t o = (size_t)ba * N;
+    for (int c0 = 0; c0 < C; c0 += 256) {
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int n0 = 0; n0 < N; n0 += 64) {
+            const int n = n0 + lane;
+            const bool f = n < N && visible[o + n];
+            const u32 pl = f ? place[((size_t)b * N + n) * A + an] : 0u;
+            const float sc = f && vt ? vt[o + n] : 1.f;
+            uint64_t mask = __ballot(f);
+            while (mask) {
+                int k[4];
+                int m = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    k[q] = mask ? __builtin_ctzll(mask) : 0;
+                    if (mask) { mask &= mask - 1; ++m; }
+                }
+                float g[4][4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const u32 i = (u32)__shfl((int)pl, k[q], 64);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int c = c0 + lane + 64 * j;
+                        g[q][j] = q < m && c < C ? part[(size_t)i * C + c] : 0.f;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q >= m) break;
+                    const float w = __shfl(sc, k[q], 64);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[j] = vt ? fmaf(w, g[q][j], acc[j]) : acc[j] + g[q][j];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = c0 + lane + 64 * j;
+            if (c < C) out[(size_t)ba * C + c] = acc[j];
+        }
     }
-    out[t] = s;
 }
 
 template <class FT, int CPL>
@@ -279,7 +322,7 @@ __global__ void __launch_bounds__(512) msda_bwd_visible_kernel(OpArgs a, const u
             end_chunk();
         }
         if (item_dot) {
-            for (int sft = 1; sft < 64; sft <<= 1) dot += xor_shuffle(dot, sft);
+            dot = group_sum(dot, 64);
             if (q.lane == 0) item_dot[i] = dot;
         }
     });
@@ -302,9 +345,9 @@ static hipError_t fwd_visible_launch(const OpArgs& a, int waves, size_t lds, con
     mark_end(s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t total = (size_t)a.B * a.A * a.C;
+    const size_t anchors = (size_t)a.B * a.A;
     mark_begin("fwd_visible_reduce", s);
-    hipLaunchKernelGGL(fwd_visible_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(fwd_visible_reduce, dim3((unsigned)((anchors + 3) / 4)), dim3(256), 0, s,
                        part, visible, place, vt, a.B, a.N, a.A, a.C, a.out);
     mark_end(s);
     return hipGetLastError();
@@ -374,7 +417,7 @@ hipError_t launch_view_scale(const uint8_t* visible, const float* score, int BA,
                              float* vt, hipStream_t s) {
     if (BA <= 0) return hipSuccess;
     mark_begin("view_scale", s);
-    hipLaunchKernelGGL(view_scale_kernel, dim3((unsigned)((BA + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(view_scale_kernel, dim3((unsigned)((BA + 3) / 4)), dim3(256), 0, s,
                        visible, score, BA, N, vt);
     mark_end(s);
     return hipGetLastError();
@@ -385,7 +428,7 @@ hipError_t launch_grad_score(const float* grad_out, const float* out, const uint
                              int A, int N, int C, float* grad_score, hipStream_t s) {
     if (B * A <= 0) return hipSuccess;
     mark_begin("grad_score", s);
-    hipLaunchKernelGGL(grad_score_kernel, dim3((unsigned)((B * A + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(grad_score_kernel, dim3((unsigned)((B * A + 3) / 4)), dim3(256), 0, s,
                        grad_out, out, visible, score, place, item_dot, B, A, N, C, grad_score);
     mark_end(s);
     return hipGetLastError();
