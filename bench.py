@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-cold", action="store_true",
                     help="skip the cold-cache steps (1 GiB write before each step)")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 forward")
+    ap.add_argument("--no-f16", action="store_true", help="skip the FP16-storage comparison")
     ap.add_argument("--no-visible", action="store_true",
                     help="skip the projection + visible-view steps (outside-in camera network)")
     ap.add_argument("--cpu-anchors", type=int, default=0,
@@ -436,6 +437,10 @@ def main():
     if not args.no_fp32:
         fp = run_gpu(args, torch, ops, synth, p, torch.float32, args.steps, args.warmup)
         print(f"# fp32 done: {fp}", file=sys.stderr, flush=True)
+    hf = None
+    if not args.no_f16:
+        hf = run_gpu(args, torch, ops, synth, p, torch.float16, args.steps, args.warmup)
+        print(f"# f16 done: {hf}", file=sys.stderr, flush=True)
 
     C, G, L, P, N = p.channels, p.groups, p.num_levels, p.num_points, p.num_cams
     fwd_b, bwd_b = bytes_per_sample(C, G, L, P, N, 2)
@@ -495,6 +500,15 @@ def main():
         res["fp32_kernels_ms"] = {n: round(v["ms"], 4) for n, v in fp["kernels"].items()}
         res["fp32_fwd_ms"] = fp["fwd_ms"]
         res["fp32_bwd_ms"] = fp["bwd_ms"]
+    if hf is not None:
+        hf_ms = hf["total_s"] / args.steps * 1e3
+        res["f16"] = {"ms_per_step": round(hf_ms, 4),
+                      "value": round(S * args.steps / hf["total_s"] / 1e9, 4),
+                      "fwd_ms": hf["fwd_ms"], "bwd_ms": hf["bwd_ms"],
+                      "kernels_ms": {n: round(v["ms"], 4) for n, v in hf["kernels"].items()},
+                      "note": "IEEE half storage, FP32 arithmetic (the paper's own precision)"}
+        if fp is not None:
+            res["f16"]["speedup_vs_fp32"] = round(fp["total_s"] / hf["total_s"], 3)
     if not args.no_fp8:
         f8 = run_fp8_forward(torch, ops, p, args.steps, args.warmup)
         res["fp8_forward"] = {"ms": f8, "value": round(S / (f8["median"] * 1e-3) / 1e9, 4),

@@ -19,14 +19,14 @@
  * ---------------------------------------
  * Layouts (row-major, contiguous, element strides implied):
  *   feat               [B][R][C]          R rows per batch item, channels fastest;
- *                                          FP32, BF16 or FP8-e4m3 (OCP e4m3fn)
+ *                                          FP32, BF16, FP16 or FP8-e4m3 (OCP e4m3fn)
  *   spatial_shapes     [Ncam][L][2] int32 (H, W) of level l of camera n
  *   level_start_index  [Ncam][L]   int32  first row of region (n, l) in a batch item
  *   sampling_loc       [B][A][P][Ncam][2] FP32, (x, y) normalised so 0..1 spans the image
  *   weights            [B][A][P][Ncam][L][G] FP32; channel c uses group c / (C/G)
  *   out, grad_out      [B][A][C] FP32
  *   grad_sampling_loc  like sampling_loc, grad_weights like weights (FP32)
- *   grad_feat          like feat, in the feat dtype (FP32 or BF16)
+ *   grad_feat          like feat, in the feat dtype (FP32, BF16 or FP16)
  * Pointers named "device" are HIP device memory; "host" pointers are read
  * during the call only. The caller owns every buffer, including workspaces;
  * the library never allocates, frees or synchronises on these calls, so they
@@ -65,7 +65,8 @@ typedef enum msda_status {
 typedef enum msda_dtype {
     MSDA_F32 = 0,
     MSDA_BF16 = 1,
-    MSDA_FP8_E4M3 = 2 /* OCP e4m3fn codes; value = decode(code) * level_scale[l] */
+    MSDA_FP8_E4M3 = 2, /* OCP e4m3fn codes; value = decode(code) * level_scale[l] */
+    MSDA_F16 = 3       /* IEEE binary16; grad_feat also binary16 (FP32 sums, one RNE rounding) */
 } msda_dtype;
 
 /* msda_desc.flags */
@@ -97,7 +98,7 @@ typedef struct msda_tile {
                                  anchor; view order: wavefronts per workgroup, one
                                  anchor each. 1, 2, 4 or 8                            */
     int32_t chans_per_lane;   /* channels each lane owns: 1, 2, 4 (FP32), 2, 4, 8
-                                 (BF16), 4, 8, 16 (FP8)                              */
+                                 (BF16, FP16), 4, 8, 16 (FP8)                        */
     int32_t order;            /* MSDA_ORDER_*                                          */
     int32_t scatter;          /* MSDA_SCATTER_* (backward only)                        */
 } msda_tile;
@@ -159,8 +160,8 @@ size_t msda_forward_workspace_size(const msda_desc* desc);
  * and weights (the analytic derivative of the forward; at an integer
  * coordinate the right-hand derivative). Any of grad_feat,
  * grad_sampling_loc, grad_weights may be NULL to skip it. grad_feat has the
- * feat dtype; FP8 grad_feat is UNSUPPORTED. Accumulation is FP32; a BF16
- * grad_feat is rounded once (to nearest even) from the FP32 sum.
+ * feat dtype; FP8 grad_feat is UNSUPPORTED. Accumulation is FP32; a BF16 or
+ * FP16 grad_feat is rounded once (to nearest even) from the FP32 sum.
  * grad_feat is formed as msda_tile.scatter says: by default every (sample,
  * corner) contribution is recorded, the records are sorted by feature row
  * (a stable radix sort) and each row is summed in sample order and written
@@ -178,7 +179,7 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
 
 /* Bytes of device workspace msda_backward needs for desc (0 if none): about
  * 24 bytes per sample plus 4 per bilinear cell for the sorted form; B*R*C*4
- * for the atomic form with BF16 features. */
+ * for the atomic form with BF16 or FP16 features. */
 size_t msda_backward_workspace_size(const msda_desc* desc);
 
 /*

@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "UNSUPPORTED", 3: "HIP", 4: "
 MSDA_F32 = 0
 MSDA_BF16 = 1
 MSDA_FP8_E4M3 = 2
+MSDA_F16 = 3
 
 MSDA_DETERMINISTIC = 1
 

@@ -27,9 +27,10 @@ import torch
 
 CACHE_ENV = "MSDA_TUNE_CACHE"
 WAVES = (1, 2, 4, 8)
-CPL = {torch.float32: (4, 2, 1), torch.bfloat16: (8, 4, 2),
+CPL = {torch.float32: (4, 2, 1), torch.bfloat16: (8, 4, 2), torch.float16: (8, 4, 2),
        torch.float8_e4m3fn: (16, 8, 4), torch.uint8: (16, 8, 4)}
-_DTYPE_NAME = {torch.float32: "f32", torch.bfloat16: "bf16", torch.float8_e4m3fn: "fp8",
+_DTYPE_NAME = {torch.float32: "f32", torch.bfloat16: "bf16", torch.float16: "f16",
+               torch.float8_e4m3fn: "fp8",
                torch.uint8: "fp8"}
 
 
@@ -148,7 +149,7 @@ def tune_single(feat, layout, loc, w, grad_out=None, level_scale=None, reps: int
         if best is None or ms < best[1]:
             best = (t, ms)
     result["forward"], result["forward_ms"] = best
-    if grad_out is not None and feat.dtype in (torch.float32, torch.bfloat16):
+    if grad_out is not None and feat.dtype in (torch.float32, torch.bfloat16, torch.float16):
         ws = torch.empty(ops.backward_workspace_bytes(feat, layout, loc, w) + 256,
                          dtype=torch.uint8, device=feat.device)
         ref = ops.backward(feat, layout, loc, w, grad_out, workspace=ws)
@@ -156,7 +157,7 @@ def tune_single(feat, layout, loc, w, grad_out=None, level_scale=None, reps: int
         best = None
         for t in candidates(feat.dtype, C, G):
             got = ops.backward(feat, layout, loc, w, grad_out, tile=t, workspace=ws)
-            tol = 1e-2 if feat.dtype == torch.bfloat16 else 1e-4
+            tol = 1e-2 if feat.dtype in (torch.bfloat16, torch.float16) else 1e-4
             if not all(_agree(g, r, tol) for g, r in zip(got, ref)):
                 continue
             ms = _time(lambda: ops.backward(feat, layout, loc, w, grad_out, tile=t, workspace=ws),
@@ -181,7 +182,7 @@ def tune_batch(batch, reps: int = 3, save: bool = True, path: Optional[str] = No
     torch.cuda.synchronize()
     ref = [t.clone() for t in batch.out + [g for g in batch.grad_feat if g is not None]]
     best = None
-    tol = 1e-2 if batch.dtype == torch.bfloat16 else 1e-4
+    tol = 1e-2 if batch.dtype in (torch.bfloat16, torch.float16) else 1e-4
     for t in candidates(batch.dtype, batch.C, batch.G, orders=("anchor",)):
         batch.set_tile(t)
         batch.forward()

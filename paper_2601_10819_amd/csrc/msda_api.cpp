@@ -42,6 +42,7 @@ int elem_bytes(int32_t dtype) {
     switch (dtype) {
         case MSDA_F32: return 4;
         case MSDA_BF16: return 2;
+        case MSDA_F16: return 2;
         case MSDA_FP8_E4M3: return 1;
         default: return 0;
     }
@@ -62,7 +63,8 @@ const int* cpl_candidates(int32_t dtype) {
     static const int fp8[] = {16, 8, 4, 0};
     switch (dtype) {
         case MSDA_F32: return f32;
-        case MSDA_BF16: return bf16;
+        case MSDA_BF16:
+        case MSDA_F16: return bf16;
         default: return fp8;
     }
 }
@@ -441,7 +443,7 @@ VisibleWs visible_layout(const msda_desc* d, size_t at) {
 size_t msda_backward_workspace_size(const msda_desc* d) {
     if (!d || d->batch < 1 || d->rows < 1 || d->channels < 1 || d->num_anchors < 0) return 0;
     if (scatter_mode(d) == MSDA_SCATTER_ATOMIC) {
-        if (d->feat_dtype == MSDA_BF16)   // FP32 accumulator for grad_feat
+        if (d->feat_dtype == MSDA_BF16 || d->feat_dtype == MSDA_F16)   // FP32 accumulator
             return (size_t)d->batch * (size_t)d->rows * (size_t)d->channels * sizeof(float);
         return 0;
     }
@@ -558,6 +560,10 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
             (e = msda::launch_f32_to_bf16(acc, static_cast<uint16_t*>(grad_feat), gf_elems, s)) !=
                 hipSuccess)
             return hip_fail(e, "round grad_feat to bf16");
+        if (desc->feat_dtype == MSDA_F16 &&
+            (e = msda::launch_f32_to_f16(acc, static_cast<uint16_t*>(grad_feat), gf_elems, s)) !=
+                hipSuccess)
+            return hip_fail(e, "round grad_feat to f16");
         return ok();
     }
 

@@ -148,14 +148,19 @@ __device__ __forceinline__ void store_row(void* base, size_t elem, const float* 
             for (int i = 0; i < CPL; ++i) p[i] = acc[i];
         }
     } else {
+        // one rounding of the FP32 sum to the storage type
+        auto rnd = [](float x) -> u32 {
+            if constexpr (OT::kKind == 3) return f16_rne(x);
+            else return bf16_rne(x);
+        };
         uint16_t* p = static_cast<uint16_t*>(base) + elem;
         if constexpr (CPL == 4) {
-            const u32 lo = (u32)bf16_rne(acc[0]) | ((u32)bf16_rne(acc[1]) << 16);
-            const u32 hi = (u32)bf16_rne(acc[2]) | ((u32)bf16_rne(acc[3]) << 16);
+            const u32 lo = rnd(acc[0]) | (rnd(acc[1]) << 16);
+            const u32 hi = rnd(acc[2]) | (rnd(acc[3]) << 16);
             *reinterpret_cast<u32x2*>(p) = u32x2{lo, hi};
         } else {
 #pragma unroll
-            for (int i = 0; i < CPL; ++i) p[i] = bf16_rne(acc[i]);
+            for (int i = 0; i < CPL; ++i) p[i] = (uint16_t)rnd(acc[i]);
         }
     }
 }
@@ -594,8 +599,11 @@ hipError_t launch_backward(const OpArgs& a, int dtype, int cpl, int waves, size_
         case kF32 * 100 + 2: return bwd_launch<TF32, 2>(a, waves, lds, s);
         case kF32 * 100 + 4: return bwd_launch<TF32, 4>(a, waves, lds, s);
         case kBF16 * 100 + 2: return bwd_launch<TBF16, 2>(a, waves, lds, s);
+        case kF16 * 100 + 2: return bwd_launch<TF16, 2>(a, waves, lds, s);
         case kBF16 * 100 + 4: return bwd_launch<TBF16, 4>(a, waves, lds, s);
+        case kF16 * 100 + 4: return bwd_launch<TF16, 4>(a, waves, lds, s);
         case kBF16 * 100 + 8: return bwd_launch<TBF16, 8>(a, waves, lds, s);
+        case kF16 * 100 + 8: return bwd_launch<TF16, 8>(a, waves, lds, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -618,8 +626,11 @@ hipError_t launch_backward_view(const OpArgs& a, int dtype, int cpl, int waves, 
         case kF32 * 100 + 2: return bwd_view_launch<TF32, 2>(a, waves, lds, s);
         case kF32 * 100 + 4: return bwd_view_launch<TF32, 4>(a, waves, lds, s);
         case kBF16 * 100 + 2: return bwd_view_launch<TBF16, 2>(a, waves, lds, s);
+        case kF16 * 100 + 2: return bwd_view_launch<TF16, 2>(a, waves, lds, s);
         case kBF16 * 100 + 4: return bwd_view_launch<TBF16, 4>(a, waves, lds, s);
+        case kF16 * 100 + 4: return bwd_view_launch<TF16, 4>(a, waves, lds, s);
         case kBF16 * 100 + 8: return bwd_view_launch<TBF16, 8>(a, waves, lds, s);
+        case kF16 * 100 + 8: return bwd_view_launch<TF16, 8>(a, waves, lds, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -661,8 +672,11 @@ hipError_t launch_backward_batched(const BatchArgs& b, int dtype, int cpl, int w
         case kF32 * 100 + 2: return bwd_batched_launch<TF32, 2>(b, waves, blocks, lds, s);
         case kF32 * 100 + 4: return bwd_batched_launch<TF32, 4>(b, waves, blocks, lds, s);
         case kBF16 * 100 + 2: return bwd_batched_launch<TBF16, 2>(b, waves, blocks, lds, s);
+        case kF16 * 100 + 2: return bwd_batched_launch<TF16, 2>(b, waves, blocks, lds, s);
         case kBF16 * 100 + 4: return bwd_batched_launch<TBF16, 4>(b, waves, blocks, lds, s);
+        case kF16 * 100 + 4: return bwd_batched_launch<TF16, 4>(b, waves, blocks, lds, s);
         case kBF16 * 100 + 8: return bwd_batched_launch<TBF16, 8>(b, waves, blocks, lds, s);
+        case kF16 * 100 + 8: return bwd_batched_launch<TF16, 8>(b, waves, blocks, lds, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -693,8 +707,11 @@ hipError_t launch_gfeat_tiles_batched(const BatchArgs& b, int out_dtype, int cpl
         case kF32 * 100 + 2: return tile_batched_launch<TF32, 2>(b, s);
         case kF32 * 100 + 4: return tile_batched_launch<TF32, 4>(b, s);
         case kBF16 * 100 + 1: return tile_batched_launch<TBF16, 1>(b, s);
+        case kF16 * 100 + 1: return tile_batched_launch<TF16, 1>(b, s);
         case kBF16 * 100 + 2: return tile_batched_launch<TBF16, 2>(b, s);
+        case kF16 * 100 + 2: return tile_batched_launch<TF16, 2>(b, s);
         case kBF16 * 100 + 4: return tile_batched_launch<TBF16, 4>(b, s);
+        case kF16 * 100 + 4: return tile_batched_launch<TF16, 4>(b, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -705,8 +722,11 @@ hipError_t launch_gfeat_tiles(const TileArgs& t, int out_dtype, int cpl, hipStre
         case kF32 * 100 + 2: return tile_launch<TF32, 2>(t, s);
         case kF32 * 100 + 4: return tile_launch<TF32, 4>(t, s);
         case kBF16 * 100 + 1: return tile_launch<TBF16, 1>(t, s);
+        case kF16 * 100 + 1: return tile_launch<TF16, 1>(t, s);
         case kBF16 * 100 + 2: return tile_launch<TBF16, 2>(t, s);
+        case kF16 * 100 + 2: return tile_launch<TF16, 2>(t, s);
         case kBF16 * 100 + 4: return tile_launch<TBF16, 4>(t, s);
+        case kF16 * 100 + 4: return tile_launch<TF16, 4>(t, s);
         default: return hipErrorInvalidValue;
     }
 }

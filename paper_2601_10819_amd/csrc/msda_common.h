@@ -49,9 +49,13 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, u32 bytes) {
 
 // ---------------------------------------------------------------- storage types
 
-struct TF32 { static constexpr int kBytes = 4; };
-struct TBF16 { static constexpr int kBytes = 2; };
-struct TFP8 { static constexpr int kBytes = 1; };
+// kKind matches the FeatType code of the storage type.
+struct TF32 { static constexpr int kBytes = 4, kKind = 0; };
+struct TBF16 { static constexpr int kBytes = 2, kKind = 1; };
+struct TFP8 { static constexpr int kBytes = 1, kKind = 2; };
+struct TF16 { static constexpr int kBytes = 2, kKind = 3; };
+
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
 template <class FT, int CPL>
 struct Row {
@@ -79,12 +83,22 @@ __device__ __forceinline__ void widen(const u32* w, float* f) {
     if constexpr (FT::kBytes == 4) {
 #pragma unroll
         for (int i = 0; i < CPL; ++i) f[i] = __uint_as_float(w[i]);
-    } else if constexpr (FT::kBytes == 2) {
+    } else if constexpr (FT::kKind == 1) {
         // bfloat16 is the top half of an FP32: widening is a shift.
 #pragma unroll
         for (int i = 0; i < CPL / 2; ++i) {
             f[2 * i] = __uint_as_float(w[i] << 16);
             f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+        }
+    } else if constexpr (FT::kKind == 3) {
+        // IEEE half to FP32 is exact; feeding it straight into an FMA lets the
+        // compiler use v_fma_mix_f32, which widens either half of a word
+        // inside the FP32 FMA itself.
+#pragma unroll
+        for (int i = 0; i < CPL / 2; ++i) {
+            const half2_t h = __builtin_bit_cast(half2_t, w[i]);
+            f[2 * i] = (float)h.x;
+            f[2 * i + 1] = (float)h.y;
         }
     } else {
         // OCP e4m3 to FP32 with the hardware converter, two codes at a time.
@@ -95,6 +109,12 @@ __device__ __forceinline__ void widen(const u32* w, float* f) {
             f[4 * i] = lo.x; f[4 * i + 1] = lo.y; f[4 * i + 2] = hi.x; f[4 * i + 3] = hi.y;
         }
     }
+}
+
+// FP32 -> IEEE half with the hardware conversion: round to nearest even
+// (the default rounding mode), overflow to infinity, NaN stays NaN.
+__device__ __forceinline__ uint16_t f16_rne(float x) {
+    return __builtin_bit_cast(uint16_t, (_Float16)x);
 }
 
 // FP32 -> bfloat16, round to nearest even (NaN stays NaN).

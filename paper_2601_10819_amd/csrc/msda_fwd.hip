@@ -265,6 +265,9 @@ static hipError_t fwd_view_launch(const OpArgs& a, int waves, size_t lds, float*
         case kBF16 * 100 + 2: return F<TBF16, 2>(__VA_ARGS__);          \
         case kBF16 * 100 + 4: return F<TBF16, 4>(__VA_ARGS__);          \
         case kBF16 * 100 + 8: return F<TBF16, 8>(__VA_ARGS__);          \
+        case kF16 * 100 + 2: return F<TF16, 2>(__VA_ARGS__);            \
+        case kF16 * 100 + 4: return F<TF16, 4>(__VA_ARGS__);            \
+        case kF16 * 100 + 8: return F<TF16, 8>(__VA_ARGS__);            \
         case kFP8 * 100 + 4: return F<TFP8, 4>(__VA_ARGS__);            \
         case kFP8 * 100 + 8: return F<TFP8, 8>(__VA_ARGS__);            \
         case kFP8 * 100 + 16: return F<TFP8, 16>(__VA_ARGS__);          \

@@ -110,7 +110,7 @@ struct BatchArgs {
     uint32_t tile_begin, tile_end;
 };
 
-enum FeatType { kF32 = 0, kBF16 = 1, kFP8 = 2 };
+enum FeatType { kF32 = 0, kBF16 = 1, kFP8 = 2, kF16 = 3 };
 
 // Keypoint projection (device pointers).
 struct ProjArgs {
@@ -256,6 +256,7 @@ hipError_t launch_gfeat_tiles_batched(const BatchArgs& b, int out_dtype, int cpl
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, size_t n, hipStream_t s);
+hipError_t launch_f32_to_f16(const float* src, uint16_t* dst, size_t n, hipStream_t s);
 hipError_t launch_quantize_fp8(const float* x, const int32_t* shapes, const int32_t* starts,
                                int32_t B, int32_t N, int32_t L, int64_t R, int32_t C,
                                uint8_t* codes, float* level_scale, uint32_t* amax_ws,

@@ -26,6 +26,12 @@ __global__ void f32_to_bf16_kernel(const float* src, uint16_t* dst, size_t n) {
         dst[k] = bf16_rne(src[k]);
 }
 
+__global__ void f32_to_f16_kernel(const float* src, uint16_t* dst, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+        dst[k] = f16_rne(src[k]);
+}
+
 // --- FP8 per-level quantisation: amax, scale, encode.
 
 // One block per (batch item, camera, level) region; atomicMax of |x| as bits
@@ -117,6 +123,15 @@ hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, size_t n, hipStre
     if (n == 0) return hipSuccess;
     mark_begin("f32_to_bf16", s);
     hipLaunchKernelGGL(f32_to_bf16_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, src,
+                       dst, n);
+    mark_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_f32_to_f16(const float* src, uint16_t* dst, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    mark_begin("f32_to_f16", s);
+    hipLaunchKernelGGL(f32_to_f16_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, src,
                        dst, n);
     mark_end(s);
     return hipGetLastError();

@@ -393,6 +393,7 @@ hipError_t launch_forward_visible(const OpArgs& a, int dtype, int cpl, int waves
                                             part, s);
         MSDA_CASE(kF32, TF32, 1) MSDA_CASE(kF32, TF32, 2) MSDA_CASE(kF32, TF32, 4)
         MSDA_CASE(kBF16, TBF16, 2) MSDA_CASE(kBF16, TBF16, 4) MSDA_CASE(kBF16, TBF16, 8)
+        MSDA_CASE(kF16, TF16, 2) MSDA_CASE(kF16, TF16, 4) MSDA_CASE(kF16, TF16, 8)
         MSDA_CASE(kFP8, TFP8, 4) MSDA_CASE(kFP8, TFP8, 8) MSDA_CASE(kFP8, TFP8, 16)
 #undef MSDA_CASE
         default: return hipErrorInvalidValue;
@@ -408,6 +409,7 @@ hipError_t launch_backward_visible(const OpArgs& a, int dtype, int cpl, int wave
             return bwd_visible_launch<T, K>(a, waves, lds, items, count, rec_val, vt, item_dot, s);
         MSDA_CASE(kF32, TF32, 1) MSDA_CASE(kF32, TF32, 2) MSDA_CASE(kF32, TF32, 4)
         MSDA_CASE(kBF16, TBF16, 2) MSDA_CASE(kBF16, TBF16, 4) MSDA_CASE(kBF16, TBF16, 8)
+        MSDA_CASE(kF16, TF16, 2) MSDA_CASE(kF16, TF16, 4) MSDA_CASE(kF16, TF16, 8)
 #undef MSDA_CASE
         default: return hipErrorInvalidValue;
     }

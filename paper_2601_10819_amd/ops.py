@@ -21,7 +21,7 @@ import torch
 
 from . import _lib
 
-_DTYPES = {torch.float32: _lib.MSDA_F32, torch.bfloat16: _lib.MSDA_BF16,
+_DTYPES = {torch.float32: _lib.MSDA_F32, torch.bfloat16: _lib.MSDA_BF16, torch.float16: _lib.MSDA_F16,
            torch.float8_e4m3fn: _lib.MSDA_FP8_E4M3, torch.uint8: _lib.MSDA_FP8_E4M3}
 
 

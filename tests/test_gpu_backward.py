@@ -161,7 +161,8 @@ def test_autograd_function(ops, oracle_mod):
     assert feat2.grad is not None and loc2.grad is None
 
 
-@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16], ids=["f32", "bf16"])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16, torch.float16],
+                         ids=["f32", "bf16", "f16"])
 def test_sorted_grad_feat_is_bitwise_reproducible(ops, oracle_mod, dtype):
     """The default (sorted) grad_feat sums each row in sample order: repeated
     calls and different launch shapes give identical bits, and both it and

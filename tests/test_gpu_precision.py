@@ -1,9 +1,11 @@
-"""Precision forms: BF16 and FP8-e4m3 feature storage with FP32 arithmetic.
+"""Precision forms: BF16, FP16 and FP8-e4m3 feature storage with FP32
+arithmetic.
 
 Each is measured two ways against the FP64 oracle: the kernel error (oracle
 run on the stored values, widened exactly) must meet the FP32 bar, and the
 total error (oracle run on the original FP32 features) is reported, with the
-BF16 bar of 1e-2 of the output RMS."""
+half-precision bar of 1e-2 of the output RMS (FP16, with 3 more mantissa
+bits than BF16, is also held to 1e-3)."""
 import numpy as np
 import pytest
 import torch
@@ -29,51 +31,85 @@ def ops():
     return o
 
 
-def bf16_widened(p):
-    return p.feat.to(torch.bfloat16).double()
+HALF = [torch.bfloat16, torch.float16]
+HALF_IDS = ["bf16", "f16"]
+# total-error bar per storage type, and the bar on grad_feat against the
+# oracle's sum rounded to that type (the rounding differs by at most one
+# ulp where the FP32 and FP64 sums straddle a rounding boundary)
+TOTAL_TOL = {torch.bfloat16: BF16_TOL, torch.float16: 1e-3}
+ROUNDED_TOL = {torch.bfloat16: 5e-3, torch.float16: 5e-4}
 
 
+def widened(p, dtype):
+    return p.feat.to(dtype).double()
+
+
+@pytest.mark.parametrize("dtype", HALF, ids=HALF_IDS)
 @pytest.mark.parametrize("which", ["sparse4d", "train16", "cam64"])
-def test_bf16_forward(ops, oracle_mod, which):
+def test_half_forward(ops, oracle_mod, which, dtype):
     p = {"sparse4d": lambda: synth.sparse4d(seed=0), "train16": synth.train16,
          "cam64": synth.cam64}[which]()
-    feat, layout, loc, w = to_device(p, torch.bfloat16)
+    feat, layout, loc, w = to_device(p, dtype)
     got = host(ops.forward(feat, layout, loc, w))
     idx = anchor_subset(p, 64, seed=3)
-    ref_kernel = oracle_forward_subset(oracle_mod, bf16_widened(p), p, idx)
+    ref_kernel = oracle_forward_subset(oracle_mod, widened(p, dtype), p, idx)
     ref_total = oracle_forward_subset(oracle_mod, p.feat, p, idx)
-    assert_close(got[:, idx], ref_kernel, FWD_F32_TOL, FWD_F32_MAXREL, f"{which} bf16 kernel")
+    assert_close(got[:, idx], ref_kernel, FWD_F32_TOL, FWD_F32_MAXREL, f"{which} {dtype} kernel")
     total = normwise(got[:, idx], ref_total)
-    print(f"{which} bf16 forward total error {total:.3e}", flush=True)
-    assert total <= BF16_TOL
+    print(f"{which} {dtype} forward total error {total:.3e}", flush=True)
+    assert total <= TOTAL_TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", HALF, ids=HALF_IDS)
 @pytest.mark.parametrize("which", ["sparse4d", "train16"])
-def test_bf16_backward(ops, oracle_mod, which):
+def test_half_backward(ops, oracle_mod, which, dtype):
     p = synth.sparse4d(seed=0) if which == "sparse4d" else synth.train16()
     go = synth.grad_out_like(p, seed=7)
-    feat, layout, loc, w = to_device(p, torch.bfloat16)
+    feat, layout, loc, w = to_device(p, dtype)
     gf, gl, gw = ops.backward(feat, layout, loc, w, go.cuda())
     torch.cuda.synchronize()
-    assert gf.dtype == torch.bfloat16
+    assert gf.dtype == dtype
     idx = anchor_subset(p, 48, seed=4)
-    rgl_k, rgw_k = oracle_backward_subset(oracle_mod, bf16_widened(p), p, idx, go)
+    rgl_k, rgw_k = oracle_backward_subset(oracle_mod, widened(p, dtype), p, idx, go)
     rgl_t, rgw_t = oracle_backward_subset(oracle_mod, p.feat, p, idx, go)
-    assert_close(host(gl)[:, idx], rgl_k, GRAD_F32_TOL, None, f"{which} bf16 grad_loc kernel")
-    assert_close(host(gw)[:, idx], rgw_k, GRAD_F32_TOL, None, f"{which} bf16 grad_w kernel")
-    assert normwise(host(gl)[:, idx], rgl_t) <= BF16_TOL
-    assert normwise(host(gw)[:, idx], rgw_t) <= BF16_TOL
+    assert_close(host(gl)[:, idx], rgl_k, GRAD_F32_TOL, None, f"{which} {dtype} grad_loc kernel")
+    assert_close(host(gw)[:, idx], rgw_k, GRAD_F32_TOL, None, f"{which} {dtype} grad_w kernel")
+    assert normwise(host(gl)[:, idx], rgl_t) <= TOTAL_TOL[dtype]
+    assert normwise(host(gw)[:, idx], rgw_t) <= TOTAL_TOL[dtype]
     if which == "sparse4d":
-        rgf, _, _ = oracle_mod.backward(bf16_widened(p), p.spatial_shapes, p.level_start_index,
+        rgf, _, _ = oracle_mod.backward(widened(p, dtype), p.spatial_shapes, p.level_start_index,
                                         p.sampling_loc, p.weights, go, need_loc=False,
                                         need_w=False)
-        # grad_feat is rounded once to BF16: error bounded by the BF16 bar,
-        # and the rounding is to nearest (within half a BF16 ulp of FP32 sum)
+        # grad_feat is rounded once to the storage type: error bounded by
+        # the type's bar, and the rounding is to nearest (within half an
+        # ulp of the FP32 sum)
         err = normwise(host(gf), rgf)
-        print(f"{which} bf16 grad_feat error {err:.3e}", flush=True)
-        assert err <= BF16_TOL
-        rounded = torch.from_numpy(rgf).float().to(torch.bfloat16).double().numpy()
-        assert normwise(host(gf), rounded) <= 5e-3
+        print(f"{which} {dtype} grad_feat error {err:.3e}", flush=True)
+        assert err <= TOTAL_TOL[dtype]
+        rounded = torch.from_numpy(rgf).float().to(dtype).double().numpy()
+        assert normwise(host(gf), rounded) <= ROUNDED_TOL[dtype]
+
+
+def test_f16_grad_feat_rounding_is_ieee(ops):
+    """Pixel-centre samples with one weight each: grad_feat is w * grad_out
+    summed in FP32 and rounded once to IEEE half (nearest even), overflow to
+    infinity included."""
+    C, G = 64, 4
+    shapes, starts, R = synth.layout([[(1, 4)]])
+    layout = ops.Layout(shapes, starts)
+    feat = torch.zeros(1, R, C, dtype=torch.float16, device="cuda")
+    A = 4
+    loc = torch.zeros(1, A, 1, 1, 2)
+    loc[0, :, 0, 0, 0] = (torch.arange(A) + 0.5) / 4      # pixel a of the 1x4 level
+    loc[0, :, 0, 0, 1] = 0.5
+    w = torch.ones(1, A, 1, 1, 1, G)
+    go = torch.randn(1, A, C, generator=torch.Generator().manual_seed(0)) * 3.0
+    go[0, 3, :8] = torch.tensor([7e4, -7e4, 65504.0, 65519.0, 65520.0, 1e-8, 3e-5, 6.1e-5])
+    gf, _, _ = ops.backward(feat, layout, loc.cuda(), w.cuda(), go.cuda(), need_loc=False,
+                            need_w=False)
+    torch.cuda.synchronize()
+    want = go[0].to(torch.float16)                          # torch's FP32 -> half (RNE)
+    assert torch.equal(gf[0, :A].cpu(), want)
 
 
 def test_fp8_quantiser_bit_exact(ops, oracle_mod):

@@ -112,7 +112,8 @@ def test_visible_forward_backward_match_oracle(ops, proj, i):
     assert np.all(host(gl)[np.broadcast_to(inv[:, :, None, :, None], rgl.shape)] == 0)
 
 
-@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16], ids=["f32", "bf16"])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16, torch.float16],
+                         ids=["f32", "bf16", "f16"])
 def test_all_visible_equals_dense(ops, dtype):
     """Every pair visible: grad_w, grad_loc and grad_feat are the dense
     operator's bits (same per-pair arithmetic, same record order within each
