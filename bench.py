@@ -43,6 +43,8 @@ def parse():
                     help="skip the cold-cache steps (1 GiB write before each step)")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 forward")
     ap.add_argument("--no-f16", action="store_true", help="skip the FP16-storage comparison")
+    ap.add_argument("--no-softmax", action="store_true",
+                    help="skip the steps with weights generated from logits")
     ap.add_argument("--no-visible", action="store_true",
                     help="skip the projection + visible-view steps (outside-in camera network)")
     ap.add_argument("--cpu-anchors", type=int, default=0,
@@ -122,25 +124,34 @@ def measured_traffic(kernel: str, workload: str, dtype: str):
     return ent.get("hbm_bytes_per_launch")
 
 
-def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup, cold=False):
+def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup, cold=False, weights=None,
+            logits=False):
     """Time `steps` forward+backward steps. Every kernel the library launches
     is bracketed by HIP events on its stream (the library's benchmark hook),
-    so per-kernel average durations come from the timed region itself."""
+    so per-kernel average durations come from the timed region itself.
+    weights: instead of the workload's (e.g. logits, with logits=True)."""
     lib = ops._lib.load()
     dev = "cuda"
     feat = p.feat.to(feat_dtype).to(dev)
     layout = ops.Layout(p.spatial_shapes, p.level_start_index, dev)
-    loc, w = p.sampling_loc.to(dev), p.weights.to(dev)
+    loc = p.sampling_loc.to(dev)
+    w = (weights if weights is not None else p.weights).to(dev)
     go = synth.grad_out_like(p, seed=1).to(dev)
     out = torch.empty(p.batch, p.num_anchors, p.channels, device=dev)
-    ws_bytes = ops.backward_workspace_bytes(feat, layout, loc, w)
+    ws_bytes = ops.backward_workspace_bytes(feat, layout, loc, w, logits=logits)
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev) if ws_bytes else None
-    fws_bytes = ops.forward_workspace_bytes(feat, layout, loc, w)
+    fws_bytes = ops.forward_workspace_bytes(feat, layout, loc, w, logits=logits)
     fws = torch.empty(fws_bytes + 256, dtype=torch.uint8, device=dev) if fws_bytes else None
 
+    def fwd():
+        ops.forward(feat, layout, loc, w, out=out, workspace=fws, logits=logits)
+
+    def bwd():
+        ops.backward(feat, layout, loc, w, go, workspace=ws, logits=logits)
+
     def step():
-        ops.forward(feat, layout, loc, w, out=out, workspace=fws)
-        ops.backward(feat, layout, loc, w, go, workspace=ws)
+        fwd()
+        bwd()
 
     for _ in range(warmup):
         step()
@@ -154,12 +165,14 @@ def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup, cold=False):
         for i in range(2 * cap):
             arr[i] = ev.create()
         arrays.append(arr)
-    names = []
+    names, nfwd = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
         ops._lib.check(lib.msda_set_kernel_events(arrays[i], cap))
-        step()
+        fwd()
+        nfwd.append(lib.msda_recorded_kernels())
+        bwd()
         k = lib.msda_recorded_kernels()
         names.append([lib.msda_recorded_kernel_name(j).decode() for j in range(k)])
         ops._lib.check(lib.msda_set_kernel_events(None, 0))
@@ -167,13 +180,12 @@ def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup, cold=False):
     t1 = time.perf_counter()
     per_kernel = {}
     steps_ms, fwd_ms = [], []
-    for arr, nm in zip(arrays, names):
+    for arr, nm, nf in zip(arrays, names, nfwd):
         for j, name in enumerate(nm):
             per_kernel.setdefault(name, []).append(ev.elapsed_ms(arr[2 * j], arr[2 * j + 1]))
         # first kernel's start to last kernel's end: the step on the GPU;
-        # the forward is every kernel before the backward's first
+        # the forward is the kernels the forward call launched
         steps_ms.append(ev.elapsed_ms(arr[0], arr[2 * len(nm) - 1]))
-        nf = sum(1 for name in nm if name.startswith(FWD_KERNELS))
         fwd_ms.append(ev.elapsed_ms(arr[0], arr[2 * nf - 1]))
     for arr in arrays:
         for e in arr:
@@ -202,8 +214,6 @@ def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup, cold=False):
     return res
 
 
-# kernels of the forward call (the rest of a step is the backward)
-FWD_KERNELS = ("msda_fwd", "fwd_view_reduce")
 
 
 def pct(v):
@@ -509,6 +519,22 @@ def main():
                       "note": "IEEE half storage, FP32 arithmetic (the paper's own precision)"}
         if fp is not None:
             res["f16"]["speedup_vs_fp32"] = round(fp["total_s"] / hf["total_s"], 3)
+    if not args.no_softmax:
+        g = torch.Generator().manual_seed(3)
+        x = torch.randn(p.weights.shape, generator=g) * 2.0
+        sm = {}
+        for name, xt in (("f32_logits", x), ("bf16_logits", x.to(torch.bfloat16))):
+            r = run_gpu(args, torch, ops, synth, p, torch.bfloat16, args.steps, args.warmup,
+                        weights=xt, logits=True)
+            sm[name] = {"ms_per_step": round(r["total_s"] / args.steps * 1e3, 4),
+                        "value": round(S * args.steps / r["total_s"] / 1e9, 4),
+                        "fwd_ms": r["fwd_ms"], "bwd_ms": r["bwd_ms"],
+                        "kernels_ms": {n: round(v["ms"], 4) for n, v in r["kernels"].items()}}
+            print(f"# softmax {name} done: {sm[name]}", file=sys.stderr, flush=True)
+        sm["note"] = ("BF16 features, weights generated inside from per-group logits "
+                      "(softmax over keypoints x cameras x levels); grad_weights = gradient "
+                      "of the logits")
+        res["softmax_weights"] = sm
     if not args.no_fp8:
         f8 = run_fp8_forward(torch, ops, p, args.steps, args.warmup)
         res["fp8_forward"] = {"ms": f8, "value": round(S / (f8["median"] * 1e-3) / 1e9, 4),

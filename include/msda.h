@@ -73,6 +73,20 @@ typedef enum msda_dtype {
 #define MSDA_DETERMINISTIC 1u /* backward: grad_feat must be summed in a fixed order
                                  (bitwise reproducible run to run); rejects
                                  MSDA_SCATTER_ATOMIC */
+/* Fused weight generation (the weights' upstream step, paper Sec. 3.1 / 3.2):
+ * `weights` holds logits, and the operator uses their softmax over the P*Ncam*L
+ * (keypoint, camera, level) entries of each (batch item, anchor, group):
+ *   w[b][a][p][n][l][g] = exp(x - max) / sum over (p', n', l') of exp(x' - max)
+ * (a logit of -inf is a masked entry with weight 0). The forward applies it
+ * while staging the weights (they are never written); grad_weights is then
+ * the gradient with respect to the logits, w * (dw - sum over the group of
+ * w * dw). Forward and backward need a workspace (msda_forward_ws). */
+#define MSDA_WEIGHT_LOGITS 2u
+/* `weights` (or the logits) are stored as bfloat16: the pointer holds
+ * uint16 bit patterns in the same layout; grad_weights stays FP32. */
+#define MSDA_WEIGHTS_BF16 4u
+/* The visible-view, fused and batched entry points take neither of the two
+ * weight flags (UNSUPPORTED). */
 
 /* msda_tile.scatter: how the backward forms grad_feat */
 #define MSDA_SCATTER_AUTO 0   /* the library's choice (currently SORTED)                */
@@ -119,7 +133,8 @@ typedef struct msda_desc {
     const int32_t* host_spatial_shapes;
     const int32_t* host_level_start_index;
     const float* level_scale; /* device [L] FP32; FP8 only, else NULL        */
-    uint32_t flags;           /* MSDA_DETERMINISTIC ...                       */
+    uint32_t flags;           /* MSDA_DETERMINISTIC | MSDA_WEIGHT_LOGITS |
+                                 MSDA_WEIGHTS_BF16; other bits are invalid    */
     const msda_tile* tile;    /* NULL = built-in choice                       */
 } msda_desc;
 
@@ -152,7 +167,8 @@ msda_status msda_forward_ws(const void* feat, const int32_t* spatial_shapes,
                             size_t workspace_bytes, const msda_desc* desc, void* stream);
 
 /* Bytes of device workspace msda_forward_ws needs for desc: 8*B*A*C*4 when
- * the forward runs in view order (chosen or requested), else 0. */
+ * the forward runs in view order (chosen or requested), plus B*A*G*8 (the
+ * softmax statistics) with MSDA_WEIGHT_LOGITS, each part rounded up to 256. */
 size_t msda_forward_workspace_size(const msda_desc* desc);
 
 /*
@@ -179,7 +195,9 @@ msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
 
 /* Bytes of device workspace msda_backward needs for desc (0 if none): about
  * 24 bytes per sample plus 4 per bilinear cell for the sorted form; B*R*C*4
- * for the atomic form with BF16 or FP16 features. */
+ * for the atomic form with BF16 or FP16 features; with MSDA_WEIGHT_LOGITS or
+ * MSDA_WEIGHTS_BF16 also the FP32 weights (4*G per sample) and the softmax
+ * statistics (B*A*G*8). */
 size_t msda_backward_workspace_size(const msda_desc* desc);
 
 /*

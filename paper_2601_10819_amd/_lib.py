@@ -25,6 +25,8 @@ MSDA_FP8_E4M3 = 2
 MSDA_F16 = 3
 
 MSDA_DETERMINISTIC = 1
+MSDA_WEIGHT_LOGITS = 2
+MSDA_WEIGHTS_BF16 = 4
 
 ABI_VERSION = 4
 

@@ -38,6 +38,8 @@ msda_status ok() {
     return MSDA_OK;
 }
 
+constexpr uint32_t kWeightFlags = MSDA_WEIGHT_LOGITS | MSDA_WEIGHTS_BF16;
+
 int elem_bytes(int32_t dtype) {
     switch (dtype) {
         case MSDA_F32: return 4;
@@ -162,6 +164,8 @@ msda_status prepare(const msda_desc* d, int order, msda::OpArgs* a, int* cpl_out
     }
     if (order != MSDA_ORDER_ANCHOR && order != MSDA_ORDER_VIEW)
         return fail(MSDA_ERR_UNSUPPORTED, "unknown order %d", order);
+    if (d->flags & ~(MSDA_DETERMINISTIC | kWeightFlags))
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", (unsigned)d->flags);
 
     a->B = d->batch;
     a->N = d->num_cams;
@@ -212,6 +216,23 @@ msda_status hip_fail(hipError_t e, const char* what) {
 bool aligned(const void* p, size_t n) { return ((uintptr_t)p % n) == 0; }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Fused weight generation: the softmax statistics (forward and backward)
+// and the FP32 weights the backward works on.
+// The statistics [B*A][G] float2, then the per-chunk partials they are
+// merged from (reused for the backward's per-chunk group sums).
+size_t stats_only_bytes(const msda_desc* d) {
+    return align256((size_t)d->batch * (size_t)(d->num_anchors > 0 ? d->num_anchors : 0) *
+                    (size_t)d->groups * sizeof(float2));
+}
+
+size_t stats_bytes(const msda_desc* d) {
+    if (!(d->flags & MSDA_WEIGHT_LOGITS)) return 0;
+    const int BA = d->batch * (d->num_anchors > 0 ? d->num_anchors : 0);
+    return stats_only_bytes(d) +
+           align256(msda::softmax_scratch_bytes(
+               BA, d->num_points * d->num_cams * d->num_levels, d->groups));
+}
 
 // Workspace of the sorted grad_feat form: record keys (x2 for the sort),
 // values (x2), fractions, per-cell offsets, region tables and the sort's
@@ -367,12 +388,28 @@ static msda_status forward_impl(const void* feat, const int32_t* spatial_shapes,
         (a.A > 0 && (!sampling_loc || !weights || !out)))
         return fail(MSDA_ERR_INVALID_ARGUMENT, "a required device pointer is NULL");
     if (!aligned(feat, 16)) return fail(MSDA_ERR_UNSUPPORTED, "feat must be 16-byte aligned");
-    const size_t need = order == MSDA_ORDER_VIEW
-                            ? (size_t)msda::kSlots * a.B * a.A * a.C * sizeof(float) : 0;
+    const size_t part_bytes = order == MSDA_ORDER_VIEW
+                                  ? (size_t)msda::kSlots * a.B * a.A * a.C * sizeof(float) : 0;
+    const size_t stats_off = align256(part_bytes);
+    const size_t need = stats_off + stats_bytes(desc);
+    if (need && !has_ws)
+        return fail(MSDA_ERR_WORKSPACE, "weight logits need a workspace (msda_forward_ws)");
     if (need && (!workspace || workspace_bytes < need || !aligned(workspace, 256)))
         return fail(MSDA_ERR_WORKSPACE, "forward workspace: need %zu bytes, 256-byte aligned "
                                         "(got %zu at %p)", need, workspace_bytes, workspace);
     if (a.A == 0) return ok();
+    const bool wbf16 = desc->flags & MSDA_WEIGHTS_BF16;
+    a.w_bf16 = wbf16;
+    if (desc->flags & MSDA_WEIGHT_LOGITS) {
+        char* base = static_cast<char*>(workspace) + stats_off;
+        float2* stats = reinterpret_cast<float2*>(base);
+        float2* part = reinterpret_cast<float2*>(base + stats_only_bytes(desc));
+        const hipError_t e = msda::launch_softmax_stats(weights, wbf16, a.B * a.A,
+                                                        a.P * a.N * a.L, a.G, part, stats,
+                                                        (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "softmax statistics");
+        a.wstats = stats;
+    }
     a.feat = feat;
     a.shapes = spatial_shapes;
     a.starts = level_start_index;
@@ -408,9 +445,11 @@ msda_status msda_forward_ws(const void* feat, const int32_t* spatial_shapes,
 
 size_t msda_forward_workspace_size(const msda_desc* d) {
     if (!d || d->batch < 1 || d->num_cams < 1 || d->channels < 1 || d->num_anchors < 0) return 0;
-    if (resolve_order(d, true) != MSDA_ORDER_VIEW) return 0;
-    return (size_t)msda::kSlots * (size_t)d->batch * (size_t)d->num_anchors *
-           (size_t)d->channels * sizeof(float);
+    const size_t part = resolve_order(d, true) == MSDA_ORDER_VIEW
+                            ? (size_t)msda::kSlots * (size_t)d->batch * (size_t)d->num_anchors *
+                                  (size_t)d->channels * sizeof(float)
+                            : 0;
+    return align256(part) + stats_bytes(d);
 }
 
 // The backward gather in the chosen order.
@@ -440,7 +479,8 @@ VisibleWs visible_layout(const msda_desc* d, size_t at) {
     return w;
 }
 
-size_t msda_backward_workspace_size(const msda_desc* d) {
+// The backward's workspace without the weight flags' part.
+static size_t base_backward_bytes(const msda_desc* d) {
     if (!d || d->batch < 1 || d->rows < 1 || d->channels < 1 || d->num_anchors < 0) return 0;
     if (scatter_mode(d) == MSDA_SCATTER_ATOMIC) {
         if (d->feat_dtype == MSDA_BF16 || d->feat_dtype == MSDA_F16)   // FP32 accumulator
@@ -452,6 +492,16 @@ size_t msda_backward_workspace_size(const msda_desc* d) {
     cells_and_tiles(d, &cells, &tiles);
     return sorted_layout(num_samples(d), cells * (uint64_t)d->batch,
                          (uint64_t)d->num_cams * d->num_levels).total;
+}
+
+// The FP32 weights the backward works on under a weight flag.
+static size_t weights_f32_bytes(const msda_desc* d) {
+    return (d->flags & kWeightFlags) ? align256(num_samples(d) * (size_t)d->groups * 4) : 0;
+}
+
+size_t msda_backward_workspace_size(const msda_desc* d) {
+    if (!d || d->batch < 1 || d->rows < 1 || d->channels < 1 || d->num_anchors < 0) return 0;
+    return align256(base_backward_bytes(d)) + stats_bytes(d) + weights_f32_bytes(d);
 }
 
 // The backward, dense (visible == nullptr) or over the visible views only.
@@ -520,9 +570,14 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
         if (rcpl == 4 && !aligned(grad_out, 16))
             return fail(MSDA_ERR_UNSUPPORTED, "grad_out must be 16-byte aligned");
     }
-    const size_t sorted_need = grad_feat ? msda_backward_workspace_size(desc) : 0;
+    if (visible && (desc->flags & kWeightFlags))
+        return fail(MSDA_ERR_UNSUPPORTED, "the visible-view forms take no weight flags");
+    const size_t sorted_need = grad_feat ? base_backward_bytes(desc) : 0;
     const VisibleWs VW = visible_layout(desc, align256(sorted_need));
-    const size_t need = visible && a.A > 0 ? VW.total : sorted_need;
+    // weight flags: softmax statistics and FP32 weights after the rest
+    const size_t wx_off = align256(sorted_need);
+    const size_t wx_bytes = a.A > 0 ? stats_bytes(desc) + weights_f32_bytes(desc) : 0;
+    const size_t need = visible && a.A > 0 ? VW.total : (wx_bytes ? wx_off + wx_bytes : sorted_need);
     if (need) {
         if (!workspace || workspace_bytes < need)
             return fail(MSDA_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
@@ -538,11 +593,40 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
     const size_t gf_bytes = gf_elems * (desc->feat_dtype == MSDA_F32 ? 4 : 2);
     char* ws = static_cast<char*>(workspace);
     hipError_t e = hipSuccess;
+    // Under a weight flag the backward works on FP32 weights written once
+    // (the softmax of the logits, or the widened BF16 weights); with logits,
+    // grad_weights is mapped to the logits' gradient at the end.
+    const bool logits = (desc->flags & MSDA_WEIGHT_LOGITS) && a.A > 0;
+    const float* weff = weights;
+    float* w32 = nullptr;
+    float2* part = nullptr;
+    if (wx_bytes) {
+        float2* stats = logits ? reinterpret_cast<float2*>(ws + wx_off) : nullptr;
+        part = reinterpret_cast<float2*>(ws + wx_off + stats_only_bytes(desc));
+        w32 = reinterpret_cast<float*>(ws + wx_off + stats_bytes(desc));
+        const bool wbf16 = desc->flags & MSDA_WEIGHTS_BF16;
+        const int PNL = a.P * a.N * a.L;
+        if ((logits && (e = msda::launch_softmax_stats(weights, wbf16, a.B * a.A, PNL, a.G, part,
+                                                       stats, s)) != hipSuccess) ||
+            (e = msda::launch_weights_f32(weights, wbf16, stats, a.B * a.A, PNL, a.G, w32, s)) !=
+                hipSuccess)
+            return hip_fail(e, "weights from logits");
+        weff = w32;
+    }
+    auto finish = [&]() -> msda_status {
+        if (logits && grad_weights) {
+            const hipError_t ee = msda::launch_softmax_grad(w32, grad_weights, a.B * a.A,
+                                                            a.P * a.N * a.L, a.G,
+                                                            reinterpret_cast<float*>(part), s);
+            if (ee != hipSuccess) return hip_fail(ee, "gradient through the softmax");
+        }
+        return ok();
+    };
     a.feat = feat;
     a.shapes = spatial_shapes;
     a.starts = level_start_index;
     a.loc = sampling_loc;
-    a.w = weights;
+    a.w = weff;
     a.grad_out = grad_out;
     a.grad_loc = grad_sampling_loc;
     a.grad_w = grad_weights;
@@ -564,7 +648,7 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
             (e = msda::launch_f32_to_f16(acc, static_cast<uint16_t*>(grad_feat), gf_elems, s)) !=
                 hipSuccess)
             return hip_fail(e, "round grad_feat to f16");
-        return ok();
+        return finish();
     }
 
     SortedWs W = {};
@@ -633,7 +717,7 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
                (e = launch_gather(a, order, desc->feat_dtype, cpl, waves, s)) != hipSuccess) {
         return hip_fail(e, "msda_backward launch");
     }
-    if (!grad_feat) return ok();
+    if (!grad_feat) return finish();
 
     uint32_t* sorted = nullptr;
     uint32_t* off = reinterpret_cast<uint32_t*>(ws + W.off);
@@ -648,7 +732,7 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
     t.vals = sorted ? sorted : reinterpret_cast<uint32_t*>(ws + W.vals_a);
     t.off = off;
     t.frac = a.rec_frac;
-    t.w = weights;
+    t.w = weff;
     t.grad_out = grad_out;
     t.grad_feat = grad_feat;
     t.shapes = spatial_shapes;
@@ -682,7 +766,7 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
             (e = msda::launch_gfeat_tiles(t, desc->feat_dtype, rcpl, s)) != hipSuccess)
             return hip_fail(e, "grad_feat tile reduction");
     }
-    return ok();
+    return finish();
 }
 
 msda_status msda_backward(const void* feat, const int32_t* spatial_shapes,
@@ -761,6 +845,8 @@ static msda_status forward_visible_impl(const void* feat, const int32_t* spatial
     if (!desc) return fail(MSDA_ERR_INVALID_ARGUMENT, "desc is NULL");
     if (desc->tile && desc->tile->order == MSDA_ORDER_ANCHOR)
         return fail(MSDA_ERR_UNSUPPORTED, "the visible-view form runs in view order only");
+    if (desc->flags & kWeightFlags)
+        return fail(MSDA_ERR_UNSUPPORTED, "the visible-view forms take no weight flags");
     msda::OpArgs a = {};
     int cpl = 0, waves = 0;
     msda_status st = prepare(desc, MSDA_ORDER_VIEW, &a, &cpl, &waves);
@@ -943,6 +1029,8 @@ msda_status plan_batch(const msda_batch* b, bool backward, BatchPlan* p) {
                     msda::kMaxBatchScenes);
     if (!b->scenes || !b->host_scenes || !b->host_spatial_shapes || !b->host_level_start_index)
         return fail(MSDA_ERR_INVALID_ARGUMENT, "scene table or host mirrors are NULL");
+    if (b->flags & kWeightFlags)
+        return fail(MSDA_ERR_UNSUPPORTED, "the batched form takes no weight flags");
     *p = BatchPlan{};
     const int eb = elem_bytes(b->feat_dtype);
     for (int s = 0; s < b->num_scenes; ++s) {

@@ -376,13 +376,45 @@ struct RecordSink {
     u32 cbase;           // compacted: first record of the wave's item
 };
 
+// One anchor's weights as the gathers stage them: FP32 or bfloat16 storage,
+// and optionally logits turned into the per-group softmax on the fly
+// (w = exp(logit - max_g) / sum_g, the group's statistics precomputed).
+struct WSrc {
+    const void* p;          // the anchor's [P*N][L*G] weights or logits
+    const float2* stats;    // per group (max, 1/sum), or nullptr (plain weights)
+    int G;
+    bool bf16;
+    __device__ WSrc(const float* w) : p(w), stats(nullptr), G(1), bf16(false) {}
+    __device__ WSrc(const void* w, const float2* st, int g, bool b)
+        : p(w), stats(st), G(g), bf16(b) {}
+    // entry i as stored (FP32, or bfloat16 widened exactly)
+    __device__ __forceinline__ float raw(size_t i) const {
+        return bf16 ? __uint_as_float((u32)static_cast<const uint16_t*>(p)[i] << 16)
+                    : static_cast<const float*>(p)[i];
+    }
+    // the softmax weight of a logit x of group g (G is a power of two, and
+    // entry i of a chunk belongs to group i & (G - 1))
+    __device__ __forceinline__ float softmax(float x, int g) const {
+        const float2 st = stats[g];
+        return expf(x - st.x) * st.y;
+    }
+};
+
+// The weights of anchor ba (npw = P*N*L*G entries per anchor) as staged.
+__device__ __forceinline__ WSrc anchor_weights(const OpArgs& a, size_t ba, size_t npw) {
+    const void* p = a.w_bf16 ? static_cast<const void*>(
+                                   reinterpret_cast<const uint16_t*>(a.w) + ba * npw)
+                             : static_cast<const void*>(a.w + ba * npw);
+    return WSrc(p, a.wstats ? a.wstats + ba * (size_t)a.G : nullptr, a.G, a.w_bf16 != 0);
+}
+
 // Stages pairs [k0, k0 + nj) (in the wave's pair order) of the anchor whose
 // weights / locations start at gw / gl: pair table, weights (coalesced
 // within each pair's L*G run), and one sample's taps per lane. Ends with
 // the slot readable by the whole wave.
 template <bool SCALE_TAPS, bool FRACS, class Order>
 __device__ __forceinline__ void stage_chunk(const StageSlot& s, const Order& order, int k0, int nj,
-                                            const float* gw, const float* gl, const Geo* geo,
+                                            const WSrc& gw, const float* gl, const Geo* geo,
                                             int L, int LG, u32 row_bytes, int lane,
                                             const RecordSink& rec) {
     if (lane < nj) {
@@ -398,8 +430,12 @@ __device__ __forceinline__ void stage_chunk(const StageSlot& s, const Order& ord
         const int i = t * 64 + lane;
         if (i < nw) {
             const int jj = i / LG;
-            s.w[i] = gw[(size_t)s.src[jj] * LG + (i - jj * LG)];
+            s.w[i] = gw.raw((size_t)s.src[jj] * LG + (i - jj * LG));
         }
+    }
+    if (gw.stats) {
+        // logits -> softmax weights: each lane rewrites the entries it staged
+        for (int i = lane; i < nw; i += 64) s.w[i] = gw.softmax(s.w[i], i & (gw.G - 1));
     }
     const int Lp = padded_levels(L);
     for (int i = lane; i < nj * Lp; i += 64) {

@@ -56,7 +56,7 @@ __device__ __forceinline__ void fwd_anchor(const OpArgs& a, const int ba, const 
     const int b = ba / a.A;
     const int npairs = a.P * a.N;
     const float* gl = a.loc + (size_t)ba * npairs * 2;
-    const float* gw = a.w + (size_t)ba * npairs * LG;
+    const WSrc gw = anchor_weights(a, (size_t)ba, (size_t)npairs * LG);
     const u32 row_bytes = (u32)a.C * FT::kBytes;
     const rsrc_t feat = make_rsrc(static_cast<const char*>(a.feat) + (size_t)b * a.batch_bytes,
                                   a.batch_bytes);
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(512) msda_fwd_view_kernel(OpArgs a, float* par
     const int ba = row.b * a.A + row.a;
     const int npairs = a.P * a.N;
     const float* gl = a.loc + (size_t)ba * npairs * 2;
-    const float* gw = a.w + (size_t)ba * npairs * LG;
+    const WSrc gw = anchor_weights(a, (size_t)ba, (size_t)npairs * LG);
     const u32 row_bytes = (u32)a.C * FT::kBytes;
     const rsrc_t feat = make_rsrc(
         static_cast<const char*>(a.feat) + (size_t)row.b * a.batch_bytes, a.batch_bytes);

@@ -31,6 +31,8 @@ struct OpArgs {
     uint32_t sample_offset;       // added to every record index
     float* grad_loc;              // or nullptr
     float* grad_w;                // or nullptr
+    const float2* wstats;         // forward: w holds logits; per (b, a, g) (max, 1/sum of exp)
+    int32_t w_bf16;               // forward: w holds bfloat16 bit patterns
     int32_t B, N, L, A, P, C, G;
     int64_t R;
     uint32_t batch_bytes;         // R * C * sizeof(feat element) (< 2^31)
@@ -240,6 +242,21 @@ hipError_t launch_backward_visible(const OpArgs& a, int dtype, int cpl, int wave
                                    const uint32_t* items, const uint32_t* count,
                                    uint32_t* rec_val, const float* vt, float* item_dot,
                                    hipStream_t s);
+// Fused weight generation (per-group softmax of logits, BF16 weights).
+// stats[(b*A + a)*G + g] = (max, 1 / sum of exp(logit - max)) over the
+// anchor's P*N*L logits of group g; logits FP32 or bfloat16 bit patterns.
+// part: scratch of softmax_scratch_bytes (per-chunk partials).
+size_t softmax_scratch_bytes(int BA, int PNL, int G);
+hipError_t launch_softmax_stats(const void* logits, bool bf16, int BA, int PNL, int G,
+                                float2* part, float2* stats, hipStream_t s);
+// w[i] = softmax weight (stats given) or the widened weight (stats nullptr),
+// FP32, for all BA*PNL*G entries.
+hipError_t launch_weights_f32(const void* src, bool bf16, const float2* stats, int BA, int PNL,
+                              int G, float* w, hipStream_t s);
+// In place: grad[i] = w[i] * (grad[i] - sum over the anchor's group of w * grad),
+// the gradient through the per-group softmax; part: softmax_scratch_bytes.
+hipError_t launch_softmax_grad(const float* w, float* grad, int BA, int PNL, int G, float* part,
+                               hipStream_t s);
 hipError_t launch_view_scale(const uint8_t* visible, const float* score, int BA, int N,
                              float* vt, hipStream_t s);
 hipError_t launch_grad_score(const float* grad_out, const float* out, const uint8_t* visible,

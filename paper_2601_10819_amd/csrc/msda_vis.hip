@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(512) msda_fwd_visible_kernel(OpArgs a, const u
     for_each_visible_item(a, items, count, [&](u32 i, int b, int an, int n) {
         const int ba = b * a.A + an;
         const float* gl = a.loc + (size_t)ba * npairs * 2;
-        const float* gw = a.w + (size_t)ba * npairs * LG;
+        const WSrc gw = anchor_weights(a, (size_t)ba, (size_t)npairs * LG);
         const rsrc_t feat = make_rsrc(static_cast<const char*>(a.feat) + (size_t)b * a.batch_bytes,
                                       a.batch_bytes);
         const ViewOrder order{a.N, a.P, n};

@@ -85,7 +85,7 @@ def tile_struct(tile: dict, into=None):
 
 def make_desc(feat: torch.Tensor, layout: Layout, sampling_loc: torch.Tensor,
               weights: torch.Tensor, level_scale: Optional[torch.Tensor] = None,
-              deterministic: bool = False, tile: Optional[dict] = None):
+              deterministic: bool = False, tile: Optional[dict] = None, logits: bool = False):
     """Build the msda_desc for these tensors (shapes are checked here and,
     authoritatively, by the library)."""
     if feat.dim() != 3 or sampling_loc.dim() != 5 or weights.dim() != 6:
@@ -107,7 +107,9 @@ def make_desc(feat: torch.Tensor, layout: Layout, sampling_loc: torch.Tensor,
     d.host_spatial_shapes = layout.host_shapes.ctypes.data
     d.host_level_start_index = layout.host_starts.ctypes.data
     d.level_scale = level_scale.data_ptr() if level_scale is not None else None
-    d.flags = _lib.MSDA_DETERMINISTIC if deterministic else 0
+    d.flags = ((_lib.MSDA_DETERMINISTIC if deterministic else 0) |
+               (_lib.MSDA_WEIGHT_LOGITS if logits else 0) |
+               (_lib.MSDA_WEIGHTS_BF16 if weights.dtype == torch.bfloat16 else 0))
     keep = [layout]
     if tile:
         t = tile_struct(tile)
@@ -115,6 +117,12 @@ def make_desc(feat: torch.Tensor, layout: Layout, sampling_loc: torch.Tensor,
         d.tile = ctypes.pointer(t)
     d._keep = keep        # host arrays must outlive the call
     return d
+
+
+def _need_weights(weights):
+    _need_cuda_contig("weights", weights)
+    if weights.dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError(f"weights must be float32 or bfloat16, got {weights.dtype}")
 
 
 def _resolve_tile(tile, which, feat, sampling_loc, weights):
@@ -147,26 +155,29 @@ def _workspace(nbytes: int, workspace: Optional[torch.Tensor], device):
     return ctypes.c_void_p(aligned), n, workspace
 
 
-def forward_workspace_bytes(feat, layout, sampling_loc, weights, tile=None) -> int:
-    d = make_desc(feat, layout, sampling_loc, weights, tile=tile)
+def forward_workspace_bytes(feat, layout, sampling_loc, weights, tile=None,
+                            logits=False) -> int:
+    d = make_desc(feat, layout, sampling_loc, weights, tile=tile, logits=logits)
     return int(_lib.load().msda_forward_workspace_size(ctypes.byref(d)))
 
 
 def forward(feat, layout: Layout, sampling_loc, weights, level_scale=None, tile=None,
             out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
-            stream=None) -> torch.Tensor:
+            stream=None, logits: bool = False) -> torch.Tensor:
     """out [B, A, C] FP32 = MSDA(feat, loc, weights) on the current stream.
     tile: None (the library's choice), a dict of msda_tile fields, or "auto".
     workspace: optional uint8 device tensor for the view-order forward (one
-    is allocated when needed and not given)."""
+    is allocated when needed and not given). weights: FP32 or BF16; logits:
+    they are logits and the per-group softmax over (keypoint, camera, level)
+    is applied inside."""
     lib = _lib.load()
     tile = _resolve_tile(tile, "forward", feat, sampling_loc, weights)
     _need_cuda_contig("feat", feat)
     _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
-    _need_cuda_contig("weights", weights, torch.float32)
+    _need_weights(weights)
     if level_scale is not None:
         _need_cuda_contig("level_scale", level_scale, torch.float32)
-    d = make_desc(feat, layout, sampling_loc, weights, level_scale, tile=tile)
+    d = make_desc(feat, layout, sampling_loc, weights, level_scale, tile=tile, logits=logits)
     if out is None:
         out = torch.empty(d.batch, d.num_anchors, d.channels, device=feat.device,
                           dtype=torch.float32)
@@ -179,28 +190,33 @@ def forward(feat, layout: Layout, sampling_loc, weights, level_scale=None, tile=
 
 
 def backward_workspace_bytes(feat, layout, sampling_loc, weights, deterministic=False,
-                             tile=None) -> int:
-    d = make_desc(feat, layout, sampling_loc, weights, deterministic=deterministic, tile=tile)
+                             tile=None, logits=False) -> int:
+    d = make_desc(feat, layout, sampling_loc, weights, deterministic=deterministic, tile=tile,
+                  logits=logits)
     return int(_lib.load().msda_backward_workspace_size(ctypes.byref(d)))
 
 
 def backward(feat, layout: Layout, sampling_loc, weights, grad_out,
              need_feat=True, need_loc=True, need_w=True, deterministic=False, tile=None,
-             workspace: Optional[torch.Tensor] = None, level_scale=None, stream=None
+             workspace: Optional[torch.Tensor] = None, level_scale=None, stream=None,
+             logits: bool = False
              ) -> Tuple[Optional[torch.Tensor], Optional[torch.Tensor], Optional[torch.Tensor]]:
-    """(grad_feat, grad_sampling_loc, grad_weights); an unrequested one is None."""
+    """(grad_feat, grad_sampling_loc, grad_weights); an unrequested one is None.
+    grad_weights is FP32 (with logits=True: the gradient of the logits)."""
     lib = _lib.load()
     tile = _resolve_tile(tile, "backward", feat, sampling_loc, weights)
     _need_cuda_contig("feat", feat)
     _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
-    _need_cuda_contig("weights", weights, torch.float32)
+    _need_weights(weights)
     _need_cuda_contig("grad_out", grad_out, torch.float32)
     d = make_desc(feat, layout, sampling_loc, weights, level_scale, deterministic=deterministic,
-                  tile=tile)
+                  tile=tile, logits=logits)
     gf = torch.empty_like(feat) if need_feat else None
     gl = torch.empty_like(sampling_loc) if need_loc else None
-    gw = torch.empty_like(weights) if need_w else None
-    ws_bytes = int(lib.msda_backward_workspace_size(ctypes.byref(d))) if need_feat else 0
+    gw = torch.empty(weights.shape, dtype=torch.float32, device=weights.device) if need_w else None
+    weight_flags = logits or weights.dtype == torch.bfloat16
+    ws_bytes = (int(lib.msda_backward_workspace_size(ctypes.byref(d)))
+                if need_feat or weight_flags else 0)
     ws_ptr, ws_len, workspace = _workspace(ws_bytes, workspace, feat.device)
     _lib.check(lib.msda_backward(_ptr(feat), _ptr(layout.shapes), _ptr(layout.starts),
                                  _ptr(sampling_loc), _ptr(weights), _ptr(grad_out), _ptr(gf),
@@ -381,14 +397,19 @@ def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
 
 class MSDAFunction(torch.autograd.Function):
     """Differentiable MSDA: forward and backward are the library's kernels.
-    No gradient flows to the geometry or to the FP8 level scales."""
+    No gradient flows to the geometry or to the FP8 level scales. With
+    logits=True the weights argument holds logits (softmax applied inside)
+    and receives their gradient; a BF16 weights tensor gets an FP32
+    gradient cast to BF16 by autograd's dtype rule."""
 
     @staticmethod
-    def forward(ctx, feat, sampling_loc, weights, layout, level_scale, deterministic, tile):
-        out = forward(feat, layout, sampling_loc, weights, level_scale=level_scale, tile=tile)
+    def forward(ctx, feat, sampling_loc, weights, layout, level_scale, deterministic, tile,
+                logits):
+        out = forward(feat, layout, sampling_loc, weights, level_scale=level_scale, tile=tile,
+                      logits=logits)
         ctx.save_for_backward(feat, sampling_loc, weights)
         ctx.layout, ctx.deterministic, ctx.tile = layout, deterministic, tile
-        ctx.level_scale = level_scale
+        ctx.level_scale, ctx.logits = level_scale, logits
         return out
 
     @staticmethod
@@ -400,14 +421,17 @@ class MSDAFunction(torch.autograd.Function):
             gf, gl, gw = backward(feat, ctx.layout, loc, w, grad_out.contiguous(),
                                   need_feat=nf, need_loc=nl, need_w=nw,
                                   deterministic=ctx.deterministic, tile=ctx.tile,
-                                  level_scale=ctx.level_scale)
-        return gf, gl, gw, None, None, None, None
+                                  level_scale=ctx.level_scale, logits=ctx.logits)
+            if gw is not None and gw.dtype != w.dtype:
+                gw = gw.to(w.dtype)
+        return gf, gl, gw, None, None, None, None, None
 
 
 def msda(feat, layout: Layout, sampling_loc, weights, level_scale=None, deterministic=False,
-         tile=None):
-    """Autograd-aware MSDA."""
-    return MSDAFunction.apply(feat, sampling_loc, weights, layout, level_scale, deterministic, tile)
+         tile=None, logits=False):
+    """Autograd-aware MSDA (logits=True: weights are per-group softmax logits)."""
+    return MSDAFunction.apply(feat, sampling_loc, weights, layout, level_scale, deterministic,
+                              tile, logits)
 
 
 class SceneBatch:

@@ -1,0 +1,173 @@
+"""Fused weight generation on the GPU against the FP64 oracle: MSDA with
+per-group softmax logits (forward applies the softmax while staging the
+weights; backward returns the logits' gradient), BF16 weights and logits,
+masked (-inf) logits, both work orders, the argument checks, and the
+64-camera workload on sampled anchors."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import (FWD_F32_MAXREL, FWD_F32_TOL, GRAD_F32_MAXREL, GRAD_F32_TOL, anchor_subset,
+                     assert_close, host, to_device)
+from paper_2601_10819_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_2601_10819_amd import ops as o
+    o._lib.load()
+    return o
+
+
+@pytest.fixture(scope="module")
+def ow():
+    from oracle import weights
+    return weights
+
+
+def logits_for(p, seed, scale=2.0):
+    g = torch.Generator().manual_seed(seed)
+    return torch.randn(p.weights.shape, generator=g) * scale
+
+
+CASES = [
+    # (seed, B, cams, levels, C, G, A, P, feat dtype, weights dtype, order)
+    (0, 2, 7, ((11, 13), (6, 7), (3, 3)), 64, 4, 37, 5, torch.float32, torch.float32, "anchor"),
+    (1, 2, 7, ((11, 13), (6, 7), (3, 3)), 64, 4, 37, 5, torch.float32, torch.float32, "view"),
+    (2, 1, 12, ((9, 10), (5, 5)), 256, 8, 25, 3, torch.bfloat16, torch.bfloat16, "view"),
+    (3, 3, 5, ((8, 12), (4, 6), (2, 3), (1, 2)), 128, 8, 9, 13, torch.float16, torch.float32,
+     "anchor"),
+]
+
+
+@pytest.mark.parametrize("i", range(len(CASES)))
+def test_logits_match_oracle(ops, ow, i):
+    seed, B, cams, levels, C, G, A, P, fdt, wdt, order = CASES[i]
+    p = synth.small(seed=400 + seed, B=B, cams=cams, levels=levels, C=C, G=G, A=A, P=P)
+    print(f"case {i} {p.dims()} feat {fdt} logits {wdt} {order}", flush=True)
+    feat, layout, loc, _ = to_device(p, fdt)
+    x = logits_for(p, seed).to(wdt)
+    go = synth.grad_out_like(p, seed=20 + i)
+    tile = {"order": order}
+    out = ops.forward(feat, layout, loc, x.cuda(), tile=tile, logits=True)
+    gf, gl, gx = ops.backward(feat, layout, loc, x.cuda(), go.cuda(), tile=tile, logits=True)
+    torch.cuda.synchronize()
+    f64 = p.feat.to(fdt).double()
+    x64 = x.double()                                  # the stored logits, widened exactly
+    ref = ow.forward_logits(f64, p.spatial_shapes, p.level_start_index, p.sampling_loc, x64)
+    assert_close(host(out), ref, FWD_F32_TOL, FWD_F32_MAXREL, f"case {i} out")
+    rgf, rgl, rgx = ow.backward_logits(f64, p.spatial_shapes, p.level_start_index,
+                                       p.sampling_loc, x64, go.numpy())
+    if fdt == torch.float32:
+        assert_close(host(gf), rgf, GRAD_F32_TOL, GRAD_F32_MAXREL, f"case {i} grad_feat")
+    assert_close(host(gl), rgl, GRAD_F32_TOL, GRAD_F32_MAXREL, f"case {i} grad_loc")
+    assert gx.dtype == torch.float32
+    assert_close(host(gx), rgx, GRAD_F32_TOL, GRAD_F32_MAXREL, f"case {i} grad_logits")
+
+
+def test_bf16_weights_without_softmax(ops, oracle_mod):
+    """BF16 weights are widened exactly: the operator on them equals the
+    oracle on the widened values; grad_weights is FP32."""
+    p = synth.small(seed=41, B=2, cams=6, levels=((12, 16), (6, 8), (3, 4)), C=64, G=4, A=30,
+                    P=7)
+    feat, layout, loc, w = to_device(p)
+    wb = w.to(torch.bfloat16)
+    go = synth.grad_out_like(p, seed=3)
+    for order in ("anchor", "view"):
+        out = ops.forward(feat, layout, loc, wb, tile={"order": order})
+        gf, gl, gw = ops.backward(feat, layout, loc, wb, go.cuda(), tile={"order": order})
+        torch.cuda.synchronize()
+        w64 = wb.double().cpu()
+        ref = oracle_mod.forward(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                                 w64)
+        assert_close(host(out), ref, FWD_F32_TOL, FWD_F32_MAXREL, f"{order} out")
+        rgf, rgl, rgw = oracle_mod.backward(p.feat, p.spatial_shapes, p.level_start_index,
+                                            p.sampling_loc, w64, go)
+        assert gw.dtype == torch.float32
+        for got, want, what in ((gf, rgf, "grad_feat"), (gl, rgl, "grad_loc"),
+                                (gw, rgw, "grad_w")):
+            assert_close(host(got), want, GRAD_F32_TOL, GRAD_F32_MAXREL, f"{order} {what}")
+
+
+def test_masked_logits(ops, ow):
+    """-inf logits are masked entries: weight 0, logit gradient exactly 0."""
+    p = synth.small(seed=42, B=1, cams=4, levels=((10, 12), (5, 6)), C=64, G=4, A=20, P=6)
+    feat, layout, loc, _ = to_device(p)
+    x = logits_for(p, 9)
+    mask = torch.rand(x.shape, generator=torch.Generator().manual_seed(10)) < 0.4
+    mask[:, :, 0, 0, 0, :] = False                    # one live entry per group
+    x = x.masked_fill(mask, float("-inf"))
+    go = synth.grad_out_like(p, seed=11)
+    out = ops.forward(feat, layout, loc, x.cuda(), logits=True)
+    _, gl, gx = ops.backward(feat, layout, loc, x.cuda(), go.cuda(), logits=True)
+    torch.cuda.synchronize()
+    ref = ow.forward_logits(p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc, x)
+    assert_close(host(out), ref, FWD_F32_TOL, FWD_F32_MAXREL, "masked out")
+    _, rgl, rgx = ow.backward_logits(p.feat, p.spatial_shapes, p.level_start_index,
+                                     p.sampling_loc, x, go.numpy())
+    assert_close(host(gl), rgl, GRAD_F32_TOL, GRAD_F32_MAXREL, "masked grad_loc")
+    assert_close(host(gx), rgx, GRAD_F32_TOL, GRAD_F32_MAXREL, "masked grad_logits")
+    assert torch.all(gx.cpu()[mask] == 0)
+
+
+def test_argument_checks(ops):
+    p = synth.small(seed=43, B=1, cams=4, A=6, P=3)
+    feat, layout, loc, w = to_device(p)
+    lib = ops._lib.load()
+    out = torch.empty(1, 6, p.channels, device="cuda")
+    d = ops.make_desc(feat, layout, loc, w, logits=True)
+    # the softmax statistics live in the workspace: msda_forward has none
+    st = lib.msda_forward(ops._ptr(feat), ops._ptr(layout.shapes), ops._ptr(layout.starts),
+                          ops._ptr(loc), ops._ptr(w), ops._ptr(out), ctypes.byref(d), None)
+    assert st == 4, lib.msda_last_error()
+    d.flags = 64                                     # an unknown flag
+    st = lib.msda_forward(ops._ptr(feat), ops._ptr(layout.shapes), ops._ptr(layout.starts),
+                          ops._ptr(loc), ops._ptr(w), ops._ptr(out), ctypes.byref(d), None)
+    assert st == 1, lib.msda_last_error()
+    # the visible-view forms take no weight flags
+    v = torch.ones(1, 6, 4, dtype=torch.uint8, device="cuda")
+    d = ops.make_desc(feat, layout, loc, w, logits=True)
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    st = lib.msda_forward_visible(ops._ptr(feat), ops._ptr(layout.shapes),
+                                  ops._ptr(layout.starts), ops._ptr(loc), ops._ptr(w),
+                                  ops._ptr(v), ops._ptr(out), ops._ptr(ws), ws.numel(),
+                                  ctypes.byref(d), None)
+    assert st == 2, lib.msda_last_error()
+    torch.cuda.synchronize()
+
+
+def test_logits_64cam_sampled(ops, ow):
+    """The 64-camera workload (BF16 features) with FP32 logits in the
+    benchmark's launch configuration: sampled anchors against the oracle
+    (the softmax is per anchor, so a subset is self-contained)."""
+    p = synth.cam64()
+    feat, layout, loc, _ = to_device(p, torch.bfloat16)
+    x = logits_for(p, 12)
+    go = synth.grad_out_like(p, seed=13)
+    out = ops.forward(feat, layout, loc, x.cuda(), logits=True)
+    _, gl, gx = ops.backward(feat, layout, loc, x.cuda(), go.cuda(), logits=True,
+                             need_feat=True)
+    torch.cuda.synchronize()
+    idx = anchor_subset(p, 12, seed=6)
+    f64 = p.feat.to(torch.bfloat16).double()
+    xs = x[:, idx].contiguous()
+    ls = p.sampling_loc[:, idx].contiguous()
+    ref = ow.forward_logits(f64, p.spatial_shapes, p.level_start_index, ls, xs)
+    assert_close(host(out)[:, idx], ref, FWD_F32_TOL, FWD_F32_MAXREL, "64cam logits out")
+    _, rgl, rgx = ow.backward_logits(f64, p.spatial_shapes, p.level_start_index, ls, xs,
+                                     go.numpy()[:, idx])
+    assert_close(host(gl)[:, idx], rgl, GRAD_F32_TOL, GRAD_F32_MAXREL, "64cam grad_loc")
+    assert_close(host(gx)[:, idx], rgx, GRAD_F32_TOL, GRAD_F32_MAXREL, "64cam grad_logits")
+    # every group of the logits' gradient sums to zero
+    s = gx.double().sum(dim=(2, 3, 4))
+    assert float(s.abs().max()) <= 1e-5 * float(gx.double().abs().sum(dim=(2, 3, 4)).max())
