@@ -266,6 +266,14 @@ __device__ __forceinline__ void add_sample_at(int pos, float (&acc)[4][4][CPL], 
 #undef MSDA_CELL_CASE
 }
 
+// One sample of a statically known cell (DY, DX): the arithmetic of the
+// switch's case (DY * 5 + DX).
+template <int DY, int DX, int CPL>
+__device__ __forceinline__ void cell_sample(float (&acc)[4][4][CPL], float fx, float fy,
+                                            float wv, const float* gv) {
+    add_sample<DY, DX, 4, 4, CPL>(acc, fx, fy, wv, gv);
+}
+
 // Cell boundaries of a tile's TH+1 cell rows, (TW+2) per row.
 constexpr int kBndPerGroup = (kTileH + 1) * (kTileW + 2);
 
@@ -304,7 +312,12 @@ struct TileView {
 
 // The reduction of one tile by a group of lps lanes (grp-th group of its
 // wave, lane sl within it); `waves` waves of the block share its records.
-template <class OT, int CPL, bool WHOLE_WAVE>
+// CELLS (whole-wave groups only): walk each chunk's records cell by cell in
+// a static loop over the tile's 5x5 cells, so every record's corner ->
+// pixel map is a compile-time constant (no per-record dispatch); records of
+// a cell are consecutive in the sorted order, so the visiting order, and
+// the sums, are those of the flat walk.
+template <class OT, int CPL, bool WHOLE_WAVE, bool CELLS>
 __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, const int spw,
                                             const int grp, const int sl, const int waves,
                                             u32* bnd_lds, float* work) {
@@ -401,6 +414,56 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if constexpr (CELLS && WHOLE_WAVE) {
+            // flat index of each row's first record, then each cell's run
+            // clipped to this chunk [base, base + n)
+            u32 f0 = 0;
+            static_for<TH + 1>([&](auto dyc) {
+                constexpr int DY = decltype(dyc)::value;
+                const u32 rlen = (u32)uniform((int)rn[DY]);
+                if (rlen) {
+                    const u32 rstart = (u32)uniform((int)rs[DY]);
+                    static_for<TW + 1>([&](auto dxc) {
+                        constexpr int DX = decltype(dxc)::value;
+                        const u32 e0 = (u32)uniform((int)bslot[DY * (TW + 2) + DX]);
+                        const u32 e1 = (u32)uniform((int)bslot[DY * (TW + 2) + DX + 1]);
+                        const u32 lo = max(f0 + (e0 - rstart), base);
+                        const u32 hi = min(f0 + (e1 - rstart), base + (u32)n);
+                        int qq = (int)lo - (int)base;
+                        const int qe = (int)hi - (int)base;
+                        for (; qq + 4 <= qe; qq += 4) {
+                            float gv[4][CPL];
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                const float* ent = tab + (qq + k) * stride;
+                                load_go<CPL>(v.grad_out +
+                                                 (size_t)__float_as_uint(ent[v.G + 2]) * v.C + c0,
+                                             gv[k]);
+                            }
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                const float* ent = tab + (qq + k) * stride;
+                                cell_sample<DY, DX, CPL>(acc, ent[v.G], ent[v.G + 1], ent[g],
+                                                         gv[k]);
+                            }
+                        }
+                        for (; qq < qe; ++qq) {
+                            const float* ent = tab + qq * stride;
+                            float gv[CPL];
+                            load_go<CPL>(v.grad_out + (size_t)__float_as_uint(ent[v.G + 2]) * v.C +
+                                             c0,
+                                         gv);
+                            cell_sample<DY, DX, CPL>(acc, ent[v.G], ent[v.G + 1], ent[g], gv);
+                        }
+                    });
+                }
+                f0 += rlen;
+            });
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            continue;
+        }
         int q = 0;
         for (; q + kGoBatch <= n; q += kGoBatch) {
             float gv[kGoBatch][CPL];
@@ -473,7 +536,7 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
     }
 }
 
-template <class OT, int CPL, bool WHOLE_WAVE>
+template <class OT, int CPL, bool WHOLE_WAVE, bool CELLS>
 __global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
     static_assert(kTileH == 4 && kTileW == 4, "the cell dispatch is written for 4x4 tiles");
     // LDS: per lane group its tile's cell boundaries; per wave a record table
@@ -529,7 +592,7 @@ __global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
     v.vscale = t.view_scale;
     v.N = t.N;
     v.L = t.L;
-    tile_reduce<OT, CPL, WHOLE_WAVE>(v, lps, spw, grp, sl, t.waves, bnd_lds, work);
+    tile_reduce<OT, CPL, WHOLE_WAVE, CELLS>(v, lps, spw, grp, sl, t.waves, bnd_lds, work);
 }
 
 // Batched tiled reduction: tiles of all scenes' regions in slot order.
@@ -578,7 +641,7 @@ __global__ void __launch_bounds__(256) gfeat_tile_batched_kernel(BatchArgs b) {
     v.vscale = nullptr;
     v.N = 1;
     v.L = 1;
-    tile_reduce<OT, CPL, WHOLE_WAVE>(v, lps, spw, grp, sl, b.waves, bnd_lds, work);
+    tile_reduce<OT, CPL, WHOLE_WAVE, WHOLE_WAVE>(v, lps, spw, grp, sl, b.waves, bnd_lds, work);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -645,12 +708,13 @@ static hipError_t tile_launch(const TileArgs& t, hipStream_t s) {
     const size_t tables = (size_t)t.waves * 64 * (t.G + 4) * sizeof(float);
     const size_t lds = bnd_lds_bytes(t.waves, t.lps_shift) + (part > tables ? part : tables);
     mark_begin(t.waves > 1 ? "gfeat_tile_kernel_coarse" : "gfeat_tile_kernel", s);
+    // whole-wave groups walk each chunk cell by cell
     if (t.lps_shift == 6)
-        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL, true>), dim3(blocks), dim3(64 * t.waves),
-                           lds, s, t);
+        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL, true, true>), dim3(blocks),
+                           dim3(64 * t.waves), lds, s, t);
     else
-        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL, false>), dim3(blocks), dim3(64 * t.waves),
-                           lds, s, t);
+        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL, false, false>), dim3(blocks),
+                           dim3(64 * t.waves), lds, s, t);
     mark_end(s);
     return hipGetLastError();
 }
