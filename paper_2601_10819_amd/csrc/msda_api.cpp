@@ -383,6 +383,9 @@ static msda_status forward_impl(const void* feat, const int32_t* spatial_shapes,
     int cpl = 0, waves = 0;
     msda_status st = prepare(desc, order, &a, &cpl, &waves);
     if (st != MSDA_OK) return st;
+    // the view-order forward runs fastest with one wave (one anchor row) per
+    // workgroup (measured on the 64-camera workload in FP32 and BF16)
+    if (order == MSDA_ORDER_VIEW && !(desc->tile && desc->tile->waves_per_anchor)) waves = 1;
     // sampling_loc, weights and out hold zero elements when A == 0 and may be NULL then
     if (!feat || !spatial_shapes || !level_start_index ||
         (a.A > 0 && (!sampling_loc || !weights || !out)))
