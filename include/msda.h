@@ -348,19 +348,26 @@ typedef struct msda_batch {
 size_t msda_batched_workspace_size(const msda_batch* batch, int32_t backward);
 
 /*
- * Forward of every scene of the batch in one persistent launch (workgroups
- * stride over all anchors of all scenes). workspace: device, 256-byte
- * aligned, >= msda_batched_workspace_size(batch, 0). Validation as for
- * msda_forward, per scene; in addition at most 4096 (camera, level) regions
- * over all scenes.
+ * Forward of every scene of the batch in one launch per pass. Work order
+ * (msda_batch.tile->order): view order by default -- each scene's (camera,
+ * anchor) items are split over the 8 XCD slots exactly as a single call with
+ * B = 1 splits them, one wave per (slot, anchor) row, then one kernel adds
+ * the slots' partial sums in slot order, so every scene's result is bitwise
+ * the single call's in view order; MSDA_ORDER_ANCHOR: persistent workgroups
+ * stride over all anchors of all scenes (bitwise the single call's in
+ * anchor order). workspace: device, 256-byte aligned, >=
+ * msda_batched_workspace_size(batch, 0) (it includes the view order's
+ * 8 * anchors * C FP32 partial sums in either order). Validation as for
+ * msda_forward, per scene; in addition at most 4096 (camera, level)
+ * regions over all scenes.
  */
 msda_status msda_forward_batched(const msda_batch* batch, void* workspace,
                                  size_t workspace_bytes, void* stream);
 
 /*
- * Backward of every scene: one persistent gather launch for all anchors of
- * all scenes, one sort of all scenes' grad_feat records, one tiled
- * reduction over all scenes' pixels (two launches: coarse, fine). A
+ * Backward of every scene: one gather launch for all anchors of all scenes
+ * (in the forward's work order), one sort of all scenes' grad_feat records,
+ * one tiled reduction over all scenes' pixels (two launches: coarse, fine). A
  * gradient pointer must be NULL in every scene or in none. Only the sorted
  * grad_feat form is available here. workspace: >=
  * msda_batched_workspace_size(batch, 1).

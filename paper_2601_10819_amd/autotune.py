@@ -183,7 +183,7 @@ def tune_batch(batch, reps: int = 3, save: bool = True, path: Optional[str] = No
     ref = [t.clone() for t in batch.out + [g for g in batch.grad_feat if g is not None]]
     best = None
     tol = 1e-2 if batch.dtype in (torch.bfloat16, torch.float16) else 1e-4
-    for t in candidates(batch.dtype, batch.C, batch.G, orders=("anchor",)):
+    for t in candidates(batch.dtype, batch.C, batch.G, orders=("anchor", "view")):
         batch.set_tile(t)
         batch.forward()
         batch.backward()

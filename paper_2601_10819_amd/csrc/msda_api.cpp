@@ -987,10 +987,14 @@ namespace {
 
 struct BatchWs {
     size_t anchor_start, sample_start, region_start, cell_start, slot_scene, slot_region,
-        tile_start, magic, magic_shift, keys_a, keys_b, vals_a, vals_b, frac, off, scratch, total;
+        tile_start, magic, magic_shift, keys_a, keys_b, vals_a, vals_b, frac, off, scratch, part,
+        total;
 };
 
-BatchWs batch_layout(uint64_t S, uint64_t regions, uint64_t nsamp, uint64_t ncells, bool records) {
+// part_bytes: the view-order forward's per-slot partial sums (always part of
+// the forward's workspace, so that the order can change without resizing).
+BatchWs batch_layout(uint64_t S, uint64_t regions, uint64_t nsamp, uint64_t ncells, bool records,
+                     uint64_t part_bytes = 0) {
     BatchWs w = {};
     size_t at = 0;
     auto take = [&](size_t bytes) { const size_t here = at; at += align256(bytes); return here; };
@@ -1012,6 +1016,7 @@ BatchWs batch_layout(uint64_t S, uint64_t regions, uint64_t nsamp, uint64_t ncel
         w.off = take((ncells + 1) * 4);
         w.scratch = take(msda::sort_scratch_words((uint32_t)nsamp) * 4);
     }
+    if (part_bytes) w.part = take(part_bytes);
     w.total = at;
     return w;
 }
@@ -1022,6 +1027,10 @@ struct BatchPlan {
     int max_regions_per_scene, max_cams;
     int cpl, waves;
     int64_t max_batch_bytes;
+    int order;                    // MSDA_ORDER_ANCHOR or MSDA_ORDER_VIEW
+    int view_cams;                // view order: cameras of a row at most
+    int view_waves_fwd, view_waves_bwd;
+    uint64_t part_bytes;          // view-order forward partials
 };
 
 // Validates the batch (every scene against its host mirrors) and sizes it.
@@ -1119,10 +1128,28 @@ msda_status plan_batch(const msda_batch* b, bool backward, BatchPlan* p) {
     d.host_spatial_shapes = shp.data();
     d.host_level_start_index = st.data();
     d.level_scale = b->level_scale;
-    if (b->tile && b->tile->order == MSDA_ORDER_VIEW)
-        return fail(MSDA_ERR_UNSUPPORTED, "the batched form runs in anchor order only");
     msda_status stt = prepare(&d, MSDA_ORDER_ANCHOR, &a, &p->cpl, &p->waves);
     if (stt != MSDA_OK) return stt;
+    // work order: view order (one camera range per XCD) unless anchor order
+    // is asked for; each scene is split over the XCD slots as a single call
+    // with B = 1 would be, and a row covers at most max_cams / 8 + 2 cameras
+    const int req = b->tile ? b->tile->order : MSDA_ORDER_AUTO;
+    if (req != MSDA_ORDER_AUTO && req != MSDA_ORDER_ANCHOR && req != MSDA_ORDER_VIEW)
+        return fail(MSDA_ERR_UNSUPPORTED, "unknown order %d", req);
+    p->order = req == MSDA_ORDER_ANCHOR ? MSDA_ORDER_ANCHOR : MSDA_ORDER_VIEW;
+    p->view_cams = p->max_cams / msda::kSlots + 2;
+    const int tw = b->tile ? b->tile->waves_per_anchor : 0;
+    p->view_waves_fwd = tw ? tw : 1;
+    p->view_waves_bwd = tw ? tw : 4;
+    p->part_bytes = (uint64_t)msda::kSlots * p->anchors * (uint64_t)b->channels * sizeof(float);
+    if (p->order == MSDA_ORDER_VIEW) {
+        const int J = msda::max_pairs_per_chunk(b->num_levels, b->groups);
+        const int wmax = std::max(p->view_waves_fwd, p->view_waves_bwd);
+        const size_t need = msda::batch_view_lds(p->view_cams, b->num_levels, J, b->groups, wmax);
+        if (need > 65536)
+            return fail(MSDA_ERR_UNSUPPORTED, "view-order batched launch needs %zu bytes of LDS",
+                        need);
+    }
     return MSDA_OK;
 }
 
@@ -1152,6 +1179,7 @@ void fill_batch_args(const msda_batch* b, const BatchPlan& p, char* ws, const Ba
     a->lps_shift = log2i(b->channels / p.cpl);
     a->pairs_per_chunk = msda::max_pairs_per_chunk(b->num_levels, b->groups);
     a->max_regions_per_scene = p.max_regions_per_scene;
+    a->view_cams = p.view_cams;
 }
 
 size_t batch_lds(const msda_batch* b, const BatchPlan& p) {
@@ -1202,7 +1230,8 @@ size_t msda_batched_workspace_size(const msda_batch* b, int32_t backward) {
     if (plan_batch(b, backward != 0, &p) != MSDA_OK) return 0;
     bool gf = false, gl = false, gw = false;
     if (backward && batch_grads(b, &gf, &gl, &gw) != MSDA_OK) return 0;
-    return batch_layout(b->num_scenes, p.regions, p.samples, p.cells, backward && gf).total;
+    return batch_layout(b->num_scenes, p.regions, p.samples, p.cells, backward && gf,
+                        backward ? 0 : p.part_bytes).total;
 }
 
 msda_status msda_forward_batched(const msda_batch* b, void* workspace, size_t workspace_bytes,
@@ -1210,7 +1239,8 @@ msda_status msda_forward_batched(const msda_batch* b, void* workspace, size_t wo
     BatchPlan p;
     msda_status st = plan_batch(b, false, &p);
     if (st != MSDA_OK) return st;
-    const BatchWs w = batch_layout(b->num_scenes, p.regions, p.samples, p.cells, false);
+    const BatchWs w = batch_layout(b->num_scenes, p.regions, p.samples, p.cells, false,
+                                   p.part_bytes);
     if (!workspace || workspace_bytes < w.total)
         return fail(MSDA_ERR_WORKSPACE, "workspace of %zu bytes needed", w.total);
     if (!aligned(workspace, 256)) return fail(MSDA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
@@ -1222,8 +1252,16 @@ msda_status msda_forward_batched(const msda_batch* b, void* workspace, size_t wo
     hipError_t e = msda::launch_batch_tables(a, false, s);
     if (e != hipSuccess) return hip_fail(e, "batch tables");
     if (p.anchors == 0) return ok();
-    e = msda::launch_forward_batched(a, b->feat_dtype, p.cpl, p.waves,
-                                     persistent_blocks(p.anchors, p.waves), lds, s);
+    if (p.order == MSDA_ORDER_VIEW) {
+        const size_t vlds = msda::batch_view_lds(p.view_cams, b->num_levels, a.pairs_per_chunk,
+                                                 b->groups, p.view_waves_fwd);
+        e = msda::launch_forward_batched_view(
+            a, b->feat_dtype, p.cpl, p.view_waves_fwd, vlds,
+            reinterpret_cast<float*>(static_cast<char*>(workspace) + w.part), s);
+    } else {
+        e = msda::launch_forward_batched(a, b->feat_dtype, p.cpl, p.waves,
+                                         persistent_blocks(p.anchors, p.waves), lds, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "msda_forward_batched launch");
     return ok();
 }
@@ -1303,11 +1341,19 @@ msda_status msda_backward_batched(const msda_batch* b, void* workspace, size_t w
             }
         }
     }
-    if (p.anchors > 0 && (gf || gl || gw) &&
-        (e = msda::launch_backward_batched(a, b->feat_dtype, p.cpl, p.waves,
-                                           persistent_blocks(p.anchors, p.waves), lds, s)) !=
-            hipSuccess)
-        return hip_fail(e, "msda_backward_batched launch");
+    if (p.anchors > 0 && (gf || gl || gw)) {
+        if (p.order == MSDA_ORDER_VIEW) {
+            const size_t vlds = msda::batch_view_lds(p.view_cams, b->num_levels,
+                                                     a.pairs_per_chunk, b->groups,
+                                                     p.view_waves_bwd);
+            e = msda::launch_backward_batched_view(a, b->feat_dtype, p.cpl, p.view_waves_bwd,
+                                                   vlds, s);
+        } else {
+            e = msda::launch_backward_batched(a, b->feat_dtype, p.cpl, p.waves,
+                                              persistent_blocks(p.anchors, p.waves), lds, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "msda_backward_batched launch");
+    }
     if (!gf) return ok();
     uint32_t* sorted = nullptr;
     uint32_t* off = reinterpret_cast<uint32_t*>(ws + w.off);

@@ -125,6 +125,42 @@ __global__ void __launch_bounds__(512) msda_bwd_batched_kernel(BatchArgs b) {
     }
 }
 
+// Batched backward gather in view order (see msda_fwd_batched_view_kernel):
+// one wave per (XCD slot, global anchor) row over the anchor's cameras in
+// the slot; every output is per sample or per pair.
+template <class FT, int CPL>
+__global__ void __launch_bounds__(512) msda_bwd_batched_view_kernel(BatchArgs b) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int x = (int)(blockIdx.x % kSlots);
+    const int wave = wave_index(), nwaves = blockDim.x >> 6;
+    const u32 g = (blockIdx.x / kSlots) * (u32)nwaves + (u32)wave;
+    if (g >= b.total_anchors) return;
+    const BatchRow row = batch_row(b, x, g);
+    if (row.nv == 0) return;
+    unsigned char* mine =
+        smem + (size_t)wave * batch_view_wave_bytes(b.view_cams, b.L, b.pairs_per_chunk, b.G);
+    Geo* geo = reinterpret_cast<Geo*>(mine);
+    unsigned char* work =
+        mine + (((size_t)b.view_cams * b.L * sizeof(Geo) + 15) & ~(size_t)15);
+    const OpArgs a = scene_view(b, row.s, FT::kBytes);
+    const Lanes q = lanes_of<FT, CPL>(a);
+    stage_geometry_range(geo, a, row.n_lo, row.nv, q.lane);
+
+    const int J = a.pairs_per_chunk;
+    const StageSlot st = stage_slot(work, 0, J, a.L, a.G);
+    float go[CPL];
+    const BwdAnchor xa = bwd_anchor_ctx<FT, CPL>(a, row.a, q, go);
+    const ViewOrder order{a.N, a.P, row.n_lo, row.n_lo};
+    const int nk = row.nv * a.P;
+    for (int k0 = 0; k0 < nk; k0 += J) {
+        const int nj = min(J, nk - k0);
+        stage_chunk<false, true>(st, order, k0, nj, xa.gw, xa.gl, geo, a.L, a.L * a.G,
+                                 (u32)a.C * FT::kBytes, q.lane, xa.rec);
+        bwd_chunk<FT, CPL>(a, st, nj, geo, q, xa, go);
+        end_chunk();
+    }
+}
+
 template <int I>
 using int_c = std::integral_constant<int, I>;
 
@@ -727,6 +763,34 @@ static hipError_t bwd_batched_launch(const BatchArgs& b, int waves, int blocks, 
                        b);
     mark_end(s);
     return hipGetLastError();
+}
+
+template <class FT, int CPL>
+static hipError_t bwd_batched_view_launch(const BatchArgs& b, int waves, size_t lds,
+                                          hipStream_t s) {
+    const unsigned blocks =
+        (unsigned)(kSlots * (((size_t)b.total_anchors + waves - 1) / (size_t)waves));
+    mark_begin("msda_bwd_batched_view_kernel", s);
+    hipLaunchKernelGGL((msda_bwd_batched_view_kernel<FT, CPL>), dim3(blocks), dim3(64 * waves),
+                       lds, s, b);
+    mark_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward_batched_view(const BatchArgs& b, int dtype, int cpl, int waves,
+                                        size_t lds, hipStream_t s) {
+    switch (dtype * 100 + cpl) {
+        case kF32 * 100 + 1: return bwd_batched_view_launch<TF32, 1>(b, waves, lds, s);
+        case kF32 * 100 + 2: return bwd_batched_view_launch<TF32, 2>(b, waves, lds, s);
+        case kF32 * 100 + 4: return bwd_batched_view_launch<TF32, 4>(b, waves, lds, s);
+        case kBF16 * 100 + 2: return bwd_batched_view_launch<TBF16, 2>(b, waves, lds, s);
+        case kF16 * 100 + 2: return bwd_batched_view_launch<TF16, 2>(b, waves, lds, s);
+        case kBF16 * 100 + 4: return bwd_batched_view_launch<TBF16, 4>(b, waves, lds, s);
+        case kF16 * 100 + 4: return bwd_batched_view_launch<TF16, 4>(b, waves, lds, s);
+        case kBF16 * 100 + 8: return bwd_batched_view_launch<TBF16, 8>(b, waves, lds, s);
+        case kF16 * 100 + 8: return bwd_batched_view_launch<TF16, 8>(b, waves, lds, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_backward_batched(const BatchArgs& b, int dtype, int cpl, int waves, int blocks,

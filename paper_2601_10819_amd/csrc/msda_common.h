@@ -353,9 +353,10 @@ struct AnchorOrder {
 
 struct ViewOrder {
     int N, P, n_lo;
+    int geo_lo = 0;     // first camera of the staged geometry (a wave's own slice)
     __device__ __forceinline__ void operator()(int k, u32* src, u32* cam) const {
         const int q = k / P, p = k - q * P;
-        *cam = (u32)(n_lo + q);
+        *cam = (u32)(n_lo + q - geo_lo);
         *src = (u32)(p * N + n_lo + q);
     }
 };
@@ -568,6 +569,59 @@ __device__ __forceinline__ OpArgs scene_view(const BatchArgs& b, int s, int feat
     a.lps_shift = b.lps_shift;
     a.pairs_per_chunk = b.pairs_per_chunk;
     return a;
+}
+
+// A row of the batched view order: one anchor of one scene over that
+// scene's cameras in XCD slot x, the single call's slot split of the scene
+// with B = 1. nv = 0: the anchor has no cameras in the slot.
+struct BatchRow {
+    int s, a, n_lo, nv;
+};
+
+__device__ __forceinline__ BatchRow batch_row(const BatchArgs& b, int x, u32 g) {
+    BatchRow r;
+    r.s = scene_of(b.t.anchor_start, b.S, g);
+    r.a = (int)(g - b.t.anchor_start[r.s]);
+    const int N = b.scenes[r.s].num_cams, A = b.scenes[r.s].num_anchors;
+    const SlotSpan span = slot_span(x, 1, N, A);
+    r.n_lo = 0;
+    r.nv = 0;
+    if (slot_rows(span, A) > 0) {
+        const ViewRow v = view_row(span, r.a, N, A);
+        r.n_lo = v.n_lo;
+        r.nv = v.nv;
+    }
+    // every field is the same across the wave (g is per wave)
+    r.s = uniform(r.s);
+    r.a = uniform(r.a);
+    r.n_lo = uniform(r.n_lo);
+    r.nv = uniform(r.nv);
+    return r;
+}
+
+// Bytes of one wave's LDS in the batched view order: the geometry of its
+// row's cameras (at most view_cams) and its staging slot.
+__host__ __device__ inline size_t batch_view_wave_bytes(int view_cams, int L, int J, int G) {
+    return (((size_t)view_cams * L * sizeof(Geo) + 15) & ~(size_t)15) +
+           wave_stage_bytes(J, L, G);
+}
+
+// The geometry of cameras [n_lo, n_lo + nv) of `a` into one wave's slice
+// (entry (n - n_lo) * L + l), then readable by the whole wave.
+__device__ __forceinline__ void stage_geometry_range(Geo* geo, const OpArgs& a, int n_lo, int nv,
+                                                     int lane) {
+    for (int i = lane; i < nv * a.L; i += 64) {
+        const int l = i % a.L, r = (n_lo + i / a.L) * a.L + l;
+        Geo g;
+        g.H = a.shapes[2 * r];
+        g.W = a.shapes[2 * r + 1];
+        g.start = a.starts[r];
+        g.scale = a.level_scale ? a.level_scale[l] : 1.f;
+        g.cstart = a.cell_start ? a.cell_start[r] : 0u;
+        g.pad0 = g.pad1 = g.pad2 = 0u;
+        geo[i] = g;
+    }
+    wave_lds_sync();
 }
 
 // Quotient of n < 2^30 by the divisor whose magic is (m, shift): exact

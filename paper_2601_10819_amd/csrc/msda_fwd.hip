@@ -37,6 +37,10 @@ size_t lds_bytes_for(const OpArgs& a, int waves) {
     return geo + (stage > red ? stage : red);
 }
 
+size_t batch_view_lds(int view_cams, int L, int J, int G, int waves) {
+    return (size_t)waves * batch_view_wave_bytes(view_cams, L, J, G);
+}
+
 size_t lds_bytes_view(const OpArgs& a, int waves) {
     return (size_t)a.N * a.L * sizeof(Geo) +
            (size_t)waves * wave_stage_bytes(a.pairs_per_chunk, a.L, a.G);
@@ -213,6 +217,113 @@ __global__ void __launch_bounds__(512) msda_fwd_batched_kernel(BatchArgs b) {
     }
 }
 
+// Batched forward in view order: workgroup w serves XCD slot w % kSlots;
+// each wave takes one global anchor g over its scene's cameras in that slot
+// (the single call's slot split of the scene), stages just those cameras'
+// geometry in its own LDS slice and writes the row's partial sum (zeros for
+// an anchor with no cameras in the slot) to part[slot][g]. Per anchor the
+// arithmetic is the single call's view order.
+template <class FT, int CPL>
+__global__ void __launch_bounds__(512) msda_fwd_batched_view_kernel(BatchArgs b, float* part) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int x = (int)(blockIdx.x % kSlots);
+    const int wave = wave_index(), nwaves = blockDim.x >> 6;
+    const u32 g = (blockIdx.x / kSlots) * (u32)nwaves + (u32)wave;
+    if (g >= b.total_anchors) return;
+    unsigned char* mine =
+        smem + (size_t)wave * batch_view_wave_bytes(b.view_cams, b.L, b.pairs_per_chunk, b.G);
+    Geo* geo = reinterpret_cast<Geo*>(mine);
+    unsigned char* work =
+        mine + (((size_t)b.view_cams * b.L * sizeof(Geo) + 15) & ~(size_t)15);
+    const BatchRow row = batch_row(b, x, g);
+    const OpArgs a = scene_view(b, row.s, FT::kBytes);
+    const Lanes q = lanes_of<FT, CPL>(a);
+    stage_geometry_range(geo, a, row.n_lo, row.nv, q.lane);
+
+    const int LG = a.L * a.G;
+    const int J = a.pairs_per_chunk;
+    const StageSlot st = stage_slot(work, 0, J, a.L, a.G);
+    const int npairs = a.P * a.N;
+    const float* gl = a.loc + (size_t)row.a * npairs * 2;
+    const WSrc gw = anchor_weights(a, (size_t)row.a, (size_t)npairs * LG);
+    const u32 row_bytes = (u32)a.C * FT::kBytes;
+    const rsrc_t feat = make_rsrc(a.feat, a.batch_bytes);
+    const ViewOrder order{a.N, a.P, row.n_lo, row.n_lo};
+    const RecordSink none{};
+
+    float acc[CPL];
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) acc[i] = 0.f;
+    const int nk = row.nv * a.P;
+    for (int k0 = 0; k0 < nk; k0 += J) {
+        const int nj = min(J, nk - k0);
+        stage_chunk<FT::kBytes == 1, false>(st, order, k0, nj, gw, gl, geo, a.L, LG, row_bytes,
+                                            q.lane, none);
+        fwd_chunk<FT, CPL>(st, nj, a.L, a.G, q, feat, acc);
+        end_chunk();
+    }
+    reduce_subwaves<CPL>(q, acc);
+    if (q.sub == 0) {
+        float* dst = part + ((size_t)x * b.total_anchors + g) * b.C + q.c0;
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) dst[i] = acc[i];
+    }
+}
+
+// out of global anchor g = sum over the slots of part[slot][g], in slot
+// order, written to its scene's output; V floats per thread.
+template <int V>
+__global__ void __launch_bounds__(256) fwd_batched_view_reduce(BatchArgs b, const float* part) {
+    const size_t total = (size_t)b.total_anchors * b.C;
+    const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * V;
+    if (i >= total) return;
+    const u32 g = (u32)(i / (size_t)b.C);
+    const int c = (int)(i - (size_t)g * b.C);
+    const int sc = scene_of(b.t.anchor_start, b.S, g);
+    float s[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) s[v] = 0.f;
+    for (int x = 0; x < kSlots; ++x) {
+        const float* p = part + (size_t)x * total + i;
+        if constexpr (V == 4) {
+            const float4 t = *reinterpret_cast<const float4*>(p);
+            s[0] += t.x; s[1] += t.y; s[2] += t.z; s[3] += t.w;
+        } else {
+            s[0] += p[0];
+        }
+    }
+    float* out = b.scenes[sc].out + (size_t)(g - b.t.anchor_start[sc]) * b.C + c;
+    if constexpr (V == 4) {
+        *reinterpret_cast<float4*>(out) = make_float4(s[0], s[1], s[2], s[3]);
+    } else {
+        out[0] = s[0];
+    }
+}
+
+template <class FT, int CPL>
+static hipError_t fwd_batched_view_launch(const BatchArgs& b, int waves, size_t lds, float* part,
+                                          hipStream_t s) {
+    const unsigned blocks =
+        (unsigned)(kSlots * (((size_t)b.total_anchors + waves - 1) / (size_t)waves));
+    mark_begin("msda_fwd_batched_view_kernel", s);
+    hipLaunchKernelGGL((msda_fwd_batched_view_kernel<FT, CPL>), dim3(blocks), dim3(64 * waves),
+                       lds, s, b, part);
+    mark_end(s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t total = (size_t)b.total_anchors * b.C;
+    mark_begin("fwd_batched_view_reduce", s);
+    if (b.C % 4 == 0) {
+        hipLaunchKernelGGL(fwd_batched_view_reduce<4>, dim3((unsigned)((total / 4 + 255) / 256)),
+                           dim3(256), 0, s, b, part);
+    } else {
+        hipLaunchKernelGGL(fwd_batched_view_reduce<1>, dim3((unsigned)((total + 255) / 256)),
+                           dim3(256), 0, s, b, part);
+    }
+    mark_end(s);
+    return hipGetLastError();
+}
+
 template <class FT, int CPL>
 static hipError_t fwd_batched_launch(const BatchArgs& b, int waves, int blocks, size_t lds,
                                      hipStream_t s) {
@@ -277,6 +388,11 @@ static hipError_t fwd_view_launch(const OpArgs& a, int waves, size_t lds, float*
 hipError_t launch_forward_batched(const BatchArgs& b, int dtype, int cpl, int waves, int blocks,
                                   size_t lds, hipStream_t s) {
     MSDA_FOR_EACH_LAYOUT(fwd_batched_launch, b, waves, blocks, lds, s)
+}
+
+hipError_t launch_forward_batched_view(const BatchArgs& b, int dtype, int cpl, int waves,
+                                       size_t lds, float* part, hipStream_t s) {
+    MSDA_FOR_EACH_LAYOUT(fwd_batched_view_launch, b, waves, lds, part, s)
 }
 
 hipError_t launch_forward(const OpArgs& a, int dtype, int cpl, int waves, size_t lds,

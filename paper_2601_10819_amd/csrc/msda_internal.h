@@ -103,6 +103,7 @@ struct BatchArgs {
     int32_t lps_shift;            // log2(C / chans_per_lane)
     int32_t pairs_per_chunk;
     int32_t max_regions_per_scene;   // LDS sizing of the geometry table
+    int32_t view_cams;            // view order: cameras of a row at most (geometry slice)
     uint32_t* rec_key;            // backward, grad_feat records (or nullptr)
     float2* rec_frac;
     // tiled reduction
@@ -269,6 +270,15 @@ hipError_t launch_forward_batched(const BatchArgs& b, int dtype, int cpl, int wa
                                   size_t lds_bytes, hipStream_t s);
 hipError_t launch_backward_batched(const BatchArgs& b, int dtype, int cpl, int waves, int blocks,
                                    size_t lds_bytes, hipStream_t s);
+// Batched gathers in view order: one wave per (XCD slot, global anchor)
+// row; grid kSlots * ceil(total_anchors / waves); LDS waves *
+// batch_view_wave_bytes. The forward's per-slot partials go to part
+// ([kSlots][total_anchors][C] FP32) and are added into each scene's out.
+size_t batch_view_lds(int view_cams, int L, int J, int G, int waves);
+hipError_t launch_forward_batched_view(const BatchArgs& b, int dtype, int cpl, int waves,
+                                       size_t lds, float* part, hipStream_t s);
+hipError_t launch_backward_batched_view(const BatchArgs& b, int dtype, int cpl, int waves,
+                                        size_t lds, hipStream_t s);
 hipError_t launch_gfeat_tiles_batched(const BatchArgs& b, int out_dtype, int cpl, hipStream_t s);
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);

@@ -265,11 +265,19 @@ def test_batched_validation(lib):
     t = _lib.MsdaTile(0, 0, 0, _lib.MSDA_SCATTER_ATOMIC)
     b.tile = ctypes.pointer(t)
     expect(lib, lib.msda_backward_batched(ctypes.byref(b), FAKE, 1 << 30, None), UNS, "sorted")
-    # the batched form runs in anchor order
+    # an order the batched form does not know
     b = batch_desc(geos, [4, 7])
-    t = _lib.MsdaTile(0, 0, _lib.MSDA_ORDER_VIEW, 0)
+    t = _lib.MsdaTile(0, 0, 7, 0)
     b.tile = ctypes.pointer(t)
-    expect(lib, lib.msda_forward_batched(ctypes.byref(b), FAKE, 1 << 30, None), UNS, "anchor order")
+    expect(lib, lib.msda_forward_batched(ctypes.byref(b), FAKE, 1 << 30, None), UNS, "unknown order")
+    # the forward's workspace holds the view order's per-slot partial sums
+    # (8 x anchors x C FP32) in either order
+    b = batch_desc(geos, [4, 7])
+    va = lib.msda_batched_workspace_size(ctypes.byref(b), 0)
+    t = _lib.MsdaTile(0, 0, _lib.MSDA_ORDER_ANCHOR, 0)
+    b.tile = ctypes.pointer(t)
+    assert lib.msda_batched_workspace_size(ctypes.byref(b), 0) == va
+    assert va >= 8 * 11 * b.channels * 4
 
 
 def fwd_ws(lib, d, ws=None, ws_bytes=0):
