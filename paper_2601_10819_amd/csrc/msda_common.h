@@ -273,6 +273,23 @@ __device__ __forceinline__ float group_sum(float v, int width) {
     return v;
 }
 
+// group_sum with the width known at compile time (no branches); W = 0:
+// the width given at run time.
+template <int W>
+__device__ __forceinline__ float group_sum_w(float v, int width) {
+    if constexpr (W == 0) {
+        return group_sum(v, width);
+    } else {
+        if constexpr (W > 1) v += dpp<0xB1>(v);
+        if constexpr (W > 2) v += dpp<0x4E>(v);
+        if constexpr (W > 4) v += dpp<0x141>(v);
+        if constexpr (W > 8) v += dpp<0x140>(v);
+        if constexpr (W > 16) v = swap16_sum(v);
+        if constexpr (W > 32) v = swap32_sum(v);
+        return v;
+    }
+}
+
 // v + v[lane ^ mask] for a power-of-two mask (the same in every lane).
 __device__ __forceinline__ float xor_sum(float v, int mask) {
     if (mask == 32) return swap32_sum(v);

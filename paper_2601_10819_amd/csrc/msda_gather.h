@@ -107,11 +107,10 @@ __device__ __forceinline__ BwdAnchor bwd_anchor_ctx(const OpArgs& a, int ba, con
 // group's first lane, sum of w * (sum over the group's channels of grad_out
 // * value) -- <grad_out, the anchor's feature in this view> -- for the
 // fused form's score gradient.
-template <class FT, int CPL>
-__device__ __forceinline__ void bwd_chunk(const OpArgs& a, const StageSlot& st, int nj,
-                                          const Geo* geo, const Lanes& q, const BwdAnchor& x,
-                                          const float* go, float out_scale = 1.f,
-                                          float* dot = nullptr) {
+template <class FT, int CPL, int LPG, int LPS>
+__device__ __forceinline__ void bwd_chunk_w(const OpArgs& a, const StageSlot& st, int nj,
+                                            const Geo* geo, const Lanes& q, const BwdAnchor& x,
+                                            const float* go, float out_scale, float* dot) {
     using RowT = Row<FT, CPL>;
     const int L = a.L, G = a.G, LG = L * G;
     const int lpg = (a.C / a.G) / CPL;             // lanes of one group (a power of two)
@@ -156,7 +155,7 @@ __device__ __forceinline__ void bwd_chunk(const OpArgs& a, const StageSlot& st, 
             }
             if (x.gwout || dot) {
                 float tw = t.cw[0] * d[0] + t.cw[1] * d[1] + t.cw[2] * d[2] + t.cw[3] * d[3];
-                tw = group_sum(tw, lpg);
+                tw = group_sum_w<LPG>(tw, lpg);
                 if ((q.lane & (lpg - 1)) == 0) {
                     if (x.gwout) x.gwout[(size_t)src * LG + l * G + q.g] = tw * out_scale;
                     if (dot) *dot = fmaf(wl, tw, *dot);
@@ -170,14 +169,32 @@ __device__ __forceinline__ void bwd_chunk(const OpArgs& a, const StageSlot& st, 
             gy += (float)gm.H * wl * (hx * (d[2] - d[0]) + fr.x * (d[3] - d[1]));
         }
         if (x.glout) {
-            gx = group_sum(gx, q.lps);
-            gy = group_sum(gy, q.lps);
+            gx = group_sum_w<LPS>(gx, q.lps);
+            gy = group_sum_w<LPS>(gy, q.lps);
             if ((q.lane & (q.lps - 1)) == 0) {
                 x.glout[(size_t)src * 2] = gx * out_scale;
                 x.glout[(size_t)src * 2 + 1] = gy * out_scale;
             }
         }
     }
+}
+
+// The lane widths of the common layouts (C = 256 in G = 8 groups: 32 lanes
+// per sample in groups of 4 with 8 channels per lane, 64 in groups of 8
+// with 4) are compile-time in their copies of the loop; others take the
+// run-time widths.
+template <class FT, int CPL>
+__device__ __forceinline__ void bwd_chunk(const OpArgs& a, const StageSlot& st, int nj,
+                                          const Geo* geo, const Lanes& q, const BwdAnchor& x,
+                                          const float* go, float out_scale = 1.f,
+                                          float* dot = nullptr) {
+    const int lpg = (a.C / a.G) / CPL;
+    if (lpg == 4 && q.lps == 32)
+        bwd_chunk_w<FT, CPL, 4, 32>(a, st, nj, geo, q, x, go, out_scale, dot);
+    else if (lpg == 8 && q.lps == 64)
+        bwd_chunk_w<FT, CPL, 8, 64>(a, st, nj, geo, q, x, go, out_scale, dot);
+    else
+        bwd_chunk_w<FT, CPL, 0, 0>(a, st, nj, geo, q, x, go, out_scale, dot);
 }
 
 }  // namespace msda
