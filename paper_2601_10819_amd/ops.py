@@ -474,6 +474,14 @@ class SceneBatch:
             if feat.dtype != self.dtype or feat.shape[1] != self.C:
                 raise ValueError(f"scene {s}: feat dtype / channels differ from scene 0")
             A = loc.shape[0]
+            # keypoints, levels and groups are shared by the batch (the kernels
+            # read every scene's locations and weights with scene 0's sizes)
+            if loc.shape != (A, self.P, layout.num_cams, 2):
+                raise ValueError(f"scene {s}: sampling_loc {tuple(loc.shape)} is not "
+                                 f"[A, P={self.P}, Ncam={layout.num_cams}, 2]")
+            if w.shape != (A, self.P, layout.num_cams, self.L, self.G):
+                raise ValueError(f"scene {s}: weights {tuple(w.shape)} is not "
+                                 f"[A, P={self.P}, Ncam={layout.num_cams}, L={self.L}, G={self.G}]")
             out = torch.empty(A, self.C, device=self.device, dtype=torch.float32)
             go = torch.zeros(A, self.C, device=self.device, dtype=torch.float32)
             gf = torch.empty_like(feat) if need_feat else None

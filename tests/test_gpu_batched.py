@@ -183,3 +183,43 @@ def test_batched_single_scene_and_validation(ops):
     # mixed gradient requests are rejected
     with pytest.raises(ValueError):
         ops.SceneBatch(scenes + [(feat.to(torch.bfloat16), layout, loc, w)])
+
+
+def test_batched_view_order_tiny_scenes(ops):
+    """Scenes with fewer (camera, anchor) items than XCD slots leave slots
+    empty (their rows add zeros): the view-order batch still equals the
+    single calls in view order on every scene, bit for bit."""
+    probs = [synth.small(seed=60, cams=1, A=3, P=3, C=64, G=4),
+             synth.small(seed=61, cams=2, A=1, P=3, C=64, G=4),
+             synth.small(seed=62, cams=5, A=9, P=3, C=64, G=4),
+             synth.small(seed=63, cams=13, A=2, P=3, C=64, G=4)]
+    print("case", [p.dims() for p in probs], flush=True)
+    scenes = to_scenes(ops, probs, torch.float32)
+    batch = ops.SceneBatch(scenes, tile=VIEW_TILE)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    for go in batch.grad_out:
+        go.normal_(generator=gen)
+    batch.forward()
+    batch.backward()
+    torch.cuda.synchronize()
+    for s, (feat, layout, loc, w) in enumerate(scenes):
+        out = ops.forward(feat[None], layout, loc[None], w[None], tile=VIEW_TILE)
+        gf, gl, gw = ops.backward(feat[None], layout, loc[None], w[None], batch.grad_out[s][None],
+                                  tile=VIEW_TILE)
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], batch.out[s]), f"scene {s} out"
+        assert torch.equal(gf[0], batch.grad_feat[s]), f"scene {s} grad_feat"
+        assert torch.equal(gl[0], batch.grad_loc[s]), f"scene {s} grad_loc"
+        assert torch.equal(gw[0], batch.grad_w[s]), f"scene {s} grad_w"
+
+
+
+def test_batched_rejects_uneven_shared_sizes(ops):
+    """Keypoints, levels, channels and groups are shared by a batch: a scene
+    that differs is rejected before anything runs."""
+    base = small_batch(seed=3, scenes=2, empty_scene=False)
+    odd = synth.small(seed=64, cams=3, A=4, P=base[0].num_points + 1, C=base[0].channels,
+                      G=base[0].groups, levels=((6, 10), (3, 5), (2, 3), (1, 2)))
+    scenes = to_scenes(ops, base + [odd], torch.float32)
+    with pytest.raises(ValueError, match="sampling_loc"):
+        ops.SceneBatch(scenes)
