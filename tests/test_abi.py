@@ -389,3 +389,42 @@ def test_visible_form_validation(lib):
     d0 = desc(Geo(), B=2, A=0, C=32)
     assert lib.msda_forward_visible(FAKE, FAKE, FAKE, None, None, None, None, None, 0,
                                     ctypes.byref(d0), None) == _lib.MSDA_OK
+
+
+def test_fused_form_validation(lib):
+    d = desc(Geo(), B=2, A=4, C=32)
+    assert (lib.msda_forward_fused_workspace_size(ctypes.byref(d)) ==
+            lib.msda_forward_visible_workspace_size(ctypes.byref(d)))
+    assert (lib.msda_backward_fused_workspace_size(ctypes.byref(d)) ==
+            lib.msda_backward_visible_workspace_size(ctypes.byref(d)))
+    ws, n = FAKE + (1 << 20), 1 << 30
+    # the forward needs the scores
+    expect(lib, lib.msda_forward_fused(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE + 4096, ws,
+                                       n, ctypes.byref(d), None), INV, "NULL")
+    # the backward's score gradient needs the forward's output
+    bwdf = lambda score, out, gs: lib.msda_backward_fused(
+        FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, score, out, FAKE, FAKE + 8192, FAKE, FAKE, gs, ws, n,
+        ctypes.byref(d), None)
+    expect(lib, bwdf(None, FAKE, FAKE), INV, "view_score")
+    expect(lib, bwdf(FAKE, None, FAKE), INV, "out")
+
+
+def test_weight_flag_validation(lib):
+    # an unknown flag bit
+    expect(lib, fwd(lib, desc(Geo(), flags=64)), INV, "flags")
+    # logits need the workspace for their softmax statistics
+    d = desc(Geo(ncam=4), A=4, C=32, flags=_lib.MSDA_WEIGHT_LOGITS)
+    expect(lib, fwd(lib, d), WS, "msda_forward_ws")
+    plain = desc(Geo(ncam=4), A=4, C=32)
+    assert (lib.msda_forward_workspace_size(ctypes.byref(d)) >
+            lib.msda_forward_workspace_size(ctypes.byref(plain)))
+    # the backward works on FP32 weights written once: 4 * G per sample more
+    nsamp = 1 * 4 * 3 * 4 * 2
+    for flags in (_lib.MSDA_WEIGHT_LOGITS, _lib.MSDA_WEIGHTS_BF16):
+        df = desc(Geo(ncam=4), A=4, C=32, flags=flags)
+        assert (lib.msda_backward_workspace_size(ctypes.byref(df)) >=
+                lib.msda_backward_workspace_size(ctypes.byref(plain)) + 4 * 4 * nsamp)
+    # the visible-view forms take no weight flags
+    vis = lambda f: lib.msda_forward_visible(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE + 4096,
+                                             FAKE + (1 << 20), 1 << 30, ctypes.byref(f), None)
+    expect(lib, vis(desc(Geo(), A=4, C=32, flags=_lib.MSDA_WEIGHTS_BF16)), UNS, "weight flags")
