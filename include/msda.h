@@ -85,8 +85,10 @@ typedef enum msda_dtype {
 /* `weights` (or the logits) are stored as bfloat16: the pointer holds
  * uint16 bit patterns in the same layout; grad_weights stays FP32. */
 #define MSDA_WEIGHTS_BF16 4u
-/* The visible-view, fused and batched entry points take neither of the two
- * weight flags (UNSUPPORTED). */
+/* The visible-view and fused forms take both flags (their workspaces grow
+ * accordingly; with logits, the softmax runs over every camera's entries,
+ * visible or not, and the logits' gradient reaches invisible entries through
+ * its normalisation); the batched form takes neither (UNSUPPORTED). */
 
 /* msda_tile.scatter: how the backward forms grad_feat */
 #define MSDA_SCATTER_AUTO 0   /* the library's choice (currently SORTED)                */

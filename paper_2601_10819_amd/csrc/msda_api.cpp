@@ -573,14 +573,13 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
         if (rcpl == 4 && !aligned(grad_out, 16))
             return fail(MSDA_ERR_UNSUPPORTED, "grad_out must be 16-byte aligned");
     }
-    if (visible && (desc->flags & kWeightFlags))
-        return fail(MSDA_ERR_UNSUPPORTED, "the visible-view forms take no weight flags");
     const size_t sorted_need = grad_feat ? base_backward_bytes(desc) : 0;
     const VisibleWs VW = visible_layout(desc, align256(sorted_need));
     // weight flags: softmax statistics and FP32 weights after the rest
-    const size_t wx_off = align256(sorted_need);
+    const size_t base_need = visible && a.A > 0 ? VW.total : sorted_need;
+    const size_t wx_off = align256(base_need);
     const size_t wx_bytes = a.A > 0 ? stats_bytes(desc) + weights_f32_bytes(desc) : 0;
-    const size_t need = visible && a.A > 0 ? VW.total : (wx_bytes ? wx_off + wx_bytes : sorted_need);
+    const size_t need = wx_bytes ? wx_off + wx_bytes : base_need;
     if (need) {
         if (!workspace || workspace_bytes < need)
             return fail(MSDA_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
@@ -821,7 +820,9 @@ size_t msda_backward_fused_workspace_size(const msda_desc* d) {
 
 size_t msda_backward_visible_workspace_size(const msda_desc* d) {
     if (!d || d->batch < 1 || d->rows < 1 || d->channels < 1 || d->num_anchors < 0) return 0;
-    return visible_layout(d, align256(msda_backward_workspace_size(d))).total;
+    const size_t base = visible_layout(d, align256(base_backward_bytes(d))).total;
+    const size_t extra = stats_bytes(d) + weights_f32_bytes(d);
+    return extra ? align256(base) + extra : base;
 }
 
 // The visible-view forward's workspace: the compaction, then one partial
@@ -836,7 +837,7 @@ static size_t forward_visible_part(const msda_desc* d, size_t* part_off) {
 size_t msda_forward_visible_workspace_size(const msda_desc* d) {
     if (!d || d->batch < 1 || d->num_cams < 1 || d->channels < 1 || d->num_anchors < 0) return 0;
     size_t part_off;
-    return forward_visible_part(d, &part_off);
+    return align256(forward_visible_part(d, &part_off)) + stats_bytes(d);
 }
 
 static msda_status forward_visible_impl(const void* feat, const int32_t* spatial_shapes,
@@ -848,8 +849,6 @@ static msda_status forward_visible_impl(const void* feat, const int32_t* spatial
     if (!desc) return fail(MSDA_ERR_INVALID_ARGUMENT, "desc is NULL");
     if (desc->tile && desc->tile->order == MSDA_ORDER_ANCHOR)
         return fail(MSDA_ERR_UNSUPPORTED, "the visible-view form runs in view order only");
-    if (desc->flags & kWeightFlags)
-        return fail(MSDA_ERR_UNSUPPORTED, "the visible-view forms take no weight flags");
     msda::OpArgs a = {};
     int cpl = 0, waves = 0;
     msda_status st = prepare(desc, MSDA_ORDER_VIEW, &a, &cpl, &waves);
@@ -861,7 +860,8 @@ static msda_status forward_visible_impl(const void* feat, const int32_t* spatial
     if ((uint64_t)a.B * a.N * (uint64_t)a.A >= (1ull << 31))
         return fail(MSDA_ERR_UNSUPPORTED, "B * Ncam * A must be < 2^31");
     size_t part_off = 0;
-    const size_t need = forward_visible_part(desc, &part_off);
+    const size_t stats_off = align256(forward_visible_part(desc, &part_off));
+    const size_t need = stats_off + stats_bytes(desc);
     if (a.A == 0) return ok();
     if (!workspace || workspace_bytes < need || !aligned(workspace, 256))
         return fail(MSDA_ERR_WORKSPACE, "forward workspace: need %zu bytes, 256-byte aligned "
@@ -880,6 +880,16 @@ static msda_status forward_visible_impl(const void* feat, const int32_t* spatial
     const size_t V = (size_t)a.B * a.N * a.A;
     const hipStream_t s = (hipStream_t)stream;
     float* vt = fused ? reinterpret_cast<float*>(ws + vw.vt) : nullptr;
+    const bool wbf16 = desc->flags & MSDA_WEIGHTS_BF16;
+    a.w_bf16 = wbf16;
+    if (desc->flags & MSDA_WEIGHT_LOGITS) {
+        float2* stats = reinterpret_cast<float2*>(ws + stats_off);
+        float2* spart = reinterpret_cast<float2*>(ws + stats_off + stats_only_bytes(desc));
+        const hipError_t es = msda::launch_softmax_stats(weights, wbf16, a.B * a.A,
+                                                         a.P * a.N * a.L, a.G, spart, stats, s);
+        if (es != hipSuccess) return hip_fail(es, "softmax statistics");
+        a.wstats = stats;
+    }
     hipError_t e = msda::launch_visible_items(visible, a.B, a.N, a.A, 0u, place, items, nullptr,
                                               reinterpret_cast<uint32_t*>(ws + vw.partial), s);
     if (e == hipSuccess && fused) e = msda::launch_view_scale(visible, score, a.B * a.A, a.N, vt, s);

@@ -259,14 +259,16 @@ def _need_visible(visible, sampling_loc):
 
 def forward_visible(feat, layout: Layout, sampling_loc, weights, visible, level_scale=None,
                     tile=None, out: Optional[torch.Tensor] = None,
-                    workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """out [B, A, C] = MSDA over the visible (anchor, camera) pairs only."""
+                    workspace: Optional[torch.Tensor] = None, stream=None,
+                    logits: bool = False) -> torch.Tensor:
+    """out [B, A, C] = MSDA over the visible (anchor, camera) pairs only
+    (weights FP32 or BF16; logits: per-group softmax logits)."""
     lib = _lib.load()
     _need_cuda_contig("feat", feat)
     _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
-    _need_cuda_contig("weights", weights, torch.float32)
+    _need_weights(weights)
     _need_visible(visible, sampling_loc)
-    d = make_desc(feat, layout, sampling_loc, weights, level_scale, tile=tile)
+    d = make_desc(feat, layout, sampling_loc, weights, level_scale, tile=tile, logits=logits)
     if out is None:
         out = torch.empty(d.batch, d.num_anchors, d.channels, device=feat.device,
                           dtype=torch.float32)
@@ -281,19 +283,22 @@ def forward_visible(feat, layout: Layout, sampling_loc, weights, visible, level_
 
 def backward_visible(feat, layout: Layout, sampling_loc, weights, visible, grad_out,
                      need_feat=True, need_loc=True, need_w=True, tile=None,
-                     workspace: Optional[torch.Tensor] = None, stream=None):
+                     workspace: Optional[torch.Tensor] = None, stream=None,
+                     logits: bool = False):
     """(grad_feat, grad_sampling_loc, grad_weights) of the visible-view form;
-    the gradients of invisible pairs are zero."""
+    the gradients of invisible pairs are zero (with logits, grad_weights is
+    the logits' gradient, which reaches invisible entries through the
+    softmax's normalisation)."""
     lib = _lib.load()
     _need_cuda_contig("feat", feat)
     _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
-    _need_cuda_contig("weights", weights, torch.float32)
+    _need_weights(weights)
     _need_cuda_contig("grad_out", grad_out, torch.float32)
     _need_visible(visible, sampling_loc)
-    d = make_desc(feat, layout, sampling_loc, weights, tile=tile)
+    d = make_desc(feat, layout, sampling_loc, weights, tile=tile, logits=logits)
     gf = torch.empty_like(feat) if need_feat else None
     gl = torch.empty_like(sampling_loc) if need_loc else None
-    gw = torch.empty_like(weights) if need_w else None
+    gw = torch.empty(weights.shape, dtype=torch.float32, device=weights.device) if need_w else None
     ws_ptr, ws_len, workspace = _workspace(
         int(lib.msda_backward_visible_workspace_size(ctypes.byref(d))), workspace, feat.device)
     _lib.check(lib.msda_backward_visible(_ptr(feat), _ptr(layout.shapes), _ptr(layout.starts),
@@ -312,16 +317,17 @@ def _need_scores(view_score, visible):
 
 def forward_fused(feat, layout: Layout, sampling_loc, weights, visible, view_score,
                   level_scale=None, tile=None, out: Optional[torch.Tensor] = None,
-                  workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+                  workspace: Optional[torch.Tensor] = None, stream=None,
+                  logits: bool = False) -> torch.Tensor:
     """out [B, A, C]: the visible views' features weighted by view_score over
     the visible cameras' score sum (visibility-weighted fusion, Eq. 2)."""
     lib = _lib.load()
     _need_cuda_contig("feat", feat)
     _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
-    _need_cuda_contig("weights", weights, torch.float32)
+    _need_weights(weights)
     _need_visible(visible, sampling_loc)
     _need_scores(view_score, visible)
-    d = make_desc(feat, layout, sampling_loc, weights, level_scale, tile=tile)
+    d = make_desc(feat, layout, sampling_loc, weights, level_scale, tile=tile, logits=logits)
     if out is None:
         out = torch.empty(d.batch, d.num_anchors, d.channels, device=feat.device,
                           dtype=torch.float32)
@@ -336,13 +342,14 @@ def forward_fused(feat, layout: Layout, sampling_loc, weights, visible, view_sco
 
 def backward_fused(feat, layout: Layout, sampling_loc, weights, visible, view_score, out,
                    grad_out, need_feat=True, need_loc=True, need_w=True, need_score=True,
-                   tile=None, workspace: Optional[torch.Tensor] = None, stream=None):
+                   tile=None, workspace: Optional[torch.Tensor] = None, stream=None,
+                   logits: bool = False):
     """(grad_feat, grad_sampling_loc, grad_weights, grad_score) of
     forward_fused; out is forward_fused's result (needed for grad_score)."""
     lib = _lib.load()
     _need_cuda_contig("feat", feat)
     _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
-    _need_cuda_contig("weights", weights, torch.float32)
+    _need_weights(weights)
     _need_cuda_contig("grad_out", grad_out, torch.float32)
     _need_visible(visible, sampling_loc)
     _need_scores(view_score, visible)
@@ -351,10 +358,10 @@ def backward_fused(feat, layout: Layout, sampling_loc, weights, visible, view_sc
         if out.shape != grad_out.shape:
             raise ValueError(f"out must match grad_out {tuple(grad_out.shape)}, "
                              f"got {tuple(out.shape)}")
-    d = make_desc(feat, layout, sampling_loc, weights, tile=tile)
+    d = make_desc(feat, layout, sampling_loc, weights, tile=tile, logits=logits)
     gf = torch.empty_like(feat) if need_feat else None
     gl = torch.empty_like(sampling_loc) if need_loc else None
-    gw = torch.empty_like(weights) if need_w else None
+    gw = torch.empty(weights.shape, dtype=torch.float32, device=weights.device) if need_w else None
     gs = torch.empty_like(view_score) if need_score else None
     ws_ptr, ws_len, workspace = _workspace(
         int(lib.msda_backward_fused_workspace_size(ctypes.byref(d))), workspace, feat.device)

@@ -265,6 +265,10 @@ def test_batched_validation(lib):
     t = _lib.MsdaTile(0, 0, 0, _lib.MSDA_SCATTER_ATOMIC)
     b.tile = ctypes.pointer(t)
     expect(lib, lib.msda_backward_batched(ctypes.byref(b), FAKE, 1 << 30, None), UNS, "sorted")
+    # the batched form takes no weight flags
+    b = batch_desc(geos, [4, 7])
+    b.flags = _lib.MSDA_WEIGHT_LOGITS
+    expect(lib, lib.msda_forward_batched(ctypes.byref(b), FAKE, 1 << 30, None), UNS, "weight flags")
     # an order the batched form does not know
     b = batch_desc(geos, [4, 7])
     t = _lib.MsdaTile(0, 0, 7, 0)
@@ -424,7 +428,10 @@ def test_weight_flag_validation(lib):
         df = desc(Geo(ncam=4), A=4, C=32, flags=flags)
         assert (lib.msda_backward_workspace_size(ctypes.byref(df)) >=
                 lib.msda_backward_workspace_size(ctypes.byref(plain)) + 4 * 4 * nsamp)
-    # the visible-view forms take no weight flags
-    vis = lambda f: lib.msda_forward_visible(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE + 4096,
-                                             FAKE + (1 << 20), 1 << 30, ctypes.byref(f), None)
-    expect(lib, vis(desc(Geo(), A=4, C=32, flags=_lib.MSDA_WEIGHTS_BF16)), UNS, "weight flags")
+    # the visible-view forms keep the softmax statistics in their workspaces
+    dv = desc(Geo(), B=2, A=4, C=32, flags=_lib.MSDA_WEIGHT_LOGITS)
+    pv = desc(Geo(), B=2, A=4, C=32)
+    assert (lib.msda_forward_visible_workspace_size(ctypes.byref(dv)) >
+            lib.msda_forward_visible_workspace_size(ctypes.byref(pv)))
+    assert (lib.msda_backward_fused_workspace_size(ctypes.byref(dv)) >
+            lib.msda_backward_fused_workspace_size(ctypes.byref(pv)))

@@ -134,15 +134,20 @@ def test_argument_checks(ops):
     st = lib.msda_forward(ops._ptr(feat), ops._ptr(layout.shapes), ops._ptr(layout.starts),
                           ops._ptr(loc), ops._ptr(w), ops._ptr(out), ctypes.byref(d), None)
     assert st == 1, lib.msda_last_error()
-    # the visible-view forms take no weight flags
+    # the visible-view forms keep the softmax statistics in their workspace:
+    # the plain form's size is too small
     v = torch.ones(1, 6, 4, dtype=torch.uint8, device="cuda")
+    plain = ops.make_desc(feat, layout, loc, w)
+    small = int(lib.msda_forward_visible_workspace_size(ctypes.byref(plain)))
     d = ops.make_desc(feat, layout, loc, w, logits=True)
-    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    assert int(lib.msda_forward_visible_workspace_size(ctypes.byref(d))) > small
+    ws = torch.empty(small + 256, dtype=torch.uint8, device="cuda")
+    base = (ws.data_ptr() + 255) // 256 * 256
     st = lib.msda_forward_visible(ops._ptr(feat), ops._ptr(layout.shapes),
                                   ops._ptr(layout.starts), ops._ptr(loc), ops._ptr(w),
-                                  ops._ptr(v), ops._ptr(out), ops._ptr(ws), ws.numel(),
+                                  ops._ptr(v), ops._ptr(out), ctypes.c_void_p(base), small,
                                   ctypes.byref(d), None)
-    assert st == 2, lib.msda_last_error()
+    assert st == 4, lib.msda_last_error()
     torch.cuda.synchronize()
 
 
@@ -171,3 +176,45 @@ def test_logits_64cam_sampled(ops, ow):
     # every group of the logits' gradient sums to zero
     s = gx.double().sum(dim=(2, 3, 4))
     assert float(s.abs().max()) <= 1e-5 * float(gx.double().abs().sum(dim=(2, 3, 4)).max())
+
+
+@pytest.mark.parametrize("wdt", [torch.float32, torch.bfloat16], ids=["f32", "bf16"])
+def test_visible_and_fused_forms_with_logits(ops, ow, wdt):
+    """The visible-view and the fused (Eq. 2) forms with weights generated
+    from logits: the oracle is the softmax composed with those forms'
+    oracles, the logits' gradient its Jacobian applied to theirs (nonzero
+    for invisible entries through the normalisation)."""
+    from oracle import projection as proj
+    p = synth.small(seed=470, B=2, cams=7, levels=((11, 13), (6, 7), (3, 3)), C=64, G=4, A=37,
+                    P=5)
+    feat, layout, loc, _ = to_device(p)
+    rng = np.random.default_rng(47)
+    vis = rng.random((2, 37, 7)) < 0.35
+    score = torch.from_numpy(rng.uniform(0.05, 1.0, (2, 37, 7)).astype(np.float32))
+    x = logits_for(p, 48).to(wdt)
+    go = synth.grad_out_like(p, seed=49)
+    v = torch.from_numpy(vis.astype(np.uint8)).cuda()
+    xd, s = x.cuda(), score.cuda()
+    out_v = ops.forward_visible(feat, layout, loc, xd, v, logits=True)
+    gf_v, gl_v, gx_v = ops.backward_visible(feat, layout, loc, xd, v, go.cuda(), logits=True)
+    out_f = ops.forward_fused(feat, layout, loc, xd, v, s, logits=True)
+    gf_f, gl_f, gx_f, gs_f = ops.backward_fused(feat, layout, loc, xd, v, s, out_f, go.cuda(),
+                                                logits=True)
+    torch.cuda.synchronize()
+    w64 = ow.softmax_weights(x.double())
+    geo = (p.feat, p.spatial_shapes, p.level_start_index, p.sampling_loc)
+    ref = proj.forward_visible(*geo, w64, vis)
+    assert_close(host(out_v), ref, FWD_F32_TOL, FWD_F32_MAXREL, "visible out")
+    rgf, rgl, rgw = proj.backward_visible(*geo, w64, vis, go.numpy())
+    assert_close(host(gf_v), rgf, GRAD_F32_TOL, GRAD_F32_MAXREL, "visible grad_feat")
+    assert_close(host(gl_v), rgl, GRAD_F32_TOL, GRAD_F32_MAXREL, "visible grad_loc")
+    assert_close(host(gx_v), ow.softmax_grad(w64, rgw), GRAD_F32_TOL, GRAD_F32_MAXREL,
+                 "visible grad_logits")
+    ref, _ = proj.forward_fused(*geo, w64, vis, score)
+    assert_close(host(out_f), ref, FWD_F32_TOL, FWD_F32_MAXREL, "fused out")
+    rgf, rgl, rgw, rgs = proj.backward_fused(*geo, w64, vis, score, go.numpy())
+    assert_close(host(gf_f), rgf, GRAD_F32_TOL, GRAD_F32_MAXREL, "fused grad_feat")
+    assert_close(host(gl_f), rgl, GRAD_F32_TOL, GRAD_F32_MAXREL, "fused grad_loc")
+    assert_close(host(gx_f), ow.softmax_grad(w64, rgw), GRAD_F32_TOL, GRAD_F32_MAXREL,
+                 "fused grad_logits")
+    assert_close(host(gs_f), rgs, GRAD_F32_TOL, GRAD_F32_MAXREL, "fused grad_score")
