@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define MSDA_ABI_VERSION 4
+#define MSDA_ABI_VERSION 5
 
 typedef enum msda_status {
     MSDA_OK = 0,
@@ -376,6 +376,23 @@ msda_status msda_forward_batched(const msda_batch* batch, void* workspace,
  */
 msda_status msda_backward_batched(const msda_batch* batch, void* workspace,
                                   size_t workspace_bytes, void* stream);
+
+/*
+ * The grouping step of the deterministic grad_feat reduction on its own (the
+ * backward's scatter to the features, Sec. 3.3, done by sorting the samples'
+ * records by bilinear cell): a stable sort of n uint32 keys in [0, max_key].
+ * keys [n] device, read only; order [n] device, written: order[i] is the
+ * index of the i-th smallest key, equal keys in index order; seg
+ * [max_key + 1] device, written: seg[r] is the first position of the sorted
+ * keys whose key is >= r (n if none). A key above max_key is not detected:
+ * only its low bits are used, so its place is unspecified (no access leaves
+ * the buffers). workspace: device, 256-byte aligned, >=
+ * msda_sort_workspace_size(n, max_key) bytes, contents not kept. n == 0
+ * writes seg only. Asynchronous on `stream`.
+ */
+msda_status msda_sort_keys(const uint32_t* keys, uint32_t n, uint32_t max_key, uint32_t* order,
+                           uint32_t* seg, void* workspace, size_t workspace_bytes, void* stream);
+size_t msda_sort_workspace_size(uint32_t n, uint32_t max_key);
 
 /*
  * Streaming copy of `bytes` (multiple of 16) from src to dst, both device and

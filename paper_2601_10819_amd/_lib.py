@@ -28,7 +28,7 @@ MSDA_DETERMINISTIC = 1
 MSDA_WEIGHT_LOGITS = 2
 MSDA_WEIGHTS_BF16 = 4
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 # Every symbol include/msda.h declares.
 EXPORTS = (
@@ -39,7 +39,7 @@ EXPORTS = (
     "msda_forward_fused_workspace_size", "msda_backward_fused",
     "msda_backward_fused_workspace_size", "msda_quantize_fp8",
     "msda_quantize_workspace_size", "msda_batched_workspace_size", "msda_forward_batched",
-    "msda_backward_batched", "msda_stream_copy", "msda_set_kernel_events",
+    "msda_backward_batched", "msda_sort_keys", "msda_sort_workspace_size", "msda_stream_copy", "msda_set_kernel_events",
     "msda_recorded_kernels", "msda_recorded_kernel_name", "msda_last_error", "msda_abi_version",
 )
 
@@ -159,6 +159,11 @@ def load(path: str = LIB_PATH):
     lib.msda_forward_batched.restype = ctypes.c_int
     lib.msda_backward_batched.argtypes = [bp, vp, sz, vp]
     lib.msda_backward_batched.restype = ctypes.c_int
+    u32 = ctypes.c_uint32
+    lib.msda_sort_keys.argtypes = [vp, u32, u32, vp, vp, vp, sz, vp]
+    lib.msda_sort_keys.restype = ctypes.c_int
+    lib.msda_sort_workspace_size.argtypes = [u32, u32]
+    lib.msda_sort_workspace_size.restype = sz
     lib.msda_stream_copy.argtypes = [vp, vp, sz, vp]
     lib.msda_stream_copy.restype = ctypes.c_int
     lib.msda_set_kernel_events.argtypes = [vp, ctypes.c_int32]

@@ -336,12 +336,13 @@ namespace msda {
 void mark_begin(const char* kernel, hipStream_t s) {
     if (!g_events || g_event_used >= g_event_cap) return;
     g_event_names[g_event_used] = kernel;
-    hipEventRecord(static_cast<hipEvent_t>(g_events[2 * g_event_used]), s);
+    // instrumentation only: a failed record shows as a missing duration
+    (void)hipEventRecord(static_cast<hipEvent_t>(g_events[2 * g_event_used]), s);
 }
 
 void mark_end(hipStream_t s) {
     if (!g_events || g_event_used >= g_event_cap) return;
-    hipEventRecord(static_cast<hipEvent_t>(g_events[2 * g_event_used + 1]), s);
+    (void)hipEventRecord(static_cast<hipEvent_t>(g_events[2 * g_event_used + 1]), s);
     ++g_event_used;
 }
 
@@ -1387,6 +1388,56 @@ msda_status msda_backward_batched(const msda_batch* b, void* workspace, size_t w
             (e = msda::launch_gfeat_tiles_batched(a, b->feat_dtype, rcpl, s)) != hipSuccess)
             return hip_fail(e, "batched grad_feat tile reduction");
     }
+    return ok();
+}
+
+namespace {
+struct SortWs { size_t keys_a, keys_b, vals_a, vals_b, scratch, total; };
+SortWs sort_layout(uint32_t n) {
+    SortWs w = {};
+    size_t at = 0;
+    auto take = [&](size_t bytes) { const size_t here = at; at += align256(bytes); return here; };
+    w.keys_a = take((size_t)n * 4);
+    w.keys_b = take((size_t)n * 4);
+    w.vals_a = take((size_t)n * 4);
+    w.vals_b = take((size_t)n * 4);
+    w.scratch = take(msda::sort_scratch_words(n) * 4);
+    w.total = at;
+    return w;
+}
+}  // namespace
+
+size_t msda_sort_workspace_size(uint32_t n, uint32_t max_key) {
+    (void)max_key;
+    return sort_layout(n).total;
+}
+
+msda_status msda_sort_keys(const uint32_t* keys, uint32_t n, uint32_t max_key, uint32_t* order,
+                           uint32_t* seg, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!seg || (n > 0 && (!keys || !order)))
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "a required device pointer is NULL");
+    if (max_key == UINT32_MAX) return fail(MSDA_ERR_INVALID_ARGUMENT, "max_key must be < 2^32 - 1");
+    if (n > (1u << 31)) return fail(MSDA_ERR_INVALID_ARGUMENT, "n must be <= 2^31");
+    const SortWs w = sort_layout(n);
+    if (!workspace || workspace_bytes < w.total)
+        return fail(MSDA_ERR_WORKSPACE, "sort workspace too small");
+    if (!aligned(workspace, 256)) return fail(MSDA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    const hipStream_t s = (hipStream_t)stream;
+    char* ws = static_cast<char*>(workspace);
+    hipError_t e = hipSuccess;
+    if (n > 0 && (e = hipMemcpyAsync(ws + w.keys_a, keys, (size_t)n * 4,
+                                     hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return hip_fail(e, "copy keys");
+    uint32_t* sorted = nullptr;
+    e = msda::launch_sort_records(reinterpret_cast<uint32_t*>(ws + w.keys_a),
+                                  reinterpret_cast<uint32_t*>(ws + w.keys_b),
+                                  reinterpret_cast<uint32_t*>(ws + w.vals_a),
+                                  reinterpret_cast<uint32_t*>(ws + w.vals_b), n, max_key,
+                                  reinterpret_cast<uint32_t*>(ws + w.scratch), seg, &sorted, s);
+    if (e != hipSuccess) return hip_fail(e, "msda_sort_keys launch");
+    if (n > 0 && (e = hipMemcpyAsync(order, sorted, (size_t)n * 4, hipMemcpyDeviceToDevice, s)) !=
+                     hipSuccess)
+        return hip_fail(e, "copy order");
     return ok();
 }
 

@@ -8,12 +8,14 @@
 // tiled reduction that follows sums them in a fixed order: grad_feat is
 // bitwise reproducible, and no float atomics are needed.
 //
-// The key bits are split into as few passes as digits of at most 10 bits
-// allow (a 20-bit key space, about a million cells, takes two). Each pass:
-// a per-tile digit histogram, an exclusive scan of the histograms in
-// digit-major order, then a stable scatter where a tile ranks equal digits
-// by wave ballots (lanes in order), then waves in order, then rounds in
-// order.
+// The key bits are split into as few passes as digits of at most 8 bits
+// allow (a 20-bit key space, about a million cells, takes three of 7 bits:
+// wider digits leave runs too short for whole-line writes and cost more
+// ballots). Each pass: a per-tile digit histogram (one row per tile), the
+// tiles' global offsets per digit (band sums, then a walk down each band),
+// then a stable scatter where a tile ranks equal digits by wave ballots,
+// sorts itself by digit in LDS and writes each digit's run to consecutive
+// addresses.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,8 +26,9 @@ namespace msda {
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // elements per tile
-constexpr int kMaxDigitBits = 10;
-constexpr int kMaxDigits = 1 << kMaxDigitBits;
+constexpr int kMaxDigitBits = 8;
+constexpr int kMaxDigits = 1 << kMaxDigitBits;         // one thread per digit below
+constexpr int kBand = 32;                              // tiles per band of the offset scan
 constexpr int kScanTile = 4096;                          // scan: 256 threads x 16
 
 __global__ void __launch_bounds__(kSortThreads)
@@ -38,14 +41,77 @@ radix_hist_kernel(const u32* __restrict__ keys, u32 n, const u32* n_dev, int shi
     __syncthreads();
     const u32 mask = (u32)digits - 1u;
     const u32 base = blockIdx.x * (u32)kSortTile;
-#pragma unroll 4
-    for (int i = 0; i < kSortItems; ++i) {
+    u32 k[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {          // every load in flight at once
         const u32 idx = base + i * kSortThreads + threadIdx.x;
-        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
+        k[i] = idx < n ? keys[idx] : 0u;
     }
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i)
+        if (base + i * kSortThreads + threadIdx.x < n) atomicAdd(&h[(k[i] >> shift) & mask], 1u);
     __syncthreads();
     for (int d = threadIdx.x; d < digits; d += kSortThreads)
-        table[(size_t)d * ntiles + blockIdx.x] = h[d];      // digit-major
+        table[(size_t)blockIdx.x * digits + d] = h[d];      // tile-major: one coalesced row
+}
+
+// Tile offsets from the tile-major count table, in two launches: the column
+// sums of each band of kBand tiles, then per band: the digit's start over the
+// whole input (an exclusive scan over digits of the digit totals) + the
+// counts of earlier bands, walked down the band's tiles in order, each count
+// replaced by its tile's global start for the digit. One thread per digit.
+__global__ void __launch_bounds__(kMaxDigits) digit_band_kernel(const u32* __restrict__ table,
+                                                                u32 ntiles, int digits,
+                                                                u32* __restrict__ band_sum) {
+    const int d = threadIdx.x;
+    if (d >= digits) return;
+    const u32 t0 = blockIdx.x * (u32)kBand;
+    u32 c[kBand];
+#pragma unroll
+    for (int k = 0; k < kBand; ++k)            // every load in flight at once
+        c[k] = t0 + k < ntiles ? table[(size_t)(t0 + k) * digits + d] : 0u;
+    u32 s = 0;
+#pragma unroll
+    for (int k = 0; k < kBand; ++k) s += c[k];
+    band_sum[(size_t)blockIdx.x * digits + d] = s;
+}
+
+__global__ void __launch_bounds__(kMaxDigits) digit_offsets_kernel(u32* __restrict__ table,
+                                                                   u32 ntiles, int digits,
+                                                                   const u32* __restrict__ band_sum,
+                                                                   u32 nbands) {
+    __shared__ u32 lds4[4];
+    const int d = threadIdx.x;
+    const u32 t0 = blockIdx.x * (u32)kBand;
+    u32 c[kBand];
+    u32 total = 0, before = 0;
+    if (d < digits) {
+#pragma unroll
+        for (int k = 0; k < kBand; ++k)
+            c[k] = t0 + k < ntiles ? table[(size_t)(t0 + k) * digits + d] : 0u;
+        constexpr int kStep = 8;               // band sums read 8 at a time
+        for (u32 b = 0; b < nbands; b += kStep) {
+            u32 v[kStep];
+#pragma unroll
+            for (int k = 0; k < kStep; ++k)
+                v[k] = b + k < nbands ? band_sum[(size_t)(b + k) * digits + d] : 0u;
+#pragma unroll
+            for (int k = 0; k < kStep; ++k) {
+                total += v[k];
+                if (b + k < blockIdx.x) before += v[k];
+            }
+        }
+    }
+    u32 all;
+    u32 off = block_inclusive_scan(total, lds4, &all) - total + before;
+    if (d >= digits) return;
+#pragma unroll
+    for (int k = 0; k < kBand; ++k) {
+        if (t0 + k < ntiles) {
+            table[(size_t)(t0 + k) * digits + d] = off;
+            off += c[k];
+        }
+    }
 }
 
 // Scan, phase 1: per-tile sums.
@@ -102,64 +168,128 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(u32* x, u32 n,
 }
 
 // Stable scatter of one tile by the `bits`-bit digit at `shift`. vals_in ==
-// nullptr means the value is the element's index (first pass). Per round of
-// 256 elements: lanes of a wave with equal digits are found with one ballot
-// per digit bit and ranked by lane; the first lane of each such group
-// publishes the group size for its wave, so a lane's place is the tile's
-// offset for the digit + the digit's count in earlier rounds + the groups
-// of earlier waves + its rank. Only the entries a round sets are cleared.
+// nullptr means the value is the element's index (first pass).
+//
+// Wave w owns the tile's elements [w*kWaveItems, (w+1)*kWaveItems) and loads
+// all of them at once (lane-consecutive, kSortItems per lane). Ranking needs
+// no block barrier: per round of 64, lanes with equal digits are found with
+// one ballot per digit bit and ranked by lane, and the wave's running count
+// of the digit (in LDS, one row per wave) is read by every peer and advanced
+// by the group size. After the rounds, per digit, the waves' counts become
+// exclusive prefixes in wave order, offset by the digit's start in the tile
+// (an exclusive scan of the tile's digit counts), so an element's place in
+// the tile, sorted by digit, is that start + its running rank: wave order,
+// then round order, then lane order, i.e. index order (stable). The tile is
+// sorted in LDS, then written out by consecutive lanes, so each digit's run
+// leaves as consecutive addresses.
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kWaveItems = 64 * kSortItems;
+
+template <int BITS>
 __global__ void __launch_bounds__(kSortThreads)
 radix_scatter_kernel(const u32* __restrict__ keys_in, const u32* __restrict__ vals_in,
                      u32* __restrict__ keys_out, u32* __restrict__ vals_out, u32 n,
-                     const u32* n_dev, int shift, int bits, const u32* __restrict__ table,
-                     u32 ntiles) {
-    __shared__ u32 base_off[kMaxDigits];
-    __shared__ u32 running[kMaxDigits];
-    __shared__ u32 wcount[kSortThreads / 64][kMaxDigits];
+                     const u32* n_dev, int shift, const u32* __restrict__ table) {
+    constexpr int bits = BITS;
+    __shared__ u32 s_keys[kSortTile];
+    __shared__ u32 s_vals[kSortTile];
+    __shared__ u32 wcount[kSortWaves][kMaxDigits];
+    __shared__ u32 dest_base[kMaxDigits];      // global start - start in the tile (mod 2^32)
+    __shared__ u32 lds4[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int digits = 1 << bits;
     const u32 mask = (u32)digits - 1u;
     if (n_dev) n = min(n, *n_dev);
-    for (int d = tid; d < digits; d += kSortThreads) {
-        base_off[d] = table[(size_t)d * ntiles + blockIdx.x];
-        running[d] = 0;
+    const u32 tile0 = blockIdx.x * (u32)kSortTile;
+    if (tile0 >= n) return;                    // block-uniform: a tile past a device count
+    const u32 tile_n = min((u32)kSortTile, n - tile0);
+    for (int i = tid; i < kSortWaves * digits; i += kSortThreads)
+        wcount[i / digits][i % digits] = 0;
+
+    u32 key[kSortItems], val[kSortItems], rank[kSortItems];
+    const u32 w0 = tile0 + (u32)(wave * kWaveItems) + (u32)lane;
 #pragma unroll
-        for (int w = 0; w < kSortThreads / 64; ++w) wcount[w][d] = 0;
-    }
-    __syncthreads();
-    const u64 lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int r = 0; r < kSortItems; ++r) {
-        const u32 idx = blockIdx.x * (u32)kSortTile + r * kSortThreads + tid;
+        const u32 idx = w0 + (u32)(r * 64);
         const bool valid = idx < n;
-        const u32 key = valid ? keys_in[idx] : 0u;
-        const u32 val = valid ? (vals_in ? vals_in[idx] : idx) : 0u;
-        const u32 d = (key >> shift) & mask;
-        // lanes of this wave holding the same digit
-        u64 peers = __ballot(valid);
+        key[r] = valid ? keys_in[idx] : 0u;
+        val[r] = valid ? (vals_in ? vals_in[idx] : idx) : 0u;
+    }
+    __syncthreads();                           // wcount cleared
+
+    const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    u32* const run = wcount[wave];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const bool valid = w0 + (u32)(r * 64) < n;
+        const u32 d = (key[r] >> shift) & mask;
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
         for (int bit = 0; bit < bits; ++bit) {
-            const u64 b = __ballot((d >> bit) & 1u);
+            const unsigned long long b = __ballot((d >> bit) & 1u);
             peers &= ((d >> bit) & 1u) ? b : ~b;
         }
-        const u32 rank = __popcll(peers & lt_mask);
-        const u32 count = __popcll(peers);
-        const bool leader = valid && rank == 0;
-        if (leader) wcount[wave][d] = count;
-        __syncthreads();
         if (valid) {
-            u32 before = 0;
-            for (int w = 0; w < wave; ++w) before += wcount[w][d];
-            const u32 dest = base_off[d] + running[d] + before + rank;
-            if (dest < n) {            // always true for a consistent histogram
-                keys_out[dest] = key;
-                vals_out[dest] = val;
+            // every peer reads the running count, then writes the same new
+            // value; the next round's reads come after this write in the
+            // wave's program order
+            const u32 before = run[d];
+            rank[r] = before + (u32)__popcll(peers & lt_mask);
+            run[d] = before + (u32)__popcll(peers);
+        }
+    }
+    __syncthreads();
+
+    // per digit: waves' counts -> exclusive prefixes; the tile's digit
+    // counts -> exclusive scan (each thread owns dpt consecutive digits)
+    const int dpt = digits > kSortThreads ? digits / kSortThreads : 1;
+    const int d0 = tid * dpt;
+    u32 cnt_own = 0;
+    for (int k = 0; k < dpt; ++k) {
+        const int d = d0 + k;
+        if (d < digits) {
+            u32 pre = 0;
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) {
+                const u32 c = wcount[w][d];
+                wcount[w][d] = pre;
+                pre += c;
             }
+            cnt_own += pre;
+            dest_base[d] = pre;                // the digit's count, for now
         }
-        __syncthreads();
-        if (leader) {
-            atomicAdd(&running[d], count);   // integer: the order of the adds does not matter
-            wcount[wave][d] = 0;
+    }
+    u32 total;
+    u32 start = block_inclusive_scan(cnt_own, lds4, &total) - cnt_own;
+    for (int k = 0; k < dpt; ++k) {
+        const int d = d0 + k;
+        if (d < digits) {
+            const u32 c = dest_base[d];
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) wcount[w][d] += start;
+            dest_base[d] = table[(size_t)blockIdx.x * digits + d] - start;
+            start += c;
         }
-        __syncthreads();
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        if (w0 + (u32)(r * 64) < n) {
+            const u32 pos = run[(key[r] >> shift) & mask] + rank[r];
+            s_keys[pos] = key[r];
+            s_vals[pos] = val[r];
+        }
+    }
+    __syncthreads();
+
+    for (u32 j = (u32)tid; j < tile_n; j += kSortThreads) {
+        const u32 k = s_keys[j];
+        const u32 dest = dest_base[(k >> shift) & mask] + j;
+        if (dest < n) {                        // always true for a consistent histogram
+            keys_out[dest] = k;
+            vals_out[dest] = s_vals[j];
+        }
     }
 }
 
@@ -209,11 +339,11 @@ hipError_t launch_exclusive_scan(u32* x, u32 n, u32* partial, hipStream_t s) {
 
 size_t scan_scratch_words(u32 n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
+static u32 bands_of(u32 ntiles) { return (ntiles + kBand - 1) / kBand; }
+
 size_t sort_scratch_words(u32 n) {
     const u32 ntiles = (n + kSortTile - 1) / kSortTile;
-    const size_t table = (size_t)kMaxDigits * ntiles;
-    const size_t partial = (table + kScanTile - 1) / kScanTile + 1;
-    return table + partial;
+    return (size_t)kMaxDigits * ntiles + (size_t)kMaxDigits * bands_of(ntiles);
 }
 
 // Passes and digit width for keys in [0, max_key]: the fewest passes of at
@@ -237,8 +367,9 @@ hipError_t launch_sort_records(u32* keys_a, u32* keys_b, u32* vals_a, u32* vals_
                                hipStream_t s, const u32* n_dev, bool vals_given) {
     hipError_t e = hipSuccess;
     const u32 ntiles = (n + kSortTile - 1) / kSortTile;
+    const u32 nbands = bands_of(ntiles);
     u32* table = scratch;
-    u32* partial = scratch + (size_t)kMaxDigits * ntiles;
+    u32* band_sum = scratch + (size_t)kMaxDigits * ntiles;
     u32* kin = keys_a;
     u32* kout = keys_b;
     // first pass: values are the indices, or the caller's (in vals_a)
@@ -253,11 +384,27 @@ hipError_t launch_sort_records(u32* keys_a, u32* keys_b, u32* vals_a, u32* vals_
                            n_dev, shift, bits, table, ntiles);
         mark_end(s);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = launch_exclusive_scan(table, (u32)(ntiles << bits), partial, s)) != hipSuccess)
-            return e;
+        mark_begin("digit_band", s);
+        hipLaunchKernelGGL(digit_band_kernel, dim3(nbands), dim3(kMaxDigits), 0, s, table, ntiles,
+                           1 << bits, band_sum);
+        mark_end(s);
+        mark_begin("digit_offsets", s);
+        hipLaunchKernelGGL(digit_offsets_kernel, dim3(nbands), dim3(kMaxDigits), 0, s, table,
+                           ntiles, 1 << bits, band_sum, nbands);
+        mark_end(s);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
         mark_begin("radix_scatter", s);
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3(ntiles), dim3(kSortThreads), 0, s, kin, vin,
-                           kout, vout, n, n_dev, shift, bits, table, ntiles);
+        switch (bits) {
+#define MSDA_SCATTER_BITS(B)                                                                   \
+    case B:                                                                                    \
+        hipLaunchKernelGGL(radix_scatter_kernel<B>, dim3(ntiles), dim3(kSortThreads), 0, s, kin, \
+                           vin, kout, vout, n, n_dev, shift, table);                           \
+        break;
+            MSDA_SCATTER_BITS(1) MSDA_SCATTER_BITS(2) MSDA_SCATTER_BITS(3) MSDA_SCATTER_BITS(4)
+            MSDA_SCATTER_BITS(5) MSDA_SCATTER_BITS(6) MSDA_SCATTER_BITS(7) MSDA_SCATTER_BITS(8)
+#undef MSDA_SCATTER_BITS
+            default: return hipErrorInvalidValue;    // sort_plan keeps bits in [1, 8]
+        }
         mark_end(s);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // next pass reads what this one wrote

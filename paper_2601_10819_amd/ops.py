@@ -395,6 +395,26 @@ def quantize_fp8(feat_f32: torch.Tensor, layout: Layout, stream=None):
     return codes, scales
 
 
+def sort_keys(keys: torch.Tensor, max_key: int, stream=None):
+    """Stable sort of uint32 keys (an int32 or uint32 device tensor, values in
+    [0, max_key]) with the backward's record sort: (order int32 [n],
+    seg int32 [max_key + 1]) where order lists the indices by key, equal keys
+    in index order, and seg[r] is the first sorted position whose key >= r."""
+    lib = _lib.load()
+    if keys.dtype not in (torch.int32, torch.uint32) or not keys.is_cuda or keys.dim() != 1:
+        raise ValueError("keys must be a 1-D int32/uint32 device tensor")
+    keys = keys.contiguous()
+    n = keys.numel()
+    order = torch.empty(n, dtype=torch.int32, device=keys.device)
+    seg = torch.empty(max_key + 1, dtype=torch.int32, device=keys.device)
+    ws = torch.empty(max(256, int(lib.msda_sort_workspace_size(n, max_key))), dtype=torch.uint8,
+                     device=keys.device)
+    _lib.check(lib.msda_sort_keys(_ptr(keys) if n else None, n, max_key,
+                                  _ptr(order) if n else None, _ptr(seg), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return order, seg
+
+
 def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
     """Plain streaming copy kernel (the achievable-bandwidth reference)."""
     lib = _lib.load()

@@ -435,3 +435,15 @@ def test_weight_flag_validation(lib):
             lib.msda_forward_visible_workspace_size(ctypes.byref(pv)))
     assert (lib.msda_backward_fused_workspace_size(ctypes.byref(dv)) >
             lib.msda_backward_fused_workspace_size(ctypes.byref(pv)))
+
+
+def test_sort_validation(lib):
+    n, mk = 5000, 1000
+    ws = lib.msda_sort_workspace_size(n, mk)
+    assert ws >= 4 * n * 4
+    expect(lib, lib.msda_sort_keys(FAKE, n, mk, FAKE, None, FAKE, ws, None), INV)
+    expect(lib, lib.msda_sort_keys(None, n, mk, FAKE, FAKE, FAKE, ws, None), INV)
+    expect(lib, lib.msda_sort_keys(FAKE, n, 0xFFFFFFFF, FAKE, FAKE, FAKE, ws, None), INV,
+           "max_key")
+    expect(lib, lib.msda_sort_keys(FAKE, n, mk, FAKE, FAKE, FAKE, ws - 1, None), WS)
+    expect(lib, lib.msda_sort_keys(FAKE, n, mk, FAKE, FAKE, FAKE + 16, ws, None), WS, "aligned")
