@@ -258,12 +258,13 @@ __global__ void __launch_bounds__(256) region_tables_kernel(const int32_t* shape
 // One sample's corners that fall in the tile, added to the accumulators.
 // The sample's cell sits at tile offset (DY, DX), so the corner -> pixel map
 // is static: corners land on (DY-1, DX-1), (DY-1, DX), (DY, DX-1), (DY, DX).
+// f holds the bilinear factors ((1-ly)(1-lx), (1-ly)lx, ly(1-lx), ly lx),
+// computed once per record; each corner's weight is its factor times wv.
 template <int DY, int DX, int TH, int TW, int CPL>
-__device__ __forceinline__ void add_sample(float (&acc)[TH][TW][CPL], float fx, float fy,
-                                           float wv, const float* gv) {
-    const float hx = 1.f - fx, hy = 1.f - fy;
-    const float k00 = hy * hx * wv, k01 = hy * fx * wv;
-    const float k10 = fy * hx * wv, k11 = fy * fx * wv;
+__device__ __forceinline__ void add_sample(float (&acc)[TH][TW][CPL], float4 f, float wv,
+                                           const float* gv) {
+    const float k00 = f.x * wv, k01 = f.y * wv;
+    const float k10 = f.z * wv, k11 = f.w * wv;
     if constexpr (DY >= 1 && DX >= 1) {
 #pragma unroll
         for (int i = 0; i < CPL; ++i) acc[DY - 1][DX - 1][i] = fmaf(k00, gv[i], acc[DY - 1][DX - 1][i]);
@@ -286,10 +287,10 @@ __device__ __forceinline__ void add_sample(float (&acc)[TH][TW][CPL], float fx, 
 // (uniform within the lane group) to the static accumulation: a switch, which
 // the compiler lowers to a jump table.
 template <int CPL>
-__device__ __forceinline__ void add_sample_at(int pos, float (&acc)[4][4][CPL], float fx,
-                                              float fy, float wv, const float* gv) {
+__device__ __forceinline__ void add_sample_at(int pos, float (&acc)[4][4][CPL], float4 f,
+                                              float wv, const float* gv) {
 #define MSDA_CELL_CASE(P) \
-    case P: add_sample<(P) / 5, (P) % 5, 4, 4, CPL>(acc, fx, fy, wv, gv); break;
+    case P: add_sample<(P) / 5, (P) % 5, 4, 4, CPL>(acc, f, wv, gv); break;
     switch (pos) {
         MSDA_CELL_CASE(0) MSDA_CELL_CASE(1) MSDA_CELL_CASE(2) MSDA_CELL_CASE(3) MSDA_CELL_CASE(4)
         MSDA_CELL_CASE(5) MSDA_CELL_CASE(6) MSDA_CELL_CASE(7) MSDA_CELL_CASE(8) MSDA_CELL_CASE(9)
@@ -305,10 +306,15 @@ __device__ __forceinline__ void add_sample_at(int pos, float (&acc)[4][4][CPL], 
 // One sample of a statically known cell (DY, DX): the arithmetic of the
 // switch's case (DY * 5 + DX).
 template <int DY, int DX, int CPL>
-__device__ __forceinline__ void cell_sample(float (&acc)[4][4][CPL], float fx, float fy,
-                                            float wv, const float* gv) {
-    add_sample<DY, DX, 4, 4, CPL>(acc, fx, fy, wv, gv);
+__device__ __forceinline__ void cell_sample(float (&acc)[4][4][CPL], float4 f, float wv,
+                                            const float* gv) {
+    add_sample<DY, DX, 4, 4, CPL>(acc, f, wv, gv);
 }
+
+// Floats per record-table entry: the 4 bilinear factors, the anchor, the
+// cell position, 2 spare, then the G weights (16-byte multiple, so the
+// factors load as one vector).
+__host__ __device__ inline int tile_entry_floats(int G) { return 8 + ((G + 3) & ~3); }
 
 // Cell boundaries of a tile's TH+1 cell rows, (TW+2) per row.
 constexpr int kBndPerGroup = (kTileH + 1) * (kTileW + 2);
@@ -359,7 +365,7 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
                                             u32* bnd_lds, float* work) {
     constexpr int TH = kTileH, TW = kTileW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int stride = v.G + 4;                     // floats per record-table entry
+    const int stride = tile_entry_floats(v.G);      // floats per record-table entry
     float* tab = work + (size_t)wave * 64 * stride + (size_t)(lane - sl) * stride;
     const bool active = v.active;
     const int H = v.H, W = v.W, ty = v.ty, tx = v.tx;
@@ -436,14 +442,15 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
                 // the fused form: the sample's weights times its view's factor
                 const u32 n = (ls / (u32)v.L) % (u32)v.N;
                 const float sc = v.vscale[(size_t)an * v.N + n];
-                for (int k = 0; k < v.G; ++k) ent[k] = ws[k] * sc;
+                for (int k = 0; k < v.G; ++k) ent[8 + k] = ws[k] * sc;
             } else {
-                for (int k = 0; k < v.G; ++k) ent[k] = ws[k];
+                for (int k = 0; k < v.G; ++k) ent[8 + k] = ws[k];
             }
-            ent[v.G] = fr.x;
-            ent[v.G + 1] = fr.y;
-            ent[v.G + 2] = __uint_as_float(an);
-            ent[v.G + 3] = __int_as_float(dy * (TW + 1) + dx);
+            const float hx = 1.f - fr.x, hy = 1.f - fr.y;
+            *reinterpret_cast<float4*>(ent) =
+                make_float4(hy * hx, hy * fr.x, fr.y * hx, fr.y * fr.x);
+            ent[4] = __uint_as_float(an);
+            ent[5] = __int_as_float(dy * (TW + 1) + dx);
         }
         // LDS accesses of one wave are performed in order; keep the compiler
         // from hoisting the reads above the writes
@@ -473,23 +480,23 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
                             for (int k = 0; k < 4; ++k) {
                                 const float* ent = tab + (qq + k) * stride;
                                 load_go<CPL>(v.grad_out +
-                                                 (size_t)__float_as_uint(ent[v.G + 2]) * v.C + c0,
+                                                 (size_t)__float_as_uint(ent[4]) * v.C + c0,
                                              gv[k]);
                             }
 #pragma unroll
                             for (int k = 0; k < 4; ++k) {
                                 const float* ent = tab + (qq + k) * stride;
-                                cell_sample<DY, DX, CPL>(acc, ent[v.G], ent[v.G + 1], ent[g],
-                                                         gv[k]);
+                                cell_sample<DY, DX, CPL>(
+                                    acc, *reinterpret_cast<const float4*>(ent), ent[8 + g], gv[k]);
                             }
                         }
                         for (; qq < qe; ++qq) {
                             const float* ent = tab + qq * stride;
                             float gv[CPL];
-                            load_go<CPL>(v.grad_out + (size_t)__float_as_uint(ent[v.G + 2]) * v.C +
-                                             c0,
+                            load_go<CPL>(v.grad_out + (size_t)__float_as_uint(ent[4]) * v.C + c0,
                                          gv);
-                            cell_sample<DY, DX, CPL>(acc, ent[v.G], ent[v.G + 1], ent[g], gv);
+                            cell_sample<DY, DX, CPL>(acc, *reinterpret_cast<const float4*>(ent),
+                                                     ent[8 + g], gv);
                         }
                     });
                 }
@@ -506,21 +513,21 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
 #pragma unroll
             for (int k = 0; k < kGoBatch; ++k) {
                 const float* ent = tab + (q + k) * stride;
-                load_go<CPL>(v.grad_out + (size_t)__float_as_uint(ent[v.G + 2]) * v.C + c0, gv[k]);
+                load_go<CPL>(v.grad_out + (size_t)__float_as_uint(ent[4]) * v.C + c0, gv[k]);
             }
 #pragma unroll
             for (int k = 0; k < kGoBatch; ++k) {
                 const float* ent = tab + (q + k) * stride;
-                add_sample_at<CPL>(__float_as_int(ent[v.G + 3]), acc, ent[v.G], ent[v.G + 1],
-                                   ent[g], gv[k]);
+                add_sample_at<CPL>(__float_as_int(ent[5]), acc,
+                                   *reinterpret_cast<const float4*>(ent), ent[8 + g], gv[k]);
             }
         }
         for (; q < n; ++q) {
             const float* ent = tab + q * stride;
             float gv[CPL];
-            load_go<CPL>(v.grad_out + (size_t)__float_as_uint(ent[v.G + 2]) * v.C + c0, gv);
-            add_sample_at<CPL>(__float_as_int(ent[v.G + 3]), acc, ent[v.G], ent[v.G + 1], ent[g],
-                               gv);
+            load_go<CPL>(v.grad_out + (size_t)__float_as_uint(ent[4]) * v.C + c0, gv);
+            add_sample_at<CPL>(__float_as_int(ent[5]), acc, *reinterpret_cast<const float4*>(ent),
+                               ent[8 + g], gv);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -573,11 +580,12 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
 }
 
 template <class OT, int CPL, bool WHOLE_WAVE, bool CELLS>
-__global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
+__device__ __forceinline__ void gfeat_tile_body(const TileArgs& t) {
     static_assert(kTileH == 4 && kTileW == 4, "the cell dispatch is written for 4x4 tiles");
     // LDS: per lane group its tile's cell boundaries; per wave a record table
-    // (64 entries of G weights, lx, ly, anchor, cell position); after the
-    // records, the waves' partial sums reuse the record tables' space.
+    // (64 entries of bilinear factors, anchor, cell position and G weights);
+    // after the records, the waves' partial sums reuse the record tables'
+    // space.
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int TH = kTileH, TW = kTileW;
     const int lane = threadIdx.x & 63;
@@ -631,9 +639,25 @@ __global__ void __launch_bounds__(256) gfeat_tile_kernel(TileArgs t) {
     tile_reduce<OT, CPL, WHOLE_WAVE, CELLS>(v, lps, spw, grp, sl, t.waves, bnd_lds, work);
 }
 
+// Whole-wave lane groups (C = 64 * CPL): at most 128 VGPRs, i.e. 4 waves per
+// SIMD. The reduction waits on record and grad_out loads, and a fourth wave
+// hides more of that than the few registers it spills cost (measured on the
+// 64-camera scene: light tiles 0.28 -> 0.24 ms, coarse 0.19 -> 0.18 ms).
+// Narrower groups keep the compiler's choice (they would spill heavily).
+template <class OT, int CPL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+gfeat_tile_kernel(TileArgs t) {
+    gfeat_tile_body<OT, CPL, true, true>(t);
+}
+
+template <class OT, int CPL>
+__global__ void __launch_bounds__(256) gfeat_tile_group_kernel(TileArgs t) {
+    gfeat_tile_body<OT, CPL, false, false>(t);
+}
+
 // Batched tiled reduction: tiles of all scenes' regions in slot order.
 template <class OT, int CPL, bool WHOLE_WAVE>
-__global__ void __launch_bounds__(256) gfeat_tile_batched_kernel(BatchArgs b) {
+__device__ __forceinline__ void gfeat_tile_batched_body(const BatchArgs& b) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int TH = kTileH, TW = kTileW;
     const int lane = threadIdx.x & 63;
@@ -678,6 +702,17 @@ __global__ void __launch_bounds__(256) gfeat_tile_batched_kernel(BatchArgs b) {
     v.N = 1;
     v.L = 1;
     tile_reduce<OT, CPL, WHOLE_WAVE, WHOLE_WAVE>(v, lps, spw, grp, sl, b.waves, bnd_lds, work);
+}
+
+template <class OT, int CPL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+gfeat_tile_batched_kernel(BatchArgs b) {
+    gfeat_tile_batched_body<OT, CPL, true>(b);
+}
+
+template <class OT, int CPL>
+__global__ void __launch_bounds__(256) gfeat_tile_batched_group_kernel(BatchArgs b) {
+    gfeat_tile_batched_body<OT, CPL, false>(b);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -741,15 +776,15 @@ static hipError_t tile_launch(const TileArgs& t, hipStream_t s) {
     const u32 blocks = (ntiles + spw - 1) / spw;
     if (blocks == 0) return hipSuccess;
     const size_t part = t.waves > 1 ? (size_t)(t.waves / 2) * kTileH * kTileW * CPL * 64 * 4 : 0;
-    const size_t tables = (size_t)t.waves * 64 * (t.G + 4) * sizeof(float);
+    const size_t tables = (size_t)t.waves * 64 * tile_entry_floats(t.G) * sizeof(float);
     const size_t lds = bnd_lds_bytes(t.waves, t.lps_shift) + (part > tables ? part : tables);
     mark_begin(t.waves > 1 ? "gfeat_tile_kernel_coarse" : "gfeat_tile_kernel", s);
     // whole-wave groups walk each chunk cell by cell
     if (t.lps_shift == 6)
-        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL, true, true>), dim3(blocks),
+        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL>), dim3(blocks),
                            dim3(64 * t.waves), lds, s, t);
     else
-        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL, false, false>), dim3(blocks),
+        hipLaunchKernelGGL((gfeat_tile_group_kernel<OT, CPL>), dim3(blocks),
                            dim3(64 * t.waves), lds, s, t);
     mark_end(s);
     return hipGetLastError();
@@ -816,14 +851,14 @@ static hipError_t tile_batched_launch(const BatchArgs& b, hipStream_t s) {
     const u32 blocks = (ntiles + spw - 1) / spw;
     if (blocks == 0) return hipSuccess;
     const size_t part = b.waves > 1 ? (size_t)(b.waves / 2) * kTileH * kTileW * CPL * 64 * 4 : 0;
-    const size_t tables = (size_t)b.waves * 64 * (b.G + 4) * sizeof(float);
+    const size_t tables = (size_t)b.waves * 64 * tile_entry_floats(b.G) * sizeof(float);
     const size_t lds = bnd_lds_bytes(b.waves, b.lps_shift) + (part > tables ? part : tables);
     mark_begin(b.waves > 1 ? "gfeat_tile_batched_coarse" : "gfeat_tile_batched", s);
     if (b.lps_shift == 6)
-        hipLaunchKernelGGL((gfeat_tile_batched_kernel<OT, CPL, true>), dim3(blocks),
+        hipLaunchKernelGGL((gfeat_tile_batched_kernel<OT, CPL>), dim3(blocks),
                            dim3(64 * b.waves), lds, s, b);
     else
-        hipLaunchKernelGGL((gfeat_tile_batched_kernel<OT, CPL, false>), dim3(blocks),
+        hipLaunchKernelGGL((gfeat_tile_batched_group_kernel<OT, CPL>), dim3(blocks),
                            dim3(64 * b.waves), lds, s, b);
     mark_end(s);
     return hipGetLastError();
