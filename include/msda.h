@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define MSDA_ABI_VERSION 5
+#define MSDA_ABI_VERSION 6
 
 typedef enum msda_status {
     MSDA_OK = 0,
@@ -410,8 +410,14 @@ msda_status msda_stream_copy(void* dst, const void* src, size_t bytes, void* str
  * hipEventElapsedTime. msda_recorded_kernels() returns how many were
  * recorded so far and msda_recorded_kernel_name(i) the name of the i-th.
  * events == NULL turns the hook off. Not for use during graph capture.
+ * msda_set_kernel_event_filter(name) restricts the hook to kernels of that
+ * instrumentation name (as msda_recorded_kernel_name reports it; other
+ * launches record nothing and use no slot), so that one kernel can be timed
+ * without an event pair around every other launch; NULL or "" records all.
+ * The filter is per calling thread and stays until changed.
  */
 msda_status msda_set_kernel_events(void* const* events, int32_t max_kernels);
+msda_status msda_set_kernel_event_filter(const char* kernel);
 int32_t msda_recorded_kernels(void);
 const char* msda_recorded_kernel_name(int32_t i);
 

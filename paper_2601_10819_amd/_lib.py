@@ -28,7 +28,7 @@ MSDA_DETERMINISTIC = 1
 MSDA_WEIGHT_LOGITS = 2
 MSDA_WEIGHTS_BF16 = 4
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 # Every symbol include/msda.h declares.
 EXPORTS = (
@@ -39,7 +39,8 @@ EXPORTS = (
     "msda_forward_fused_workspace_size", "msda_backward_fused",
     "msda_backward_fused_workspace_size", "msda_quantize_fp8",
     "msda_quantize_workspace_size", "msda_batched_workspace_size", "msda_forward_batched",
-    "msda_backward_batched", "msda_sort_keys", "msda_sort_workspace_size", "msda_stream_copy", "msda_set_kernel_events",
+    "msda_backward_batched", "msda_sort_keys", "msda_sort_workspace_size", "msda_stream_copy",
+    "msda_set_kernel_events", "msda_set_kernel_event_filter",
     "msda_recorded_kernels", "msda_recorded_kernel_name", "msda_last_error", "msda_abi_version",
 )
 
@@ -168,6 +169,8 @@ def load(path: str = LIB_PATH):
     lib.msda_stream_copy.restype = ctypes.c_int
     lib.msda_set_kernel_events.argtypes = [vp, ctypes.c_int32]
     lib.msda_set_kernel_events.restype = ctypes.c_int
+    lib.msda_set_kernel_event_filter.argtypes = [ctypes.c_char_p]
+    lib.msda_set_kernel_event_filter.restype = ctypes.c_int
     lib.msda_recorded_kernels.argtypes = []
     lib.msda_recorded_kernels.restype = ctypes.c_int32
     lib.msda_recorded_kernel_name.argtypes = [ctypes.c_int32]

@@ -7,6 +7,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <cstring>
 #include <string>
 #include <utility>
 #include <vector>
@@ -22,6 +23,8 @@ thread_local void* const* g_events = nullptr;
 thread_local int32_t g_event_cap = 0;
 thread_local int32_t g_event_used = 0;
 thread_local const char* g_event_names[256];
+thread_local std::string g_event_filter;     // record only this kernel name ("" = all)
+thread_local bool g_event_open = false;      // the last mark_begin recorded an event
 
 msda_status fail(msda_status st, const char* fmt, ...) {
     char buf[512];
@@ -334,14 +337,18 @@ void divmagic(uint32_t d, uint64_t* m, int* shift) {
 namespace msda {
 
 void mark_begin(const char* kernel, hipStream_t s) {
+    g_event_open = false;
     if (!g_events || g_event_used >= g_event_cap) return;
+    if (!g_event_filter.empty() && g_event_filter != kernel) return;
+    g_event_open = true;
     g_event_names[g_event_used] = kernel;
     // instrumentation only: a failed record shows as a missing duration
     (void)hipEventRecord(static_cast<hipEvent_t>(g_events[2 * g_event_used]), s);
 }
 
 void mark_end(hipStream_t s) {
-    if (!g_events || g_event_used >= g_event_cap) return;
+    if (!g_event_open) return;
+    g_event_open = false;
     (void)hipEventRecord(static_cast<hipEvent_t>(g_events[2 * g_event_used + 1]), s);
     ++g_event_used;
 }
@@ -358,6 +365,13 @@ msda_status msda_set_kernel_events(void* const* events, int32_t max_kernels) {
     g_events = events;
     g_event_cap = events ? max_kernels : 0;
     g_event_used = 0;
+    return ok();
+}
+
+msda_status msda_set_kernel_event_filter(const char* kernel) {
+    if (kernel && std::strlen(kernel) > 255)
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "kernel name longer than 255 characters");
+    g_event_filter = kernel ? kernel : "";
     return ok();
 }
 

@@ -172,6 +172,9 @@ def test_kernel_event_hook_validation(lib):
     assert lib.msda_set_kernel_events(None, 0) == _lib.MSDA_OK
     assert lib.msda_recorded_kernels() == 0
     assert lib.msda_recorded_kernel_name(0) == b""
+    expect(lib, lib.msda_set_kernel_event_filter(b"k" * 256), INV, "255")
+    assert lib.msda_set_kernel_event_filter(b"radix_scatter") == _lib.MSDA_OK
+    assert lib.msda_set_kernel_event_filter(None) == _lib.MSDA_OK
 
 
 def test_empty_anchor_set_is_ok_without_launch(lib):

@@ -24,7 +24,9 @@ CASES = [
     (100_000, 630_000, "sorted"),
     (100_000, 630_000, "reversed"),
     (65_536, 630_000, "clustered"),    # runs of equal keys longer than a tile
-    (50_000, (1 << 24) - 1, "uniform"),  # three 9-bit passes
+    (50_000, (1 << 24) - 1, "uniform"),  # three 8-bit passes
+    (2_995_200, 630_000, "uniform"),   # the 64-camera scene's record count: 732 tiles, 23 bands
+    (20_056_660, 4_000_000, "sentinel"),  # the 12-scene batch's: 4,897 tiles, 154 bands
 ]
 
 
@@ -64,3 +66,41 @@ def test_two_sizes_back_to_back():
         keys = make_keys(n, 630_000, "uniform", seed)
         order, seg = ops.sort_keys(torch.from_numpy(keys.astype(np.int32)).to(DEV), 630_000)
         np.testing.assert_array_equal(order.cpu().numpy(), np.argsort(keys, kind="stable"))
+
+
+def test_kernel_event_filter_records_only_the_named_kernel():
+    # the benchmark times its roofline kernel this way: with the filter set,
+    # only that kernel's launches take event slots (three radix passes here)
+    import ctypes
+
+    from bench import HipEvents
+    from paper_2601_10819_amd import _lib
+
+    lib = _lib.load()
+    ev = HipEvents()
+    cap = 8
+    arr = (ctypes.c_void_p * (2 * cap))(*[ev.create() for _ in range(2 * cap)])
+    keys = torch.from_numpy(make_keys(100_000, 630_000, "uniform", 3).astype(np.int32)).to(DEV)
+    try:
+        assert lib.msda_set_kernel_event_filter(b"radix_scatter") == _lib.MSDA_OK
+        assert lib.msda_set_kernel_events(arr, cap) == _lib.MSDA_OK
+        ops.sort_keys(keys, 630_000)
+        names = [lib.msda_recorded_kernel_name(i).decode()
+                 for i in range(lib.msda_recorded_kernels())]
+        lib.msda_set_kernel_events(None, 0)
+        torch.cuda.synchronize()
+        assert names == ["radix_scatter"] * 3
+        assert all(ev.elapsed_ms(arr[2 * i], arr[2 * i + 1]) > 0 for i in range(3))
+        # without the filter every launch of the sort is recorded
+        assert lib.msda_set_kernel_event_filter(None) == _lib.MSDA_OK
+        assert lib.msda_set_kernel_events(arr, cap) == _lib.MSDA_OK
+        ops.sort_keys(keys, 630_000)
+        n_all = lib.msda_recorded_kernels()
+        lib.msda_set_kernel_events(None, 0)
+        torch.cuda.synchronize()
+        assert n_all == min(cap, 3 * 4 + 1)
+    finally:
+        lib.msda_set_kernel_events(None, 0)
+        lib.msda_set_kernel_event_filter(None)
+        for e in arr:
+            ev.destroy(e)
