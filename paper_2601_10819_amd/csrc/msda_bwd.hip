@@ -359,7 +359,7 @@ struct TileView {
 // pixel map is a compile-time constant (no per-record dispatch); records of
 // a cell are consecutive in the sorted order, so the visiting order, and
 // the sums, are those of the flat walk.
-template <class OT, int CPL, bool WHOLE_WAVE, bool CELLS>
+template <class OT, int CPL, bool WHOLE_WAVE, bool CELLS, int QB = 4>
 __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, const int spw,
                                             const int grp, const int sl, const int waves,
                                             u32* bnd_lds, float* work) {
@@ -474,17 +474,17 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
                         const u32 hi = min(f0 + (e1 - rstart), base + (u32)n);
                         int qq = (int)lo - (int)base;
                         const int qe = (int)hi - (int)base;
-                        for (; qq + 4 <= qe; qq += 4) {
-                            float gv[4][CPL];
+                        for (; qq + QB <= qe; qq += QB) {
+                            float gv[QB][CPL];
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) {
+                            for (int k = 0; k < QB; ++k) {
                                 const float* ent = tab + (qq + k) * stride;
                                 load_go<CPL>(v.grad_out +
                                                  (size_t)__float_as_uint(ent[4]) * v.C + c0,
                                              gv[k]);
                             }
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) {
+                            for (int k = 0; k < QB; ++k) {
                                 const float* ent = tab + (qq + k) * stride;
                                 cell_sample<DY, DX, CPL>(
                                     acc, *reinterpret_cast<const float4*>(ent), ent[8 + g], gv[k]);
@@ -579,7 +579,7 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
     }
 }
 
-template <class OT, int CPL, bool WHOLE_WAVE, bool CELLS>
+template <class OT, int CPL, bool WHOLE_WAVE, bool CELLS, int QB = 4>
 __device__ __forceinline__ void gfeat_tile_body(const TileArgs& t) {
     static_assert(kTileH == 4 && kTileW == 4, "the cell dispatch is written for 4x4 tiles");
     // LDS: per lane group its tile's cell boundaries; per wave a record table
@@ -636,7 +636,7 @@ __device__ __forceinline__ void gfeat_tile_body(const TileArgs& t) {
     v.vscale = t.view_scale;
     v.N = t.N;
     v.L = t.L;
-    tile_reduce<OT, CPL, WHOLE_WAVE, CELLS>(v, lps, spw, grp, sl, t.waves, bnd_lds, work);
+    tile_reduce<OT, CPL, WHOLE_WAVE, CELLS, QB>(v, lps, spw, grp, sl, t.waves, bnd_lds, work);
 }
 
 // Whole-wave lane groups (C = 64 * CPL): at most 128 VGPRs, i.e. 4 waves per
@@ -644,10 +644,14 @@ __device__ __forceinline__ void gfeat_tile_body(const TileArgs& t) {
 // hides more of that than the few registers it spills cost (measured on the
 // 64-camera scene: light tiles 0.28 -> 0.24 ms, coarse 0.19 -> 0.18 ms).
 // Narrower groups keep the compiler's choice (they would spill heavily).
-template <class OT, int CPL>
+// QB: records whose grad_out rows are loaded together in the cell walk; 2
+// for the one-wave light tiles (fewer registers: no spills at 128), 4 for
+// the coarse tiles (measured: light 0.248 -> 0.234 ms with 2, coarse 0.180
+// -> 0.191 ms).
+template <class OT, int CPL, int QB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 gfeat_tile_kernel(TileArgs t) {
-    gfeat_tile_body<OT, CPL, true, true>(t);
+    gfeat_tile_body<OT, CPL, true, true, QB>(t);
 }
 
 template <class OT, int CPL>
@@ -780,8 +784,11 @@ static hipError_t tile_launch(const TileArgs& t, hipStream_t s) {
     const size_t lds = bnd_lds_bytes(t.waves, t.lps_shift) + (part > tables ? part : tables);
     mark_begin(t.waves > 1 ? "gfeat_tile_kernel_coarse" : "gfeat_tile_kernel", s);
     // whole-wave groups walk each chunk cell by cell
-    if (t.lps_shift == 6)
-        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL>), dim3(blocks),
+    if (t.lps_shift == 6 && t.waves > 1)
+        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL, 4>), dim3(blocks),
+                           dim3(64 * t.waves), lds, s, t);
+    else if (t.lps_shift == 6)
+        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL, 2>), dim3(blocks),
                            dim3(64 * t.waves), lds, s, t);
     else
         hipLaunchKernelGGL((gfeat_tile_group_kernel<OT, CPL>), dim3(blocks),
