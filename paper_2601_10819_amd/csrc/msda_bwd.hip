@@ -660,7 +660,7 @@ __global__ void __launch_bounds__(256) gfeat_tile_group_kernel(TileArgs t) {
 }
 
 // Batched tiled reduction: tiles of all scenes' regions in slot order.
-template <class OT, int CPL, bool WHOLE_WAVE>
+template <class OT, int CPL, bool WHOLE_WAVE, int QB = 4>
 __device__ __forceinline__ void gfeat_tile_batched_body(const BatchArgs& b) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int TH = kTileH, TW = kTileW;
@@ -705,13 +705,15 @@ __device__ __forceinline__ void gfeat_tile_batched_body(const BatchArgs& b) {
     v.vscale = nullptr;
     v.N = 1;
     v.L = 1;
-    tile_reduce<OT, CPL, WHOLE_WAVE, WHOLE_WAVE>(v, lps, spw, grp, sl, b.waves, bnd_lds, work);
+    tile_reduce<OT, CPL, WHOLE_WAVE, WHOLE_WAVE, QB>(v, lps, spw, grp, sl, b.waves, bnd_lds,
+                                                     work);
 }
 
-template <class OT, int CPL>
+// As gfeat_tile_kernel: 4 waves per SIMD, QB = 2 for the light tiles.
+template <class OT, int CPL, int QB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 gfeat_tile_batched_kernel(BatchArgs b) {
-    gfeat_tile_batched_body<OT, CPL, true>(b);
+    gfeat_tile_batched_body<OT, CPL, true, QB>(b);
 }
 
 template <class OT, int CPL>
@@ -861,8 +863,11 @@ static hipError_t tile_batched_launch(const BatchArgs& b, hipStream_t s) {
     const size_t tables = (size_t)b.waves * 64 * tile_entry_floats(b.G) * sizeof(float);
     const size_t lds = bnd_lds_bytes(b.waves, b.lps_shift) + (part > tables ? part : tables);
     mark_begin(b.waves > 1 ? "gfeat_tile_batched_coarse" : "gfeat_tile_batched", s);
-    if (b.lps_shift == 6)
-        hipLaunchKernelGGL((gfeat_tile_batched_kernel<OT, CPL>), dim3(blocks),
+    if (b.lps_shift == 6 && b.waves > 1)
+        hipLaunchKernelGGL((gfeat_tile_batched_kernel<OT, CPL, 4>), dim3(blocks),
+                           dim3(64 * b.waves), lds, s, b);
+    else if (b.lps_shift == 6)
+        hipLaunchKernelGGL((gfeat_tile_batched_kernel<OT, CPL, 2>), dim3(blocks),
                            dim3(64 * b.waves), lds, s, b);
     else
         hipLaunchKernelGGL((gfeat_tile_batched_group_kernel<OT, CPL>), dim3(blocks),
