@@ -450,3 +450,9 @@ def test_sort_validation(lib):
            "max_key")
     expect(lib, lib.msda_sort_keys(FAKE, n, mk, FAKE, FAKE, FAKE, ws - 1, None), WS)
     expect(lib, lib.msda_sort_keys(FAKE, n, mk, FAKE, FAKE, FAKE + 16, ws, None), WS, "aligned")
+    big = (1 << 31) + 1
+    expect(lib, lib.msda_sort_keys(FAKE, big, mk, FAKE, FAKE, FAKE,
+                                   lib.msda_sort_workspace_size(big, mk), None), INV, "2^31")
+    # n == 0 needs no keys or order, only seg
+    assert lib.msda_sort_workspace_size(0, mk) >= 0
+    expect(lib, lib.msda_sort_keys(None, 0, mk, None, None, FAKE, 256, None), INV)
