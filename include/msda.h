@@ -154,7 +154,8 @@ msda_status msda_forward(const void* feat, const int32_t* spatial_shapes,
                          void* stream);
 
 /*
- * msda_forward with a workspace, which lets the library use view order
+ * msda_forward (the same operator, Sec. 3.1/3.2) with a workspace, which lets
+ * the library use view order
  * (MSDA_ORDER_VIEW) for the forward: the library's choice for inputs with at
  * least 8 (batch item, camera) views. Same results contract as
  * msda_forward; the two orders add the samples in different orders, each
@@ -176,7 +177,12 @@ size_t msda_forward_workspace_size(const msda_desc* desc);
 /*
  * Backward: gradients of <grad_out, out> with respect to feat, sampling_loc
  * and weights (the analytic derivative of the forward; at an integer
- * coordinate the right-hand derivative). Any of grad_feat,
+ * coordinate the right-hand derivative). The paper describes and accelerates
+ * the forward only (Sec. 5.3); the model it belongs to is trained end to end
+ * with the losses of Sec. 3.3 (Eq. 3), which is why the operator needs a
+ * backward at all. Its form here -- the derivative of the sum defined above,
+ * with a deterministic grad_feat reduction -- is this library's design, not
+ * a procedure from the paper. Any of grad_feat,
  * grad_sampling_loc, grad_weights may be NULL to skip it. grad_feat has the
  * feat dtype; FP8 grad_feat is UNSUPPORTED. Accumulation is FP32; a BF16 or
  * FP16 grad_feat is rounded once (to nearest even) from the FP32 sum.
@@ -232,7 +238,10 @@ msda_status msda_project_keypoints(const float* anchors, const float* keypoints,
 
 /*
  * Visible-view MSDA: the forward and backward restricted to the (batch item,
- * anchor, camera) pairs with visible[b][a][n] != 0 (uint8 [B][A][Ncam],
+ * anchor, camera) pairs with visible[b][a][n] != 0 (the cameras an anchor is
+ * seen from; the paper scores visibility per object and camera, Sec. 3.2 /
+ * Eq. 1, with a network -- here any flag, e.g. the geometric one of
+ * msda_project_keypoints) (uint8 [B][A][Ncam],
  * device; e.g. from msda_project_keypoints). Samples of other pairs are not
  * read or computed: out sums over the visible pairs only, and their
  * grad_sampling_loc and grad_weights are written as zero. The visible items
@@ -291,7 +300,9 @@ msda_status msda_backward_fused(const void* feat, const int32_t* spatial_shapes,
 size_t msda_backward_fused_workspace_size(const msda_desc* desc);
 
 /*
- * Per-level FP8 quantisation of an FP32 feat (the precision form's storage):
+ * Per-level FP8 quantisation of an FP32 feat (the precision form's storage;
+ * the paper stores MSDA's features in FP16, Sec. 5.3, and e4m3 with a scale
+ * per level is this library's lower-precision option):
  * scale_l = amax_l / 448 over every batch item, camera and channel of level l
  * (1 when the level is all zero), code = round-to-nearest-even(clamp(x /
  * scale_l, -448, 448)) in OCP e4m3fn. Rows in no region are written as 0.
@@ -306,7 +317,10 @@ size_t msda_quantize_workspace_size(const msda_desc* desc);
 
 /*
  * Batched form: several scenes of uneven size in one persistent launch per
- * pass (the scenes of a multi-camera deployment processed together). Each
+ * pass (the scenes of a multi-camera deployment processed together). The
+ * paper measures how many camera streams one GPU serves (Sec. 5.3, App. B,
+ * App. C) but gives no batched kernel; this form is this library's design
+ * for that workload. Each
  * scene is one batch item with its own cameras, feature geometry and
  * anchors; levels, keypoints, channels, groups and the feature dtype are
  * shared. The results are those of msda_forward / msda_backward called on
@@ -378,9 +392,10 @@ msda_status msda_backward_batched(const msda_batch* batch, void* workspace,
                                   size_t workspace_bytes, void* stream);
 
 /*
- * The grouping step of the deterministic grad_feat reduction on its own (the
- * backward's scatter to the features, Sec. 3.3, done by sorting the samples'
- * records by bilinear cell): a stable sort of n uint32 keys in [0, max_key].
+ * The grouping step of the backward's deterministic grad_feat reduction on
+ * its own (the scatter of the samples' contributions to the features, done
+ * by sorting the samples' records by bilinear cell; part of this library's
+ * backward, which the paper does not describe -- see msda_backward): a stable sort of n uint32 keys in [0, max_key].
  * keys [n] device, read only; order [n] device, written: order[i] is the
  * index of the i-th smallest key, equal keys in index order; seg
  * [max_key + 1] device, written: seg[r] is the first position of the sorted

@@ -317,38 +317,6 @@ def test_view_order_forward_workspace(lib):
                                None) == _lib.MSDA_OK
 
 
-def test_view_partition_covers_every_item_once():
-    """The slot / row partition of view order (mirrored from the C++ helpers
-    in csrc/msda_internal.h): every (batch item, anchor, camera) lands in
-    exactly one row of one slot, every row's cameras lie in [0, N), and the
-    slots' item counts differ by at most one."""
-    def span(x, B, N, A):
-        T = B * N * A
-        lo, hi = T * x // 8, T * (x + 1) // 8
-        if hi <= lo:
-            return lo, hi, 1, 0
-        return lo, hi, lo // A // N, (hi - 1) // A // N
-
-    for B, N, A in [(1, 64, 900), (2, 16, 1800), (1, 6, 900), (3, 7, 5), (2, 3, 1), (1, 1, 3)]:
-        seen = set()
-        sizes = []
-        for x in range(8):
-            lo, hi, bf, bl = span(x, B, N, A)
-            sizes.append(hi - lo)
-            rows = (bl - bf + 1) * A if bl >= bf else 0
-            for r in range(rows):
-                b, a = bf + r // A, r % A
-                v0, v1 = (lo - a + A - 1) // A, (hi - a + A - 1) // A
-                v0, v1 = max(v0, b * N), min(v1, (b + 1) * N)
-                for v in range(v0, v1):
-                    n = v - b * N
-                    assert 0 <= n < N and 0 <= b < B
-                    assert (b, a, n) not in seen
-                    seen.add((b, a, n))
-        assert len(seen) == B * N * A
-        assert max(sizes) - min(sizes) <= 1
-
-
 def test_projection_validation(lib):
     d = _lib.MsdaProjDesc(1, 4, 3, 2, 0.1)
     expect(lib, lib.msda_project_keypoints(FAKE, FAKE, FAKE, FAKE, FAKE, None, ctypes.byref(d),

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 from helpers import (BF16_TOL, GRAD_F32_MAXREL, GRAD_F32_TOL, anchor_subset, assert_close,
-                     host, oracle_backward_subset, to_device)
+                     host, normwise, oracle_backward_subset, to_device)
 from paper_2601_10819_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -159,6 +159,56 @@ def test_autograd_function(ops, oracle_mod):
     feat2 = feat.detach().requires_grad_(True)
     ops.msda(feat2, layout, loc2, w.detach()).sum().backward()
     assert feat2.grad is not None and loc2.grad is None
+
+
+def test_autograd_training_step_train16_bf16(ops, oracle_mod):
+    """The outside-in training step (B = 2, 16 cameras, BF16 features, FP32
+    locations and weights, 25% of keypoints outside each camera's view)
+    through the autograd Function with loss = <grad_out, out>: the forward on
+    an anchor subset, feat.grad in full, loc.grad and w.grad on an anchor
+    subset, each against the oracle on the stored (widened) features, plus
+    the Euler identities of the whole step."""
+    p = synth.train16()
+    print(f"case {p.name} {p.dims()} bf16 autograd", flush=True)
+    go = synth.grad_out_like(p, seed=11)
+    feat, layout, loc, w = to_device(p, torch.bfloat16)
+    feat.requires_grad_(True)
+    loc.requires_grad_(True)
+    w.requires_grad_(True)
+    out = ops.msda(feat, layout, loc, w)
+    loss = (out * go.cuda()).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    assert feat.grad.dtype == torch.bfloat16
+    assert loc.grad.dtype == torch.float32 and w.grad.dtype == torch.float32
+    feat64 = p.feat.to(torch.bfloat16).double()
+    idx = anchor_subset(p, 48, seed=12)
+    ref_out = oracle_mod.forward(feat64, p.spatial_shapes, p.level_start_index,
+                                 p.sampling_loc[:, idx].contiguous(),
+                                 p.weights[:, idx].contiguous())
+    assert_close(host(out)[:, idx], ref_out, 1e-5, 2e-4, "train16 bf16 out")
+    rgl, rgw = oracle_backward_subset(oracle_mod, feat64, p, idx, go)
+    assert_close(host(loc.grad)[:, idx], rgl, GRAD_F32_TOL, GRAD_F32_MAXREL, "train16 loc.grad")
+    assert_close(host(w.grad)[:, idx], rgw, GRAD_F32_TOL, GRAD_F32_MAXREL, "train16 w.grad")
+    # the out-of-view samples (a quarter of the keypoint-camera pairs) give
+    # exact zeros in loc.grad
+    u = p.sampling_loc[..., 0]
+    v = p.sampling_loc[..., 1]
+    outside = ((u < -0.4) | (u > 1.4) | (v < -0.4) | (v > 1.4)).cuda()
+    assert 0.2 < float(outside.double().mean()) < 0.3
+    assert torch.all(loc.grad[outside] == 0)
+    rgf, _, _ = oracle_mod.backward(feat64, p.spatial_shapes, p.level_start_index,
+                                    p.sampling_loc, p.weights, go, need_loc=False, need_w=False)
+    gf = host(feat.grad)
+    assert normwise(gf, rgf) <= BF16_TOL
+    rounded = torch.from_numpy(rgf).float().to(torch.bfloat16).double().numpy()
+    assert normwise(gf, rounded) <= 5e-3
+    assert np.mean(gf == rounded) >= 0.99
+    e_out = float(loss.double())
+    pf = feat.grad.double() * feat.detach().double()
+    pw = w.grad.double() * w.detach().double()
+    assert abs(float(pf.sum()) - e_out) <= 2.0 ** -9 * float(pf.abs().sum()), e_out
+    assert abs(float(pw.sum()) - e_out) <= 1e-5 * float(pw.abs().sum()), e_out
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16, torch.float16],

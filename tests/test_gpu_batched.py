@@ -7,7 +7,7 @@ import pytest
 import torch
 
 from helpers import (BF16_TOL, FWD_F32_MAXREL, FWD_F32_TOL, GRAD_F32_MAXREL, GRAD_F32_TOL,
-                     anchor_subset, assert_close, host, normwise)
+                     anchor_subset, assert_close, host, normwise, oracle_backward_subset)
 from paper_2601_10819_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -159,6 +159,14 @@ def test_batched_full_size_bf16(ops, oracle_mod):
         ref = oracle_mod.forward(feat64, p.spatial_shapes, p.level_start_index,
                                  p.sampling_loc[:, idx].contiguous(), p.weights[:, idx].contiguous())
         assert_close(host(batch.out[s])[idx][None], ref, FWD_F32_TOL, FWD_F32_MAXREL, f"scene {s}")
+        # grad_sampling_loc and grad_weights of the same anchors (per-anchor
+        # quantities) against the oracle's analytic gradient
+        go = batch.grad_out[s].cpu()[None]
+        rgl, rgw = oracle_backward_subset(oracle_mod, feat64, p, idx, go)
+        assert_close(host(batch.grad_loc[s])[idx][None], rgl, GRAD_F32_TOL, GRAD_F32_MAXREL,
+                     f"scene {s} grad_loc")
+        assert_close(host(batch.grad_w[s])[idx][None], rgw, GRAD_F32_TOL, GRAD_F32_MAXREL,
+                     f"scene {s} grad_w")
     for s in range(len(probs)):
         feat, layout, loc, w = scenes[s]
         e_out = float((batch.out[s].double() * batch.grad_out[s].double()).sum())

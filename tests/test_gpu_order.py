@@ -135,3 +135,47 @@ def test_view_order_bf16_full_size_cam64(ops, oracle_mod):
     rgl, rgw = oracle_backward_subset(oracle_mod, feat64, p, idx, go)
     assert_close(host(gl)[:, idx], rgl, GRAD_F32_TOL, GRAD_F32_MAXREL, "cam64 view grad_loc")
     assert_close(host(gw)[:, idx], rgw, GRAD_F32_TOL, GRAD_F32_MAXREL, "cam64 view grad_w")
+
+
+@pytest.mark.parametrize("B,N,A,waves", [(1, 64, 900, 1), (1, 64, 900, 4), (2, 16, 1800, 2),
+                                         (1, 6, 900, 4), (3, 7, 5, 1), (2, 3, 1, 8),
+                                         (1, 1, 3, 2), (2, 9, 37, 4)])
+def test_view_order_counts_every_item_once(ops, B, N, A, waves):
+    """The view-order partition of the (batch item, camera, anchor) items over
+    the XCD slots, checked through the library: channel n of every pixel of
+    camera n is 1 (all other channels 0), every weight is 1 and every
+    location is a pixel centre of the single level, so out[b, a, n] counts
+    the samples of item (b, a, n) that the forward summed -- exactly P for
+    every camera, none dropped or repeated -- and the backward's per-sample
+    grad_w is 1 exactly where the camera's channel lies in the group, its
+    grad_loc the exact one-sided difference."""
+    C, G, P, H, W = 64, 16, 3, 4, 8
+    shapes, starts, R = synth.layout([[(H, W)]] * N)
+    feat = torch.zeros(B, R, C)
+    for n in range(N):
+        feat[:, starts[n, 0]:starts[n, 0] + H * W, n] = 1.0
+    gen = torch.Generator().manual_seed(B * 1000 + N * 10 + A)
+    ix = torch.randint(0, W, (B, A, P, N), generator=gen)
+    iy = torch.randint(0, H, (B, A, P, N), generator=gen)
+    loc = torch.stack([(ix + 0.5) / W, (iy + 0.5) / H], dim=-1)
+    w = torch.ones(B, A, P, N, 1, G)
+    layout = ops.Layout(shapes, starts)
+    tile = {"order": "view", "waves_per_anchor": waves}
+    feat, loc, w = feat.cuda(), loc.cuda(), w.cuda()
+    out = ops.forward(feat, layout, loc, w, tile=tile)
+    go = torch.ones(B, A, C, device="cuda")
+    _, gl, gw = ops.backward(feat, layout, loc, w, go, need_feat=False, tile=tile)
+    torch.cuda.synchronize()
+    want = torch.zeros(B, A, C)
+    want[..., :N] = float(P)
+    assert torch.equal(out.cpu(), want)
+    want_w = torch.zeros(B, A, P, N, 1, G)
+    for n in range(N):
+        want_w[:, :, :, n, 0, n // (C // G)] = 1.0
+    assert torch.equal(gw.cpu(), want_w)
+    # d out / d x at a pixel centre is the right-hand difference of the
+    # camera's constant channel: 0 inside, -W (-H) at the last column (row),
+    # where the right (lower) neighbour is zero padding
+    want_l = torch.stack([torch.where(ix == W - 1, -float(W), 0.0),
+                          torch.where(iy == H - 1, -float(H), 0.0)], dim=-1)
+    assert torch.equal(gl.cpu(), want_l)

@@ -1,7 +1,7 @@
 """The record sort of the deterministic grad_feat reduction (samples' records
 grouped by bilinear cell), through its own entry point: bit-exact against
-numpy's stable argsort and searchsorted, over one to four radix passes,
-ragged tiles, heavy duplicates and already ordered inputs."""
+numpy's stable argsort and searchsorted, over one to four radix passes (keys
+of 1 to 29 bits), ragged tiles, heavy duplicates and already ordered inputs."""
 import numpy as np
 import pytest
 import torch
@@ -19,12 +19,14 @@ CASES = [
     (4095, 7, "uniform"),              # under one tile, one 3-bit pass
     (4097, 1023, "uniform"),           # ragged second tile, one 10-bit pass
     (300_000, 1024, "uniform"),        # 11-bit keys: two 6-bit passes
-    (70_001, 630_000, "uniform"),      # 20-bit keys (the 64-camera cell space): two passes
+    (70_001, 630_000, "uniform"),      # 20-bit keys (the 64-camera cell space): three 7-bit passes
     (200_000, 630_000, "sentinel"),    # most records outside their level (sentinel key)
     (100_000, 630_000, "sorted"),
     (100_000, 630_000, "reversed"),
     (65_536, 630_000, "clustered"),    # runs of equal keys longer than a tile
     (50_000, (1 << 24) - 1, "uniform"),  # three 8-bit passes
+    (100_000, (1 << 25) - 1, "uniform"),  # 25-bit keys: four 7-bit passes
+    (30_000, (1 << 28) + 12_345, "sentinel"),  # 29-bit keys: four 8-bit passes
     (2_995_200, 630_000, "uniform"),   # the 64-camera scene's record count: 732 tiles, 23 bands
     (20_056_660, 4_000_000, "sentinel"),  # the 12-scene batch's: 4,897 tiles, 154 bands
 ]

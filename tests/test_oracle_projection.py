@@ -215,3 +215,51 @@ def test_fused_gradients_by_finite_differences(oracle_mod):
                               p.weights, vis, score)
     e = float((f * go).sum())
     assert abs(float((gf * p.feat.numpy()).sum()) - e) <= 1e-12 * max(1.0, abs(e))
+
+
+def test_fused_grad_loc_by_finite_differences(oracle_mod):
+    """grad_sampling_loc of the fusion (Sec. 3.2, Eq. 2) against central
+    differences of <grad_out, f> in FP64, at coordinates at least 1e-3 px
+    from every grid line of the camera's levels (so the step stays inside one
+    bilinear cell); coordinates of invisible pairs have an exactly zero
+    gradient and no effect on f."""
+    p, vis, score = fused_case()
+    go = synth.grad_out_like(p, seed=7).numpy().astype(np.float64)
+    _, gl, _, _ = proj.backward_fused(p.feat, p.spatial_shapes, p.level_start_index,
+                                      p.sampling_loc, p.weights, vis, score, go)
+    loc0 = p.sampling_loc.numpy().astype(np.float64)
+    shapes = p.spatial_shapes.numpy()
+
+    def loss(loc):
+        f, _ = proj.forward_fused(p.feat, p.spatial_shapes, p.level_start_index, loc, p.weights,
+                                  vis, score)
+        return float((f * go).sum())
+
+    def clear_of_grid(b, a, pp, n, k):
+        # x = u*W - 0.5 (k = 0) or y = v*H - 0.5 (k = 1) at every level
+        size = shapes[n, :, 1 - k].astype(np.float64)
+        t = loc0[b, a, pp, n, k] * size - 0.5
+        return bool(np.all(np.abs(t - np.round(t)) >= 1e-3))
+
+    h = 1e-7
+    rng = np.random.default_rng(9)
+    checked_vis = checked_invis = 0
+    B, A, P, N = loc0.shape[:4]
+    for _ in range(400):
+        idx = tuple(int(rng.integers(0, s)) for s in (B, A, P, N, 2))
+        if not clear_of_grid(*idx):
+            continue
+        d = np.zeros_like(loc0)
+        d[idx] = h
+        fd = (loss(loc0 + d) - loss(loc0 - d)) / (2 * h)
+        if vis[idx[:2] + (idx[3],)]:
+            assert abs(fd - gl[idx]) <= 1e-6 * max(1.0, abs(fd)), (idx, fd, gl[idx])
+            checked_vis += 1
+        else:
+            assert gl[idx] == 0.0 and fd == 0.0, (idx, fd, gl[idx])
+            checked_invis += 1
+        if checked_vis >= 12 and checked_invis >= 3:
+            break
+    assert checked_vis >= 12 and checked_invis >= 3
+    # a nonzero gradient somewhere, so the comparison above is not vacuous
+    assert np.abs(gl).max() > 1e-3
