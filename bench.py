@@ -47,23 +47,57 @@ def parse():
                     help="skip the steps with weights generated from logits")
     ap.add_argument("--no-visible", action="store_true",
                     help="skip the projection + visible-view steps (outside-in camera network)")
+    ap.add_argument("--no-autograd", action="store_true",
+                    help="skip the 16-camera training step through the autograd Function")
     ap.add_argument("--cpu-anchors", type=int, default=0,
                     help="anchors in the oracle's timed sample (0 = all of them)")
     return ap.parse_args()
 
 
 def bytes_per_sample(C, G, L, P, N, s):
-    """Algorithmic bytes one sample moves, per pass (the method's own traffic,
-    independent of the implementation): 4 corner rows of C elements of s bytes,
-    the sample's G weights, its share of the location (shared by L levels) and
-    of the anchor's output row (shared by P*N*L samples). The backward re-reads
-    the corners, scatters 4 corner contributions at the feature's precision,
-    reads weights and writes their gradient, reads the location and writes its
-    gradient, and reads grad_out."""
+    """Bytes one sample accesses, per pass, counting every corner access (the
+    effective gather traffic: caches serve most re-reads, so this is not HBM
+    traffic): 4 corner rows of C elements of s bytes, the sample's G weights,
+    its share of the location (shared by L levels) and of the anchor's output
+    row (shared by P*N*L samples). The backward re-reads the corners, scatters
+    4 corner contributions at the feature's precision, reads weights and
+    writes their gradient, reads the location and writes its gradient, and
+    reads grad_out."""
     share_out = C * 4.0 / (P * N * L)
     fwd = 4 * C * s + G * 4 + 8.0 / L + share_out
     bwd = 4 * C * s + 4 * C * s + 2 * G * 4 + 2 * 8.0 / L + share_out
     return fwd, bwd
+
+
+def footprint_bytes(p, s):
+    """Unique bytes each pass must move through HBM at least (every tensor
+    read or written once): the HBM roofline's algorithmic bytes. Per unit:
+    s bytes per feature element (B*R*C of them), 4*G per sample for the
+    weights (and 4*G for grad_weights), 8 per (anchor, keypoint, camera)
+    for the location (and 8 for its gradient), 4*C per anchor for out or
+    grad_out. By kernel: the forward gather reads feat, weights and locations
+    and writes out; the backward gather reads feat, weights, locations and
+    grad_out and writes grad_weights and grad_sampling_loc; the grad_feat
+    reduction reads weights and grad_out and writes grad_feat."""
+    B, A, P, N, L = p.batch, p.num_anchors, p.num_points, p.num_cams, p.num_levels
+    C, G = p.channels, p.groups
+    S = B * A * P * N * L
+    feat = B * int(p.rows) * C * s
+    w = S * G * 4
+    loc = B * A * P * N * 8
+    row = B * A * C * 4
+    terms = {
+        "fwd": {"feat": feat, "weights": w, "loc": loc, "out": row},
+        "bwd_gather": {"feat": feat, "weights": w, "grad_weights": w, "loc": loc,
+                       "grad_loc": loc, "grad_out": row},
+        "gfeat": {"grad_feat": feat, "weights": w, "grad_out": row},
+    }
+    return {k: (sum(v.values()), v) for k, v in terms.items()}
+
+
+KERNEL_PASS = {"msda_fwd_kernel": "fwd", "msda_fwd_view_kernel": "fwd",
+               "msda_bwd_kernel": "bwd_gather", "msda_bwd_view_kernel": "bwd_gather",
+               "gfeat_tile_kernel": "gfeat", "gfeat_tile_kernel_coarse": "gfeat"}
 
 
 class HipEvents:
@@ -111,17 +145,17 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel: str, workload: str, dtype: str):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources (else None)."""
+    """(HBM bytes per launch, L2 hit rate) from a committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources (else None, None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         table = json.load(open(path))
     except (OSError, ValueError):
-        return None
+        return None, None
     ent = table.get(f"{kernel}/{workload}/{dtype}")
     if not ent or ent.get("source_hash") != kernel_source_hash():
-        return None
-    return ent.get("hbm_bytes_per_launch")
+        return None, None
+    return ent.get("hbm_bytes_per_launch"), ent.get("l2_hit_rate")
 
 
 def run_gpu(args, torch, ops, synth, p, feat_dtype, steps, warmup, cold=False, weights=None,
@@ -417,6 +451,59 @@ def run_visible(torch, ops, synth, p, steps, warmup, fused=False):
     }
 
 
+def run_autograd(torch, ops, synth, steps, warmup):
+    """The outside-in training step of the 16-camera workload (B = 2, 4
+    levels from 384x640, C = 256 in 8 groups, 1800 anchors x 13 keypoints,
+    BF16 features, FP32 locations and weights, 25% of keypoints outside each
+    camera's view) through the autograd Function: out = msda(feat, loc, w),
+    then out.backward(grad_out), the leaves' .grad cleared (set to None)
+    before each step as an optimizer's zero_grad does. Wall clock over the
+    steps; stream events split each step's forward and backward."""
+    p = synth.train16()
+    dev = "cuda"
+    feat = p.feat.to(torch.bfloat16).to(dev).requires_grad_(True)
+    loc = p.sampling_loc.to(dev).requires_grad_(True)
+    w = p.weights.to(dev).requires_grad_(True)
+    layout = ops.Layout(p.spatial_shapes, p.level_start_index, dev)
+    go = synth.grad_out_like(p, seed=1).to(dev)
+    ev = HipEvents()
+
+    def step(marks=None):
+        feat.grad = loc.grad = w.grad = None
+        if marks:
+            ev.record(marks[0])
+        out = ops.msda(feat, layout, loc, w)
+        if marks:
+            ev.record(marks[1])
+        out.backward(go)
+        if marks:
+            ev.record(marks[2])
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    marks = [(ev.create(), ev.create(), ev.create()) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for m in marks:
+        step(m)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = [ev.elapsed_ms(a, c) for a, _, c in marks]
+    fw = [ev.elapsed_ms(a, b) for a, b, _ in marks]
+    for m in marks:
+        for e in m:
+            ev.destroy(e)
+    S = p.samples
+    ms = (t1 - t0) / steps * 1e3
+    return {"workload": p.name, "batch": p.batch, "cameras": p.num_cams,
+            "anchors": p.num_anchors, "samples_per_step": S,
+            "ms_per_step": round(ms, 4), "value": round(S / (ms * 1e-3) / 1e9, 4),
+            "unit": "GSamples/s", "step_ms": pct(st), "fwd_ms": pct(fw),
+            "bwd_ms": pct([a - b for a, b in zip(st, fw)]),
+            "note": "BF16 features; torch.autograd.Function forward + backward (all three "
+                    "gradients), grads set to None before each step"}
+
+
 def copy_bandwidth(torch, ops, nbytes=1 << 30, reps=10):
     """Achievable streaming bandwidth (read + write) of the library's copy kernel."""
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -455,6 +542,37 @@ def cpu_baseline(p, anchors, min_seconds=10.0, max_reps=20):
     return samples * reps / dt / 1e9, dt, oracle.num_threads(), samples, reps
 
 
+def cpu_baselines(synth, min_seconds=3.0, max_reps=50):
+    """The FP64 oracle (as it stands) on the smaller workloads, in full:
+    forward alone and forward + full backward, each repeated until about
+    `min_seconds` have been measured. A baseline only."""
+    import numpy as np
+    import oracle
+    oracle._load()
+    res = {}
+    for maker in (synth.tiny, lambda: synth.sparse4d(seed=0), synth.train16):
+        p = maker()
+        feat = p.feat.double().numpy()
+        go = np.random.default_rng(0).standard_normal((p.batch, p.num_anchors, p.channels))
+        row = {"samples": p.samples}
+        for name in ("fwd", "fwd_bwd"):
+            reps, dt = 0, 0.0
+            while reps < max_reps and (reps == 0 or dt < min_seconds):
+                t0 = time.perf_counter()
+                oracle.forward(feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                               p.weights)
+                if name == "fwd_bwd":
+                    oracle.backward(feat, p.spatial_shapes, p.level_start_index, p.sampling_loc,
+                                    p.weights, go)
+                dt += time.perf_counter() - t0
+                reps += 1
+            row[name + "_s"] = round(dt / reps, 5)
+            row[name + "_GSamples_per_s"] = round(p.samples * reps / dt / 1e9, 6)
+        res[p.name] = row
+    res["cores"] = oracle.num_threads()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -491,20 +609,20 @@ def main():
 
     C, G, L, P, N = p.channels, p.groups, p.num_levels, p.num_points, p.num_cams
     fwd_b, bwd_b = bytes_per_sample(C, G, L, P, N, 2)
-    # roofline of the dominant kernel (largest time per step); its algorithmic
-    # bytes are the pass's per-sample bytes times the samples of one launch
+    # roofline of the dominant kernel (largest time per step): its
+    # algorithmic bytes are the unique bytes its pass must move through HBM
+    # (footprint_bytes), over its average launch duration in the timed region
     ks = bf["kernels"]
     kern = bf["timed_kernel"]["name"]
     kms = bf["timed_kernel"]["ms"]
-    gather_bwd = bwd_b - 4 * C * 2
-    alg_per_sample = {"msda_fwd_kernel": fwd_b, "msda_fwd_view_kernel": fwd_b,
-                      # the backward's gather kernel: re-gather, weights + grad_w,
-                      # loc + grad_loc, grad_out; the grad_feat scatter bytes are
-                      # charged to the tiled grad_feat reduction
-                      "msda_bwd_kernel": gather_bwd, "msda_bwd_view_kernel": gather_bwd}.get(kern)
-    kbytes = S * alg_per_sample if alg_per_sample else None
+    fpb = footprint_bytes(p, 2)
+    kpass = KERNEL_PASS.get(kern)
+    kbytes, kterms = fpb[kpass] if kpass else (None, None)
     achieved = kbytes / (kms * 1e-3) / 1e9 if kbytes else None
-    traffic = measured_traffic(kern, p.name, "bf16")
+    traffic, l2hit = measured_traffic(kern, p.name, "bf16")
+    # the same launch counted per corner access (every re-read included)
+    per_access = {"fwd": fwd_b, "bwd_gather": bwd_b - 4 * C * 2, "gfeat": 4 * C * 2}.get(kpass)
+    step_fp = fpb["fwd"][0] + fpb["bwd_gather"][0] + fpb["gfeat"][0]
 
     res = {
         "metric": "MSDA fwd+bwd GSamples/s (64-camera scene, BF16 storage, FP32 math)",
@@ -530,13 +648,26 @@ def main():
         "kernels_note": (f"average per launch from {bf['probe_steps']} instrumented steps outside "
                          "the timed region (an event pair around every launch); inside it only "
                          "the roofline kernel is bracketed"),
-        "alg_hbm_frac_fwd_bwd": round(S * (fwd_b + bwd_b) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "headline_note": ("value: K back-to-back steps (warm caches) on the wall clock; "
+                          "cold.value: the same step with L2 and the memory-side cache "
+                          "evicted before each step (event-timed median)"),
+        # the whole step's unique bytes (each tensor once per pass) per step
+        # time, against HBM peak; and its bytes counted per corner access
+        # (caches serve re-reads, so that rate is not bounded by HBM)
+        "footprint_hbm_frac_fwd_bwd": round(step_fp / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "effective_access_TBps_fwd_bwd": round(S * (fwd_b + bwd_b) / (ms_step * 1e-3) / 1e12, 3),
         "roofline": {"bound": "hbm", "kernel": kern,
                      "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": traffic, "alg_bytes_per_launch": int(kbytes) if kbytes else None,
-                     "avg_launch_ms": round(kms, 4)},
+                     "traffic": traffic,
+                     "alg_bytes_per_launch": int(kbytes) if kbytes else None,
+                     "alg_bytes_terms": kterms,
+                     "avg_launch_ms": round(kms, 4),
+                     "traffic_GBps": round(traffic / (kms * 1e-3) / 1e9, 1) if traffic else None,
+                     "l2_hit_rate": l2hit,
+                     "effective_gather_GBps": (round(S * per_access / (kms * 1e-3) / 1e9, 1)
+                                               if per_access else None)},
     }
     if "cold_ms" in bf:
         res["cold"] = {"ms_per_step": bf["cold_ms"],
@@ -588,6 +719,9 @@ def main():
     if not args.no_batched:
         res["batched"] = run_batched(torch, ops, synth, args.steps, args.warmup)
         print(f"# batched done: {res['batched']}", file=sys.stderr, flush=True)
+    if not args.no_autograd:
+        res["autograd_train16"] = run_autograd(torch, ops, synth, args.steps, args.warmup)
+        print(f"# autograd done: {res['autograd_train16']}", file=sys.stderr, flush=True)
     res["copy_GBps"] = round(copy_bandwidth(torch, ops), 1)
 
     if not args.no_cpu:
@@ -597,6 +731,7 @@ def main():
                                "kind": "oracle",
                                "sample": f"{p.name} anchors[0:{anchors}] ({ns} samples), FP64 "
                                          f"forward + full backward, {reps} runs in {dt:.1f} s"}
+        res["cpu_baseline_configs"] = cpu_baselines(synth)
     print(json.dumps(res), flush=True)
 
 
