@@ -307,7 +307,9 @@ size_t msda_backward_fused_workspace_size(const msda_desc* desc);
  * (1 when the level is all zero), code = round-to-nearest-even(clamp(x /
  * scale_l, -448, 448)) in OCP e4m3fn. Rows in no region are written as 0.
  * feat_f32 [B][R][C] device; codes [B][R][C] uint8 device; level_scale [L]
- * FP32 device (written). workspace: device, >= msda_quantize_workspace_size.
+ * FP32 device (written). workspace: device, 4-byte aligned, >=
+ * msda_quantize_workspace_size (4 bytes per (batch item, camera, level):
+ * each region's running maximum), contents not kept.
  */
 msda_status msda_quantize_fp8(const float* feat_f32, const int32_t* spatial_shapes,
                               const int32_t* level_start_index, uint8_t* codes,

@@ -973,7 +973,8 @@ msda_status msda_project_keypoints(const float* anchors, const float* keypoints,
 }
 
 size_t msda_quantize_workspace_size(const msda_desc* d) {
-    return d ? (size_t)(d->num_levels > 0 ? d->num_levels : 0) * sizeof(uint32_t) : 0;
+    if (!d || d->batch < 1 || d->num_cams < 1 || d->num_levels < 1) return 0;
+    return (size_t)d->batch * (size_t)d->num_cams * (size_t)d->num_levels * sizeof(uint32_t);
 }
 
 msda_status msda_quantize_fp8(const float* feat_f32, const int32_t* spatial_shapes,
@@ -994,11 +995,31 @@ msda_status msda_quantize_fp8(const float* feat_f32, const int32_t* spatial_shap
     if (!aligned(workspace, 4)) return fail(MSDA_ERR_WORKSPACE, "workspace must be 4-byte aligned");
     if (!aligned(codes, 4)) return fail(MSDA_ERR_INVALID_ARGUMENT, "codes must be 4-byte aligned");
     const hipStream_t s = (hipStream_t)stream;
-    // rows in no region read as code 0
-    hipError_t e = msda::launch_fill_zero(codes, (size_t)d.batch * d.rows * d.channels, s);
-    if (e != hipSuccess) return hip_fail(e, "zero codes");
+    // Rows in no region read as code 0: zero the codes first unless the
+    // regions tile [0, R) exactly (disjoint, no gaps).
+    const int64_t NL = (int64_t)d.num_cams * d.num_levels;
+    std::vector<std::pair<int64_t, int64_t>> spans((size_t)NL);
+    int64_t max_rows = 0;
+    for (int64_t i = 0; i < NL; ++i) {
+        const int64_t n = (int64_t)d.host_spatial_shapes[2 * i] * d.host_spatial_shapes[2 * i + 1];
+        spans[(size_t)i] = {d.host_level_start_index[i], n};
+        max_rows = std::max(max_rows, n);
+    }
+    std::sort(spans.begin(), spans.end());
+    int64_t end = 0;
+    bool tiled = true;
+    for (const auto& sp : spans) {
+        if (sp.first != end) { tiled = false; break; }
+        end = sp.first + sp.second;
+    }
+    tiled = tiled && end == d.rows;
+    hipError_t e = hipSuccess;
+    if (!tiled) {
+        e = msda::launch_fill_zero(codes, (size_t)d.batch * d.rows * d.channels, s);
+        if (e != hipSuccess) return hip_fail(e, "zero codes");
+    }
     e = msda::launch_quantize_fp8(feat_f32, spatial_shapes, level_start_index, d.batch,
-                                  d.num_cams, d.num_levels, d.rows, d.channels, codes,
+                                  d.num_cams, d.num_levels, d.rows, d.channels, max_rows, codes,
                                   level_scale, static_cast<uint32_t*>(workspace), s);
     if (e != hipSuccess) return hip_fail(e, "msda_quantize_fp8 launch");
     return ok();

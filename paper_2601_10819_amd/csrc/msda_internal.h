@@ -284,10 +284,11 @@ hipError_t launch_gfeat_tiles_batched(const BatchArgs& b, int out_dtype, int cpl
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, size_t n, hipStream_t s);
 hipError_t launch_f32_to_f16(const float* src, uint16_t* dst, size_t n, hipStream_t s);
+// max_region_rows: the largest H*W over the regions (sizes the grid).
 hipError_t launch_quantize_fp8(const float* x, const int32_t* shapes, const int32_t* starts,
                                int32_t B, int32_t N, int32_t L, int64_t R, int32_t C,
-                               uint8_t* codes, float* level_scale, uint32_t* amax_ws,
-                               hipStream_t s);
+                               int64_t max_region_rows, uint8_t* codes, float* level_scale,
+                               uint32_t* amax_ws, hipStream_t s);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // LDS bytes of a forward/backward launch: geometry table + per-wave staging

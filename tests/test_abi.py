@@ -192,7 +192,10 @@ def test_stream_copy_validation(lib):
 def test_quantize_validation(lib):
     d = desc(Geo(), C=64)
     ws = lib.msda_quantize_workspace_size(ctypes.byref(d))
-    assert ws == 2 * 4
+    assert ws == 2 * 2 * 4                     # one word per (camera, level) region
+    assert lib.msda_quantize_workspace_size(ctypes.byref(desc(Geo(), B=3, C=64))) == 3 * 2 * 2 * 4
+    expect(lib, lib.msda_quantize_fp8(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, ws - 4, ctypes.byref(d),
+                                      None), WS)
     expect(lib, lib.msda_quantize_fp8(FAKE, FAKE, FAKE, FAKE, FAKE, None, 0, ctypes.byref(d), None),
            WS)
     g = Geo()

@@ -132,6 +132,91 @@ def test_fp8_quantiser_bit_exact(ops, oracle_mod):
     assert np.array_equal(codes.cpu().numpy(), rcodes)
 
 
+def test_fp8_quantiser_bit_exact_cam64(ops, oracle_mod):
+    """The benchmarked 64-camera pyramid (64 x 4 regions, C = 256): the
+    vector path over regions of 8 to 7,168 rows, bit-exact."""
+    p = synth.cam64(seed=0, anchors=1)
+    layout = ops.Layout(p.spatial_shapes, p.level_start_index)
+    codes, scales = ops.quantize_fp8(p.feat.cuda(), layout)
+    torch.cuda.synchronize()
+    rcodes, rscales = oracle_mod.quantize_fp8_per_level(p.feat, p.spatial_shapes,
+                                                         p.level_start_index)
+    assert np.array_equal(scales.cpu().numpy(), rscales)
+    assert np.array_equal(codes.cpu().numpy(), rcodes)
+
+
+def test_fp8_quantiser_rounding_boundaries(ops, oracle_mod):
+    """The encoder's rounding at every boundary of the format. A level whose
+    largest |x| is 448 has scale 1, so each value reaches the encoder
+    unchanged: every finite e4m3 value, every midpoint between neighbours
+    (ties go to the even code), the FP32 neighbours of each midpoint, both
+    signs, and tiny values below the smallest subnormal (2^-9)."""
+    pos = np.sort(oracle_mod.decode_e4m3(np.arange(0, 0x7F, dtype=np.uint8))).astype(np.float32)
+    mids = ((pos[:-1].astype(np.float64) + pos[1:]) / 2).astype(np.float32)
+    vals = np.concatenate([pos, mids, np.nextafter(mids, np.float32(np.inf)),
+                           np.nextafter(mids, np.float32(0)),
+                           np.float32([1e-30, 2.0 ** -11, 2.0 ** -10, 3 * 2.0 ** -11, 448.0])])
+    vals = np.concatenate([vals, -vals]).astype(np.float32)
+    C = 64
+    rows = (len(vals) + C - 1) // C
+    flat = np.zeros(rows * C, dtype=np.float32)
+    flat[:len(vals)] = vals
+    feat = torch.from_numpy(flat.reshape(1, rows, C).copy())
+    shapes = torch.tensor([[[1, rows]]], dtype=torch.int32)
+    starts = torch.zeros(1, 1, dtype=torch.int32)
+    layout = ops.Layout(shapes, starts)
+    codes, scales = ops.quantize_fp8(feat.cuda(), layout)
+    torch.cuda.synchronize()
+    assert float(scales[0]) == 1.0
+    rcodes, rscales = oracle_mod.quantize_fp8_per_level(feat, shapes, starts)
+    assert rscales[0] == 1.0
+    got, want = codes.cpu().numpy().reshape(-1), rcodes.reshape(-1)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, [(float(flat[i]), int(got[i]), int(want[i])) for i in bad[:8]]
+
+
+@pytest.mark.parametrize("C", [6, 20, 256])
+def test_fp8_quantiser_ragged(ops, oracle_mod, C):
+    """Two batch items, regions in a permuted order with unused rows between
+    them (their codes must be 0), a level whose values are all zero (scale
+    1), values far beyond 448 x scale in one level, and C = 6 (the scalar
+    path) beside C = 20 and 256 (the vector path)."""
+    shapes = torch.tensor([[[5, 7], [3, 4], [1, 1]], [[2, 9], [4, 4], [1, 1]]], dtype=torch.int32)
+    starts = torch.tensor([[20, 3, 90], [100, 60, 80]], dtype=torch.int32)
+    R = 130
+    g = torch.Generator().manual_seed(5)
+    feat = torch.randn(2, R, C, generator=g)
+    feat[:, 90] = 0.0
+    feat[:, 80] = 0.0                                      # level 2 all zero
+    feat[1, 61, :3] = torch.tensor([3e4, -5e-7, 1e-30])    # level 1: wide range
+    layout = ops.Layout(shapes, starts)
+    dev = feat.cuda()
+    codes, scales = ops.quantize_fp8(dev, layout)
+    torch.cuda.synchronize()
+    rcodes, rscales = oracle_mod.quantize_fp8_per_level(feat, shapes, starts)
+    assert rscales[2] == 1.0
+    assert np.array_equal(scales.cpu().numpy(), rscales)
+    assert np.array_equal(codes.cpu().numpy(), rcodes)
+    # codes of unused rows are zero even over a buffer that held other bytes
+    codes2 = torch.full_like(codes, 0x5A)
+    lib = ops._lib.load()
+    d = ops._lib.MsdaDesc()
+    d.batch, d.num_cams, d.num_levels = 2, 2, 3
+    d.num_anchors, d.num_points, d.channels, d.groups = 0, 1, C, 1
+    d.feat_dtype, d.rows = ops._lib.MSDA_F32, R
+    d.host_spatial_shapes = layout.host_shapes.ctypes.data
+    d.host_level_start_index = layout.host_starts.ctypes.data
+    ws = torch.empty(64, dtype=torch.uint8, device="cuda")
+    sc2 = torch.empty(3, dtype=torch.float32, device="cuda")
+    import ctypes
+    ops._lib.check(lib.msda_quantize_fp8(dev.data_ptr(), layout.shapes.data_ptr(),
+                                         layout.starts.data_ptr(), codes2.data_ptr(),
+                                         sc2.data_ptr(), ws.data_ptr(), ws.numel(),
+                                         ctypes.byref(d), ops._stream()))
+    torch.cuda.synchronize()
+    assert np.array_equal(codes2.cpu().numpy(), rcodes)
+
+
 def test_fp8_decode_all_codes(ops, oracle_mod):
     """Every e4m3 code through the forward kernel at exact pixel centres
     (one channel group per code byte): out = decode(code) * scale exactly."""
