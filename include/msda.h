@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define MSDA_ABI_VERSION 6
+#define MSDA_ABI_VERSION 7
 
 typedef enum msda_status {
     MSDA_OK = 0,
@@ -173,6 +173,29 @@ msda_status msda_forward_ws(const void* feat, const int32_t* spatial_shapes,
  * the forward runs in view order (chosen or requested), plus B*A*G*8 (the
  * softmax statistics) with MSDA_WEIGHT_LOGITS, each part rounded up to 256. */
 size_t msda_forward_workspace_size(const msda_desc* desc);
+
+/*
+ * msda_forward_ws without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, serving loops and
+ * harnesses that forbid hipMalloc. Same operator, arguments, results and
+ * errors as msda_forward_ws (bitwise the same output for the same desc); it
+ * calls no allocating routine. The workspace lives in a fixed device array
+ * of MSDA_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs
+ * on until the process ends (looked up on the first call on that device).
+ * Every call on one GPU shares that array and leaves its contents behind:
+ * calls that overlap on one GPU (on two streams, or from two threads without
+ * ordering) race and may return wrong results; order them on one stream.
+ * Returns MSDA_ERR_UNSUPPORTED, before any HIP call, when
+ * msda_forward_workspace_size(desc) exceeds MSDA_NOALLOC_SCRATCH_BYTES (for
+ * the view order: B*A*C > 1,048,576 less the statistics' share; the anchor
+ * order, msda_tile.order = MSDA_ORDER_ANCHOR, needs none), MSDA_ERR_HIP if
+ * the device or the array cannot be looked up.
+ */
+#define MSDA_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+msda_status msda_forward_noalloc(const void* feat, const int32_t* spatial_shapes,
+                                 const int32_t* level_start_index, const float* sampling_loc,
+                                 const float* weights, float* out, const msda_desc* desc,
+                                 void* stream);
 
 /*
  * Backward: gradients of <grad_out, out> with respect to feat, sampling_loc

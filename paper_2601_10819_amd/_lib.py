@@ -28,11 +28,12 @@ MSDA_DETERMINISTIC = 1
 MSDA_WEIGHT_LOGITS = 2
 MSDA_WEIGHTS_BF16 = 4
 
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 # Every symbol include/msda.h declares.
 EXPORTS = (
-    "msda_forward", "msda_forward_ws", "msda_forward_workspace_size", "msda_backward",
+    "msda_forward", "msda_forward_ws", "msda_forward_workspace_size", "msda_forward_noalloc",
+    "msda_backward",
     "msda_backward_workspace_size", "msda_project_keypoints", "msda_forward_visible",
     "msda_forward_visible_workspace_size", "msda_backward_visible",
     "msda_backward_visible_workspace_size", "msda_forward_fused",
@@ -127,6 +128,8 @@ def load(path: str = LIB_PATH):
     lib.msda_forward_ws.restype = ctypes.c_int
     lib.msda_forward_workspace_size.argtypes = [dp]
     lib.msda_forward_workspace_size.restype = sz
+    lib.msda_forward_noalloc.argtypes = [vp] * 6 + [dp, vp]
+    lib.msda_forward_noalloc.restype = ctypes.c_int
     lib.msda_project_keypoints.argtypes = [vp] * 6 + [ctypes.POINTER(MsdaProjDesc), vp]
     lib.msda_project_keypoints.restype = ctypes.c_int
     lib.msda_forward_visible.argtypes = [vp] * 8 + [sz, dp, vp]

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmsda.so")
 SOURCES = [os.path.join(CSRC, f) for f in
            ("msda_fwd.hip", "msda_bwd.hip", "msda_tiles.hip", "msda_sort.hip", "msda_batch.hip",
-            "msda_util.hip", "msda_vis.hip", "msda_softmax.hip",
+            "msda_util.hip", "msda_vis.hip", "msda_softmax.hip", "msda_noalloc.hip",
             "msda_api.cpp")]
 HEADERS = [os.path.join(CSRC, "msda_internal.h"), os.path.join(CSRC, "msda_common.h"),
            os.path.join(CSRC, "msda_gather.h"),

@@ -336,6 +336,11 @@ void divmagic(uint32_t d, uint64_t* m, int* shift) {
 
 namespace msda {
 
+msda_status set_error(msda_status st, const char* message) {
+    g_error = message ? message : "";
+    return st;
+}
+
 void mark_begin(const char* kernel, hipStream_t s) {
     g_event_open = false;
     if (!g_events || g_event_used >= g_event_cap) return;

@@ -300,6 +300,9 @@ int max_pairs_per_chunk(int L, int G);
 
 // Benchmark instrumentation (msda_set_kernel_events): called around every
 // kernel launch; records the caller's events when enabled, else does nothing.
+// Sets the thread's last-error message (msda_last_error) and returns st.
+msda_status set_error(msda_status st, const char* message);
+
 void mark_begin(const char* kernel, hipStream_t s);
 void mark_end(hipStream_t s);
 

@@ -189,6 +189,28 @@ def forward(feat, layout: Layout, sampling_loc, weights, level_scale=None, tile=
     return out
 
 
+def forward_noalloc(feat, layout: Layout, sampling_loc, weights, out: torch.Tensor,
+                    level_scale=None, tile=None, stream=None, logits: bool = False
+                    ) -> torch.Tensor:
+    """forward() through msda_forward_noalloc: no workspace; the library's
+    fixed per-GPU scratch array holds the view order's partial sums. `out`
+    [B, A, C] FP32 is given by the caller (nothing is allocated here)."""
+    lib = _lib.load()
+    _need_cuda_contig("feat", feat)
+    _need_cuda_contig("sampling_loc", sampling_loc, torch.float32)
+    _need_weights(weights)
+    _need_cuda_contig("out", out, torch.float32)
+    if level_scale is not None:
+        _need_cuda_contig("level_scale", level_scale, torch.float32)
+    d = make_desc(feat, layout, sampling_loc, weights, level_scale, tile=tile, logits=logits)
+    if tuple(out.shape) != (d.batch, d.num_anchors, d.channels):
+        raise ValueError(f"out must be [{d.batch}, {d.num_anchors}, {d.channels}]")
+    _lib.check(lib.msda_forward_noalloc(_ptr(feat), _ptr(layout.shapes), _ptr(layout.starts),
+                                        _ptr(sampling_loc), _ptr(weights), _ptr(out),
+                                        ctypes.byref(d), _stream(stream)))
+    return out
+
+
 def backward_workspace_bytes(feat, layout, sampling_loc, weights, deterministic=False,
                              tile=None, logits=False) -> int:
     d = make_desc(feat, layout, sampling_loc, weights, deterministic=deterministic, tile=tile,

@@ -204,6 +204,20 @@ def test_quantize_validation(lib):
                                       ctypes.byref(desc(g, C=64)), None), INV, "outside")
 
 
+def test_noalloc_refuses_oversize_before_any_hip_call(lib):
+    """msda_forward_noalloc checks the workspace it would need against its
+    fixed scratch array first, so on a machine without a GPU an input too
+    large is refused by size, not by the failed device lookup."""
+    expect(lib, lib.msda_forward_noalloc(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None, None), INV)
+    d = desc(Geo(ncam=8), A=4200, C=256, G=8, dtype=_lib.MSDA_BF16)
+    need = lib.msda_forward_workspace_size(ctypes.byref(d))
+    assert need == 8 * 4200 * 256 * 4 > (32 << 20)
+    expect(lib, lib.msda_forward_noalloc(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(d),
+                                         None), UNS, "scratch")
+    d = desc(Geo(ncam=8), A=4096, C=256, G=8, dtype=_lib.MSDA_BF16)
+    assert lib.msda_forward_workspace_size(ctypes.byref(d)) == 32 << 20   # fits exactly
+
+
 def test_python_binding_fails_loudly_without_library(tmp_path):
     import importlib
     mod = importlib.import_module("paper_2601_10819_amd._lib")
