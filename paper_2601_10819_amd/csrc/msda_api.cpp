@@ -263,12 +263,16 @@ SortedWs sorted_layout(uint64_t nrec, uint64_t ncells, uint64_t nregions) {
 }
 
 // Cells and 4x4 tiles of one batch item (from the host mirror of the shapes).
-void cells_and_tiles(const msda_desc* d, uint64_t* cells, uint64_t* tiles) {
+// outside_cell: each region's cells are its (H+1)(W+1) bilinear cells and
+// one more for its samples outside the level (the single call's numbering,
+// region_tables_kernel); the batched form numbers (H+1)(W+1) per region.
+void cells_and_tiles(const msda_desc* d, uint64_t* cells, uint64_t* tiles,
+                     bool outside_cell = true) {
     *cells = *tiles = 0;
     const int64_t NL = (int64_t)d->num_cams * d->num_levels;
     for (int64_t i = 0; i < NL; ++i) {
         const uint64_t H = d->host_spatial_shapes[2 * i], W = d->host_spatial_shapes[2 * i + 1];
-        *cells += (H + 1) * (W + 1);
+        *cells += (H + 1) * (W + 1) + (outside_cell ? 1 : 0);
         *tiles += ((H + msda::kTileH - 1) / msda::kTileH) * ((W + msda::kTileW - 1) / msda::kTileW);
     }
 }
@@ -502,6 +506,31 @@ VisibleWs visible_layout(const msda_desc* d, size_t at) {
     return w;
 }
 
+// Whether the dense backward's records fit the per-bucket LDS sort: A*P
+// records per (batch item, region) bucket, every region's local keys within
+// the composite key, and the bucket's LDS within the device's per-block
+// limit (looked up once per device; no bucket sort if that fails).
+static bool bucket_sort_fits(const msda_desc* d) {
+    const uint64_t ap = (uint64_t)d->num_anchors * (uint64_t)d->num_points;
+    if (ap == 0 || ap > msda::kBucketMaxRecords) return false;
+    const int64_t NL = (int64_t)d->num_cams * d->num_levels;
+    for (int64_t i = 0; i < NL; ++i) {
+        const uint64_t H = d->host_spatial_shapes[2 * i], W = d->host_spatial_shapes[2 * i + 1];
+        if ((H + 1) * (W + 1) + 1 > msda::kBucketMaxKeys) return false;
+    }
+    static int max_lds[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+    if (max_lds[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess || v <= 0)
+            v = -1;
+        max_lds[dev] = v;
+    }
+    return max_lds[dev] > 0 && msda::bucket_sort_lds_bytes((uint32_t)ap) <= (size_t)max_lds[dev];
+}
+
 // The backward's workspace without the weight flags' part.
 static size_t base_backward_bytes(const msda_desc* d) {
     if (!d || d->batch < 1 || d->rows < 1 || d->channels < 1 || d->num_anchors < 0) return 0;
@@ -690,6 +719,9 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
         a.cell_offset = 0;
         a.no_cell = (uint32_t)ncells;
         a.sample_offset = 0;
+        // dense records sorted per (batch item, region) bucket in LDS when
+        // the buckets fit, else the global radix sort
+        if (!visible && bucket_sort_fits(desc)) a.rec_bucket_ap = (uint32_t)(a.A * a.P);
         // rows outside every region are not visited by a tile
         if (!cover && (e = msda::launch_fill_zero(grad_feat, gf_bytes, s)) != hipSuccess)
             return hip_fail(e, "zero grad_feat");
@@ -743,12 +775,19 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
 
     uint32_t* sorted = nullptr;
     uint32_t* off = reinterpret_cast<uint32_t*>(ws + W.off);
-    e = msda::launch_sort_records(reinterpret_cast<uint32_t*>(ws + W.keys_a),
-                                  reinterpret_cast<uint32_t*>(ws + W.keys_b),
-                                  reinterpret_cast<uint32_t*>(ws + W.vals_a),
-                                  reinterpret_cast<uint32_t*>(ws + W.vals_b), (uint32_t)nrec,
-                                  (uint32_t)ncells, reinterpret_cast<uint32_t*>(ws + W.scratch),
-                                  off, &sorted, s, rec_count, rec_count != nullptr);
+    if (a.rec_bucket_ap) {
+        sorted = reinterpret_cast<uint32_t*>(ws + W.vals_a);
+        e = msda::launch_bucket_sort(reinterpret_cast<uint32_t*>(ws + W.keys_a), spatial_shapes,
+                                     cell_start, a.B, a.N, a.L, a.A, a.P, (uint32_t)cells,
+                                     sorted, off, s);
+    } else {
+        e = msda::launch_sort_records(reinterpret_cast<uint32_t*>(ws + W.keys_a),
+                                      reinterpret_cast<uint32_t*>(ws + W.keys_b),
+                                      reinterpret_cast<uint32_t*>(ws + W.vals_a),
+                                      reinterpret_cast<uint32_t*>(ws + W.vals_b), (uint32_t)nrec,
+                                      (uint32_t)ncells, reinterpret_cast<uint32_t*>(ws + W.scratch),
+                                      off, &sorted, s, rec_count, rec_count != nullptr);
+    }
     if (e != hipSuccess) return hip_fail(e, "sort grad_feat records");
     msda::TileArgs t = {};
     t.vals = sorted ? sorted : reinterpret_cast<uint32_t*>(ws + W.vals_a);
@@ -1133,7 +1172,7 @@ msda_status plan_batch(const msda_batch* b, bool backward, BatchPlan* p) {
         p->max_cams = std::max(p->max_cams, sc.num_cams);
         p->max_batch_bytes = std::max<int64_t>(p->max_batch_bytes, bb);
         uint64_t cells = 0, tiles = 0;
-        cells_and_tiles(&d, &cells, &tiles);
+        cells_and_tiles(&d, &cells, &tiles, false);
         p->cells += cells;
         p->tiles += tiles;
         // heavy (scene, level): camera 0's area at most 1/16 of its largest level

@@ -384,6 +384,12 @@ struct ViewOrder {
 // (val == nullptr): the record is key[s] and its value is s. Compacted
 // records (the visible-view form): the k-th pair the wave processes writes
 // record r = cbase + k*L + l, key[r] and val[r] = s. key == nullptr: none.
+//
+// Bucketed records (bucket_ap != 0, the dense single call): the record of
+// pair src = p*N + n, level l goes to bucket (b, n, l) at slot a*P + p,
+// i.e. key[bucket_base + (n*L + l)*bucket_ap + p] with bucket_base =
+// b*N*L*bucket_ap + a*P, and its key is the local cell of the region
+// ((H+1)(W+1) outside the level); frac is still written at s.
 struct RecordSink {
     u32* key;
     float2* frac;
@@ -392,6 +398,9 @@ struct RecordSink {
     u32 no_cell;         // key of a sample outside its level
     u32* val;            // compacted records' values, or nullptr
     u32 cbase;           // compacted: first record of the wave's item
+    u32 bucket_ap;       // bucketed: A*P records per bucket (0: not bucketed)
+    u32 bucket_base;     // bucketed: b*N*L*A*P + a*P
+    u32 N;               // bucketed: cameras
 };
 
 // One anchor's weights as the gathers stage them: FP32 or bfloat16 storage,
@@ -482,11 +491,13 @@ __device__ __forceinline__ void stage_chunk(const StageSlot& s, const Order& ord
             s.frac[i] = make_float2(cr.lx, cr.ly);
             if (rec.key) {
                 const u32 smp = rec.base + src * (u32)L + (u32)l;
-                const u32 key = cr.valid ? rec.cell_base + gm.cstart +
-                                               (u32)(cr.y0 + 1) * (u32)(gm.W + 1) +
-                                               (u32)(cr.x0 + 1)
-                                         : rec.no_cell;
-                if (rec.val) {
+                const u32 local = cr.valid ? (u32)(cr.y0 + 1) * (u32)(gm.W + 1) + (u32)(cr.x0 + 1)
+                                           : (u32)(gm.H + 1) * (u32)(gm.W + 1);
+                const u32 key = cr.valid ? rec.cell_base + gm.cstart + local : rec.no_cell;
+                if (rec.bucket_ap) {
+                    const u32 p = src / rec.N, n = src - p * rec.N;
+                    rec.key[rec.bucket_base + (n * (u32)L + (u32)l) * rec.bucket_ap + p] = local;
+                } else if (rec.val) {
                     const u32 r = rec.cbase + (u32)(k0 + jj) * (u32)L + (u32)l;
                     rec.key[r] = key;
                     rec.val[r] = smp;

@@ -38,6 +38,10 @@ struct OpArgs {
     uint32_t batch_bytes;         // R * C * sizeof(feat element) (< 2^31)
     int32_t lps_shift;            // log2(lanes per sample) = log2(C / chans_per_lane)
     int32_t pairs_per_chunk;      // (keypoint, camera) pairs staged per wave step
+    // Bucketed records (dense single call): 0, or A*P -- the record of
+    // sample (b, a, p, n, l) then goes to bucket (b, n, l) at a*P + p, its
+    // key the local cell of region (n, l) (see launch_bucket_sort).
+    uint32_t rec_bucket_ap;
 };
 
 // The tiled grad_feat reduction over records sorted by bilinear cell.
@@ -221,6 +225,22 @@ hipError_t launch_sort_records(uint32_t* keys_a, uint32_t* keys_b, uint32_t* val
                                uint32_t* off, uint32_t** sorted_vals, hipStream_t s,
                                const uint32_t* n_dev = nullptr, bool vals_given = false);
 size_t sort_scratch_words(uint32_t n);
+// The dense single call's record sort, one workgroup per bucket (b, region):
+// bucket k = b*N*L + r holds the A*P records of region r of batch item b in
+// (anchor, keypoint) order at [k*ap, (k+1)*ap) of keys, key = the local cell
+// in [0, (H+1)(W+1)] ((H+1)(W+1): outside the level). Sorts each bucket by
+// key, stably, in LDS; writes vals[k*ap + i] = the sample index of the
+// bucket's i-th record in key order and off[] of the bucket's cells (global
+// cell b*cells_per_item + cell_start[r] + local), and off[B*cells_per_item]
+// = B*N*L*ap. Requires ap <= kBucketMaxRecords and (H+1)(W+1) + 1 <=
+// kBucketMaxKeys for every region, and bucket_sort_lds_bytes(ap) of LDS.
+constexpr uint32_t kBucketMaxRecords = 1u << 15;
+constexpr uint32_t kBucketMaxKeys = 1u << 17;
+size_t bucket_sort_lds_bytes(uint32_t ap);
+hipError_t launch_bucket_sort(const uint32_t* keys, const int32_t* shapes,
+                              const uint32_t* cell_start, int32_t B, int32_t N, int32_t L,
+                              int32_t A, int32_t P, uint32_t cells_per_item, uint32_t* vals,
+                              uint32_t* off, hipStream_t s);
 // In-place exclusive scan of n words; partial: scan_scratch_words(n) words.
 hipError_t launch_exclusive_scan(uint32_t* x, uint32_t n, uint32_t* partial, hipStream_t s);
 size_t scan_scratch_words(uint32_t n);

@@ -293,6 +293,204 @@ radix_scatter_kernel(const u32* __restrict__ keys_in, const u32* __restrict__ va
     }
 }
 
+// ---------------------------------------------------------------- bucket sort
+//
+// The dense single call's records arrive bucketed (see RecordSink): bucket k
+// = (batch item b, region r) holds the A*P samples of region r in (anchor,
+// keypoint) order -- which is their sample order -- keyed by local cell.
+// Every sample of a cell lies in one bucket, so sorting each bucket by key,
+// stably, gives exactly the order of the global sort (each cell's records in
+// sample order), in one launch and without leaving LDS.
+//
+// One workgroup of 1024 threads per bucket. Each element is the composite
+// key << 15 | pos (pos = its place in the bucket), held in registers: wave w
+// owns elements [w*64E, (w+1)*64E), E per lane. LSD passes over the key bits
+// with digits of at most 8 bits; a pass ranks equal digits by wave ballots
+// with per-wave running counts (as radix_scatter_kernel), turns the counts
+// into places, writes each element to its place in an LDS buffer and reloads
+// the registers from it in the new order. Then the sorted composites give
+// vals (sample index from b, r and pos) and, by a binary search per cell,
+// the cells' first positions.
+constexpr int kBucketThreads = 1024;
+constexpr int kBucketWaves = kBucketThreads / 64;
+constexpr int kBucketPosBits = 15;
+
+struct BucketSortArgs {
+    const u32* keys;
+    const int32_t* shapes;
+    const u32* cell_start;
+    u32* vals;
+    u32* off;
+    int B, N, L, A, P;
+    u32 ap;                     // A*P records per bucket
+    u32 cells_per_item;
+};
+
+size_t bucket_sort_lds_bytes(u32 ap) {
+    return ((size_t)ap + (size_t)kBucketWaves * kMaxDigits + kMaxDigits + 16) * 4;
+}
+
+template <int E>
+__global__ void __launch_bounds__(kBucketThreads) bucket_sort_kernel(BucketSortArgs p) {
+    extern __shared__ __align__(16) u32 bsm[];
+    u32* buf = bsm;                                        // [ap] composites
+    u32* wcount = bsm + p.ap;                              // [waves][256]
+    u32* dstart = wcount + kBucketWaves * kMaxDigits;      // [256]
+    u32* lds16 = dstart + kMaxDigits;                      // [16] wave totals
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const u32 k = blockIdx.x;
+    const int NL = p.N * p.L;
+    const int b = (int)(k / (u32)NL), r = (int)(k % (u32)NL);
+    const u32 H = (u32)p.shapes[2 * r], W = (u32)p.shapes[2 * r + 1];
+    const u32 nkeys = (H + 1) * (W + 1) + 1;               // local keys, the outside cell last
+    int kb = 1;
+    while (kb < 32 && ((nkeys - 1) >> kb) != 0) ++kb;
+    const int passes = (kb + kMaxDigitBits - 1) / kMaxDigitBits;
+    const int bits = (kb + passes - 1) / passes;
+    const int digits = 1 << bits;
+    const u32 mask = (u32)digits - 1u;
+    const u32 ap = p.ap;
+    const u32* keys = p.keys + (size_t)k * ap;
+
+    u32 v[E], rank[E];
+    const u32 j0 = (u32)(wave * 64 * E + lane);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {                          // every load in flight at once
+        const u32 j = j0 + (u32)(e * 64);
+        v[e] = j < ap ? (min(keys[j], nkeys - 1u) << kBucketPosBits) | j : 0u;
+    }
+    const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    u32* const run = wcount + wave * kMaxDigits;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = kBucketPosBits + pass * bits;
+        for (int i = tid; i < kBucketWaves * digits; i += kBucketThreads)
+            wcount[(i / digits) * kMaxDigits + (i % digits)] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const bool valid = j0 + (u32)(e * 64) < ap;
+            const u32 d = (v[e] >> shift) & mask;
+            unsigned long long peers = __ballot(valid);
+            for (int bit = 0; bit < bits; ++bit) {
+                const unsigned long long bb = __ballot((d >> bit) & 1u);
+                peers &= ((d >> bit) & 1u) ? bb : ~bb;
+            }
+            if (valid) {
+                // every peer reads the running count, then writes the same
+                // new value; the next element's reads follow in program order
+                const u32 before = run[d];
+                rank[e] = before + (u32)__popcll(peers & lt_mask);
+                run[d] = before + (u32)__popcll(peers);
+            }
+        }
+        __syncthreads();
+        // per digit: the waves' counts -> exclusive prefixes in wave order,
+        // plus the digit's start (exclusive scan of the digit totals)
+        u32 cnt = 0;
+        if (tid < digits) {
+#pragma unroll
+            for (int w = 0; w < kBucketWaves; ++w) {
+                const u32 c = wcount[w * kMaxDigits + tid];
+                wcount[w * kMaxDigits + tid] = cnt;
+                cnt += c;
+            }
+        }
+        // scan of cnt over the first `digits` threads (at most 4 waves)
+        u32 x = cnt;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const u32 t = __shfl_up(x, dd, 64);
+            if (lane >= dd) x += t;
+        }
+        if (lane == 63 && wave < 4) lds16[wave] = x;
+        __syncthreads();
+        if (tid < digits) {
+            u32 before = 0;
+            for (int w = 0; w < wave; ++w) before += lds16[w];
+            dstart[tid] = before + x - cnt;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (j0 + (u32)(e * 64) < ap) {
+                const u32 d = (v[e] >> shift) & mask;
+                buf[dstart[d] + wcount[wave * kMaxDigits + d] + rank[e]] = v[e];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const u32 j = j0 + (u32)(e * 64);
+            if (j < ap) v[e] = buf[j];
+        }
+        // the next pass clears wcount only after this barrier: every wave
+        // has read its places
+        __syncthreads();
+    }
+
+    // outputs: buf holds the bucket's composites in key order
+    const u32 n_ = (u32)p.N, L_ = (u32)p.L;
+    const u32 nr = (u32)r / L_, lr = (u32)r % L_;
+    u32* vals = p.vals + (size_t)k * ap;
+    for (u32 i = (u32)tid; i < ap; i += kBucketThreads) {
+        const u32 pos = buf[i] & ((1u << kBucketPosBits) - 1u);
+        const u32 a = pos / (u32)p.P, pp = pos - a * (u32)p.P;
+        // sample index of (b, a, pp, nr, lr)
+        vals[i] = ((((u32)b * (u32)p.A + a) * (u32)p.P + pp) * n_ + nr) * L_ + lr;
+    }
+    // first position of each local cell: the first composite >= cell << 15
+    u32* off = p.off + (size_t)b * p.cells_per_item + p.cell_start[r];
+    const u32 base = k * ap;
+    for (u32 c = (u32)tid; c < nkeys; c += kBucketThreads) {
+        const u32 want = c << kBucketPosBits;
+        u32 lo = 0, hi = ap;
+        while (lo < hi) {
+            const u32 mid = (lo + hi) >> 1;
+            if (buf[mid] < want) lo = mid + 1; else hi = mid;
+        }
+        off[c] = base + lo;
+    }
+    if (k + 1 == gridDim.x && tid == 0)
+        p.off[(size_t)p.B * p.cells_per_item] = (u32)gridDim.x * ap;
+}
+
+hipError_t launch_bucket_sort(const u32* keys, const int32_t* shapes, const u32* cell_start,
+                              int32_t B, int32_t N, int32_t L, int32_t A, int32_t P,
+                              u32 cells_per_item, u32* vals, u32* off, hipStream_t s) {
+    BucketSortArgs p;
+    p.keys = keys;
+    p.shapes = shapes;
+    p.cell_start = cell_start;
+    p.vals = vals;
+    p.off = off;
+    p.B = B;
+    p.N = N;
+    p.L = L;
+    p.A = A;
+    p.P = P;
+    p.ap = (u32)A * (u32)P;
+    p.cells_per_item = cells_per_item;
+    const unsigned grid = (unsigned)(B * N * L);
+    if (grid == 0 || p.ap == 0) return hipSuccess;
+    const size_t lds = bucket_sort_lds_bytes(p.ap);
+    const u32 per_lane = (p.ap + kBucketThreads - 1) / kBucketThreads;
+    mark_begin("bucket_sort", s);
+    if (per_lane <= 4)
+        hipLaunchKernelGGL(bucket_sort_kernel<4>, dim3(grid), dim3(kBucketThreads), lds, s, p);
+    else if (per_lane <= 8)
+        hipLaunchKernelGGL(bucket_sort_kernel<8>, dim3(grid), dim3(kBucketThreads), lds, s, p);
+    else if (per_lane <= 16)
+        hipLaunchKernelGGL(bucket_sort_kernel<16>, dim3(grid), dim3(kBucketThreads), lds, s, p);
+    else if (per_lane <= 32)
+        hipLaunchKernelGGL(bucket_sort_kernel<32>, dim3(grid), dim3(kBucketThreads), lds, s, p);
+    else {
+        mark_end(s);
+        return hipErrorInvalidValue;               // ap > kBucketMaxRecords: the caller's check
+    }
+    mark_end(s);
+    return hipGetLastError();
+}
+
 // off[r] = first position whose key is >= r, for r in [0, nrows]; keys are
 // sorted and every key is <= nrows.
 __global__ void segment_bounds_kernel(const u32* __restrict__ keys, u32 n, const u32* n_dev,

@@ -69,7 +69,8 @@ __device__ __forceinline__ void load_go(const float* p, float* v) {
 }
 
 // Tables of the tiled reduction for one batch item, from the shapes: the
-// first cell of each region (regions in order, (H+1)(W+1) cells each) and,
+// first cell of each region (regions in order, (H+1)(W+1) bilinear cells
+// each and one for the region's samples outside the level) and,
 // over processing slots (coarse levels first: slot o = (L-1-l)*N + n), the
 // first tile and the region of each slot. One block of 256 threads; N*L <=
 // 1024 regions, 4 per thread.
@@ -85,7 +86,7 @@ __global__ void __launch_bounds__(256) region_tables_kernel(const int32_t* shape
         cells[k] = tiles[k] = 0u;
         if (i < NL) {
             const u32 H = (u32)shapes[2 * i], W = (u32)shapes[2 * i + 1];
-            cells[k] = (H + 1) * (W + 1);
+            cells[k] = (H + 1) * (W + 1) + 1;    // + the region's outside cell
             const int o = i;                     // slot o -> region r
             const int r = (o % N) * L + (L - 1 - o / N);
             const u32 Hr = (u32)shapes[2 * r], Wr = (u32)shapes[2 * r + 1];

@@ -133,6 +133,27 @@ def test_all_visible_equals_dense(ops, dtype):
     assert normwise(host(out_v), host(out_d)) <= 1e-6
 
 
+@pytest.mark.parametrize("which", ["cam64", "train16"])
+def test_bucket_sort_equals_global_sort(ops, which):
+    """The dense backward sorts its records per (batch item, region) bucket
+    in LDS; the visible-view form, with every pair visible, sorts the same
+    records with the global radix sort. Every cell must list the same
+    records in the same order, so grad_feat is bitwise the same -- at the
+    64-camera scene (11,700 records per bucket) and the 16-camera training
+    workload (2 batch items, 23,400 per bucket, a quarter of them outside
+    every level), BF16."""
+    p = synth.cam64(seed=2, anchors=900, cams=16) if which == "cam64" else synth.train16(seed=2)
+    print(f"bucket vs global sort: {p.name} {p.dims()}", flush=True)
+    feat, layout, loc, w = to_device(p, torch.bfloat16)
+    v = torch.ones(p.batch, p.num_anchors, p.num_cams, dtype=torch.uint8, device="cuda")
+    go = synth.grad_out_like(p, seed=5).cuda()
+    gf_v, _, _ = ops.backward_visible(feat, layout, loc, w, v, go)
+    gf_d, _, _ = ops.backward(feat, layout, loc, w, go, need_loc=False, need_w=False,
+                              tile={"order": "view"})
+    torch.cuda.synchronize()
+    assert torch.equal(gf_v, gf_d)
+
+
 def test_nothing_visible(ops):
     p = synth.small(seed=33, B=1, cams=4, A=6, P=3)
     feat, layout, loc, w = to_device(p)
