@@ -117,11 +117,18 @@ __device__ __forceinline__ uint16_t f16_rne(float x) {
     return __builtin_bit_cast(uint16_t, (_Float16)x);
 }
 
-// FP32 -> bfloat16, round to nearest even (NaN stays NaN).
+// FP32 -> bfloat16 with gfx950's converter (v_cvt_pk_bf16_f32): round to
+// nearest even, overflow to infinity, NaN stays NaN.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
-    const u32 b = __float_as_uint(x);
-    if ((b & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((b >> 16) | 0x40u);
-    return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)x);
+}
+
+// Two values at once, lo in the low half: one instruction.
+__device__ __forceinline__ u32 bf16x2_rne(float lo, float hi) {
+    const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(u32, v);
 }
 
 // ---------------------------------------------------------------- geometry

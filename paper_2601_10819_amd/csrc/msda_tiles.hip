@@ -47,8 +47,14 @@ __device__ __forceinline__ void store_row(void* base, size_t elem, const float* 
         };
         uint16_t* p = static_cast<uint16_t*>(base) + elem;
         if constexpr (CPL == 4) {
-            const u32 lo = rnd(acc[0]) | (rnd(acc[1]) << 16);
-            const u32 hi = rnd(acc[2]) | (rnd(acc[3]) << 16);
+            u32 lo, hi;
+            if constexpr (OT::kKind == 3) {
+                lo = rnd(acc[0]) | (rnd(acc[1]) << 16);
+                hi = rnd(acc[2]) | (rnd(acc[3]) << 16);
+            } else {
+                lo = bf16x2_rne(acc[0], acc[1]);
+                hi = bf16x2_rne(acc[2], acc[3]);
+            }
             *reinterpret_cast<u32x2*>(p) = u32x2{lo, hi};
         } else {
 #pragma unroll
@@ -207,6 +213,7 @@ struct TileView {
     const float* vscale;        // [anchor][N] per-view weight factor, or nullptr
     int N, L;
     bool active;
+    bool w16;                   // G % 4 == 0 and w 16-byte aligned
 };
 
 // The reduction of one tile by a group of lps lanes (grp-th group of its
@@ -300,6 +307,12 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
                 const u32 n = (ls / (u32)v.L) % (u32)v.N;
                 const float sc = v.vscale[(size_t)an * v.N + n];
                 for (int k = 0; k < v.G; ++k) ent[8 + k] = ws[k] * sc;
+            } else if (v.w16) {
+                // rows of G % 4 == 0 floats from a 16-byte aligned base: 16-byte
+                // loads and LDS stores
+                const float4* ws4 = reinterpret_cast<const float4*>(ws);
+                float4* e4 = reinterpret_cast<float4*>(ent + 8);
+                for (int k = 0; k < (v.G >> 2); ++k) e4[k] = ws4[k];
             } else {
                 for (int k = 0; k < v.G; ++k) ent[8 + k] = ws[k];
             }
@@ -481,6 +494,7 @@ __device__ __forceinline__ void gfeat_tile_body(const TileArgs& t) {
     v.off = t.off;
     v.frac = t.frac;
     v.w = t.w;
+    v.w16 = (t.G & 3) == 0 && ((uintptr_t)t.w & 15) == 0;
     v.grad_out = t.grad_out;
     v.grad_feat = t.grad_feat;
     v.nrec = t.nrec;
@@ -550,6 +564,7 @@ __device__ __forceinline__ void gfeat_tile_batched_body(const BatchArgs& b) {
     v.off = b.off;
     v.frac = b.rec_frac;
     v.w = sc.weights;
+    v.w16 = (b.G & 3) == 0 && ((uintptr_t)sc.weights & 15) == 0;
     v.grad_out = sc.grad_out;
     v.grad_feat = sc.grad_feat;
     v.nrec = b.total_samples;

@@ -121,6 +121,45 @@ def test_f16_grad_feat_rounding_is_ieee(ops):
     assert torch.equal(gf[0, :A].cpu(), want)
 
 
+@pytest.mark.parametrize("C", [64, 256])
+def test_bf16_grad_feat_rounding_is_rne(ops, C):
+    """Pixel-centre samples with one weight each: grad_feat is w * grad_out
+    rounded once to bfloat16, nearest even, against torch's FP32 -> bfloat16
+    cast: exact ties both ways, the largest finite values and overflow,
+    FP32 subnormals, zeros of both signs, and random values. C = 64 runs the tile
+    reduction with 16 lanes per pixel, C = 256 with whole waves."""
+    G = 4
+    shapes, starts, R = synth.layout([[(1, 4)]])
+    layout = ops.Layout(shapes, starts)
+    feat = torch.zeros(1, R, C, dtype=torch.bfloat16, device="cuda")
+    A = 4
+    loc = torch.zeros(1, A, 1, 1, 2)
+    loc[0, :, 0, 0, 0] = (torch.arange(A) + 0.5) / 4      # pixel a of the 1x4 level
+    loc[0, :, 0, 0, 1] = 0.5
+    w = torch.ones(1, A, 1, 1, 1, G)
+    go = torch.randn(1, A, C, generator=torch.Generator().manual_seed(0)) * 3.0
+    one = 1.0
+    tie_even = one + 2.0 ** -8            # halfway between 1 and 1 + 2^-7: rounds down
+    tie_odd = one + 3 * 2.0 ** -8         # halfway, odd below: rounds up
+    special = torch.tensor([tie_even, tie_odd, -tie_even, -tie_odd, 3.3895e38, 3.4e38,
+                            -3.4e38, 1e-40, -1e-40, 2.0 ** -133, 0.0, -0.0,
+                            1.0 + 2.0 ** -8 + 2.0 ** -20, 2.0 ** -126, 65504.0, 1e-8],
+                           dtype=torch.float32)
+    go[0, 3, :len(special)] = special
+    gf, _, _ = ops.backward(feat, layout, loc.cuda(), w.cuda(), go.cuda(), need_loc=False,
+                            need_w=False)
+    torch.cuda.synchronize()
+    # the FP32 sum starts at +0 (so -0 sums to +0), then torch's FP32 ->
+    # bfloat16 cast (nearest even)
+    want = (go[0] + 0.0).to(torch.bfloat16)
+    got = gf[0, :A].cpu()
+    assert torch.equal(got.view(torch.int16), want.view(torch.int16)), \
+        [(float(go[0].reshape(-1)[i]), int(got.view(torch.int16).reshape(-1)[i]),
+          int(want.view(torch.int16).reshape(-1)[i]))
+         for i in torch.nonzero(got.view(torch.int16).reshape(-1) !=
+                                want.view(torch.int16).reshape(-1)).reshape(-1)[:8]]
+
+
 def test_fp8_quantiser_bit_exact(ops, oracle_mod):
     p = synth.sparse4d(seed=1, anchors=8)
     layout = ops.Layout(p.spatial_shapes, p.level_start_index)
