@@ -60,8 +60,11 @@ __global__ void __launch_bounds__(512) msda_bwd_kernel(OpArgs a) {
 }
 
 // View order (see slot_span): workgroup w serves slot w % kSlots, each wave
-// one row (an anchor over its views in the slot). Every output is per
-// sample or per pair, so the rows need no combining.
+// one (view, anchor) item of the slot -- one anchor in one camera -- in the
+// slot's view-major order, so an XCD's L2 holds about one camera's pyramid
+// at a time (the forward's rows span all of a slot's cameras, whose partial
+// sums it must add; here every output is per sample or per pair, so the
+// items need no combining).
 template <class FT, int CPL>
 __global__ void __launch_bounds__(512) msda_bwd_view_kernel(OpArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -74,8 +77,18 @@ __global__ void __launch_bounds__(512) msda_bwd_view_kernel(OpArgs a) {
     const int wave = wave_index(), nwaves = blockDim.x >> 6;
     const int64_t r = (int64_t)(blockIdx.x / kSlots) * nwaves + wave;
     const SlotSpan span = slot_span(xs, a.B, a.N, a.A);
-    if (r >= slot_rows(span, a.A)) return;
-    ViewRow row = view_row(span, r, a.N, a.A);
+    // one (view, anchor) item per wave, in the slot's view-major order: the
+    // waves in flight on an XCD work through about one camera at a time
+    const int64_t item = span.lo + r;
+    if (item >= span.hi) return;
+    ViewRow row;
+    {
+        const int64_t view = item / a.A;
+        row.a = (int32_t)(item - view * a.A);
+        row.b = (int32_t)(view / a.N);
+        row.n_lo = (int32_t)(view - (int64_t)row.b * a.N);
+        row.nv = 1;
+    }
     // every field is the same across the wave (r is per wave)
     row.b = uniform(row.b);
     row.a = uniform(row.a);
@@ -181,7 +194,8 @@ hipError_t launch_backward(const OpArgs& a, int dtype, int cpl, int waves, size_
 
 template <class FT, int CPL>
 static hipError_t bwd_view_launch(const OpArgs& a, int waves, size_t lds, hipStream_t s) {
-    const int64_t rows = max_slot_rows(a.B, a.N, a.A);
+    // items per slot at most (slot_span cuts B*N*A items into kSlots ranges)
+    const int64_t rows = ((int64_t)a.B * a.N * a.A + kSlots - 1) / kSlots;
     const unsigned blocks = (unsigned)(kSlots * ((rows + waves - 1) / waves));
     mark_begin("msda_bwd_view_kernel", s);
     hipLaunchKernelGGL((msda_bwd_view_kernel<FT, CPL>), dim3(blocks), dim3(64 * waves), lds, s,
