@@ -479,9 +479,14 @@ size_t msda_forward_workspace_size(const msda_desc* d) {
     return align256(part) + stats_bytes(d);
 }
 
-// The backward gather in the chosen order.
-static hipError_t launch_gather(const msda::OpArgs& a, int order, int dtype, int cpl, int waves,
+// The backward gather in the chosen order. In view order each wave takes
+// one anchor over a group of cameras: 2 for 1- and 2-byte features, 1 for
+// FP32 (measured at 64 cameras: BF16 0.457 ms with 2 against 0.478 with 1
+// and 0.470 with 4; FP32 0.709 ms with 1 against 0.754 with 2).
+static hipError_t launch_gather(const msda::OpArgs& a0, int order, int dtype, int cpl, int waves,
                                 hipStream_t s) {
+    msda::OpArgs a = a0;
+    a.view_cams = dtype == MSDA_F32 ? 1 : 2;
     if (order == MSDA_ORDER_VIEW)
         return msda::launch_backward_view(a, dtype, cpl, waves, msda::lds_bytes_view(a, waves), s);
     return msda::launch_backward(a, dtype, cpl, waves, msda::lds_bytes_for(a, waves), s);

@@ -60,11 +60,11 @@ __global__ void __launch_bounds__(512) msda_bwd_kernel(OpArgs a) {
 }
 
 // View order (see slot_span): workgroup w serves slot w % kSlots, each wave
-// one (view, anchor) item of the slot -- one anchor in one camera -- in the
-// slot's view-major order, so an XCD's L2 holds about one camera's pyramid
-// at a time (the forward's rows span all of a slot's cameras, whose partial
-// sums it must add; here every output is per sample or per pair, so the
-// items need no combining).
+// one anchor over a small group of cameras (a.view_cams; groups aligned
+// within the batch item) in the slot's view-major order, so an XCD's L2
+// holds the pyramids of about a group of cameras at a time (the forward's
+// rows span all of a slot's cameras, whose partial sums it must add; here
+// every output is per sample or per pair, so the rows need no combining).
 template <class FT, int CPL>
 __global__ void __launch_bounds__(512) msda_bwd_view_kernel(OpArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -77,17 +77,31 @@ __global__ void __launch_bounds__(512) msda_bwd_view_kernel(OpArgs a) {
     const int wave = wave_index(), nwaves = blockDim.x >> 6;
     const int64_t r = (int64_t)(blockIdx.x / kSlots) * nwaves + wave;
     const SlotSpan span = slot_span(xs, a.B, a.N, a.A);
-    // one (view, anchor) item per wave, in the slot's view-major order: the
-    // waves in flight on an XCD work through about one camera at a time
-    const int64_t item = span.lo + r;
-    if (item >= span.hi) return;
+    // one anchor over a group of a.view_cams cameras per wave (groups
+    // aligned within each batch item), rows in the slot's view-major order:
+    // the waves in flight on an XCD work through a few cameras at a time
+    if (span.hi <= span.lo) return;
+    const int M = max(1, a.view_cams);
+    const int gpb = (a.N + M - 1) / M;                     // camera groups per batch item
+    const int64_t vf = span.lo / a.A, vl = (span.hi - 1) / a.A;
+    const int64_t gf = (vf / a.N) * gpb + (vf % a.N) / M;
+    const int64_t g = gf + r / a.A;
+    const int64_t gl = (vl / a.N) * gpb + (vl % a.N) / M;
+    if (g > gl) return;
     ViewRow row;
     {
-        const int64_t view = item / a.A;
-        row.a = (int32_t)(item - view * a.A);
-        row.b = (int32_t)(view / a.N);
-        row.n_lo = (int32_t)(view - (int64_t)row.b * a.N);
-        row.nv = 1;
+        row.a = (int32_t)(r % a.A);
+        row.b = (int32_t)(g / gpb);
+        const int j = (int)(g - (int64_t)row.b * gpb);
+        const int64_t base = (int64_t)row.b * a.N;
+        int64_t v0 = base + (int64_t)j * M, v1 = base + min((j + 1) * M, a.N);
+        // the views whose item (view, a) lies in the slot
+        const int64_t lo_v = (span.lo - row.a + a.A - 1) / a.A;
+        const int64_t hi_v = (span.hi - row.a + a.A - 1) / a.A;
+        if (v0 < lo_v) v0 = lo_v;
+        if (v1 > hi_v) v1 = hi_v;
+        row.n_lo = (int32_t)(v0 - base);
+        row.nv = v1 > v0 ? (int32_t)(v1 - v0) : 0;
     }
     // every field is the same across the wave (r is per wave)
     row.b = uniform(row.b);
@@ -194,8 +208,17 @@ hipError_t launch_backward(const OpArgs& a, int dtype, int cpl, int waves, size_
 
 template <class FT, int CPL>
 static hipError_t bwd_view_launch(const OpArgs& a, int waves, size_t lds, hipStream_t s) {
-    // items per slot at most (slot_span cuts B*N*A items into kSlots ranges)
-    const int64_t rows = ((int64_t)a.B * a.N * a.A + kSlots - 1) / kSlots;
+    // rows per slot at most: the camera groups a slot touches, times A
+    int64_t rows = 0;
+    const int M = max(1, a.view_cams), gpb = (a.N + M - 1) / M;
+    for (int x = 0; x < kSlots; ++x) {
+        const SlotSpan sp = slot_span(x, a.B, a.N, a.A);
+        if (sp.hi <= sp.lo) continue;
+        const int64_t vf = sp.lo / a.A, vl = (sp.hi - 1) / a.A;
+        const int64_t gf = (vf / a.N) * gpb + (vf % a.N) / M;
+        const int64_t gl = (vl / a.N) * gpb + (vl % a.N) / M;
+        rows = max(rows, (gl - gf + 1) * (int64_t)a.A);
+    }
     const unsigned blocks = (unsigned)(kSlots * ((rows + waves - 1) / waves));
     mark_begin("msda_bwd_view_kernel", s);
     hipLaunchKernelGGL((msda_bwd_view_kernel<FT, CPL>), dim3(blocks), dim3(64 * waves), lds, s,

@@ -42,6 +42,8 @@ struct OpArgs {
     // sample (b, a, p, n, l) then goes to bucket (b, n, l) at a*P + p, its
     // key the local cell of region (n, l) (see launch_bucket_sort).
     uint32_t rec_bucket_ap;
+    // Backward view order: cameras of one anchor per wave (>= 1).
+    int32_t view_cams;
 };
 
 // The tiled grad_feat reduction over records sorted by bilinear cell.
