@@ -714,19 +714,22 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
         cell_start = reinterpret_cast<uint32_t*>(ws + W.cell_start);
         tile_start = reinterpret_cast<uint32_t*>(ws + W.tile_start);
         tile_region = reinterpret_cast<uint32_t*>(ws + W.tile_region);
-        if ((e = msda::launch_region_tables(spatial_shapes, a.N, a.L, cell_start, tile_start,
+        // dense records sorted per (batch item, region) bucket in LDS when
+        // the buckets fit (that launch also writes the region tables), else
+        // the global radix sort
+        if (!visible && bucket_sort_fits(desc)) a.rec_bucket_ap = (uint32_t)(a.A * a.P);
+        if (!a.rec_bucket_ap &&
+            (e = msda::launch_region_tables(spatial_shapes, a.N, a.L, cell_start, tile_start,
                                             tile_region, s)) != hipSuccess)
             return hip_fail(e, "region tables");
         a.rec_key = reinterpret_cast<uint32_t*>(ws + W.keys_a);
         a.rec_frac = reinterpret_cast<float2*>(ws + W.frac);
-        a.cell_start = cell_start;
+        // bucketed records carry local cells: the gather needs no cell table
+        a.cell_start = a.rec_bucket_ap ? nullptr : cell_start;
         a.cells_per_item = (uint32_t)cells;
         a.cell_offset = 0;
         a.no_cell = (uint32_t)ncells;
         a.sample_offset = 0;
-        // dense records sorted per (batch item, region) bucket in LDS when
-        // the buckets fit, else the global radix sort
-        if (!visible && bucket_sort_fits(desc)) a.rec_bucket_ap = (uint32_t)(a.A * a.P);
         // rows outside every region are not visited by a tile
         if (!cover && (e = msda::launch_fill_zero(grad_feat, gf_bytes, s)) != hipSuccess)
             return hip_fail(e, "zero grad_feat");
@@ -783,8 +786,8 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
     if (a.rec_bucket_ap) {
         sorted = reinterpret_cast<uint32_t*>(ws + W.vals_a);
         e = msda::launch_bucket_sort(reinterpret_cast<uint32_t*>(ws + W.keys_a), spatial_shapes,
-                                     cell_start, a.B, a.N, a.L, a.A, a.P, (uint32_t)cells,
-                                     sorted, off, s);
+                                     a.B, a.N, a.L, a.A, a.P, (uint32_t)cells, sorted, off,
+                                     cell_start, tile_start, tile_region, s);
     } else {
         e = msda::launch_sort_records(reinterpret_cast<uint32_t*>(ws + W.keys_a),
                                       reinterpret_cast<uint32_t*>(ws + W.keys_b),

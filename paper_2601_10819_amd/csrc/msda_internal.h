@@ -234,15 +234,17 @@ size_t sort_scratch_words(uint32_t n);
 // key, stably, in LDS; writes vals[k*ap + i] = the sample index of the
 // bucket's i-th record in key order and off[] of the bucket's cells (global
 // cell b*cells_per_item + cell_start[r] + local), and off[B*cells_per_item]
-// = B*N*L*ap. Requires ap <= kBucketMaxRecords and (H+1)(W+1) + 1 <=
-// kBucketMaxKeys for every region, and bucket_sort_lds_bytes(ap) of LDS.
+// = B*N*L*ap. Also writes the region tables of launch_region_tables
+// (cell_start, tile_start, tile_region). Requires ap <= kBucketMaxRecords,
+// (H+1)(W+1) + 1 <= kBucketMaxKeys for every region, N*L <= 1024, and
+// bucket_sort_lds_bytes(ap) of LDS.
 constexpr uint32_t kBucketMaxRecords = 1u << 15;
 constexpr uint32_t kBucketMaxKeys = 1u << 17;
 size_t bucket_sort_lds_bytes(uint32_t ap);
-hipError_t launch_bucket_sort(const uint32_t* keys, const int32_t* shapes,
-                              const uint32_t* cell_start, int32_t B, int32_t N, int32_t L,
-                              int32_t A, int32_t P, uint32_t cells_per_item, uint32_t* vals,
-                              uint32_t* off, hipStream_t s);
+hipError_t launch_bucket_sort(const uint32_t* keys, const int32_t* shapes, int32_t B, int32_t N,
+                              int32_t L, int32_t A, int32_t P, uint32_t cells_per_item,
+                              uint32_t* vals, uint32_t* off, uint32_t* cell_start,
+                              uint32_t* tile_start, uint32_t* tile_region, hipStream_t s);
 // In-place exclusive scan of n words; partial: scan_scratch_words(n) words.
 hipError_t launch_exclusive_scan(uint32_t* x, uint32_t n, uint32_t* partial, hipStream_t s);
 size_t scan_scratch_words(uint32_t n);

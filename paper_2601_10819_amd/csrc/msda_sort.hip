@@ -318,16 +318,43 @@ constexpr int kBucketPosBits = 15;
 struct BucketSortArgs {
     const u32* keys;
     const int32_t* shapes;
-    const u32* cell_start;
     u32* vals;
     u32* off;
+    // the tiled reduction's tables, written by block 0 (as region_tables_kernel)
+    u32* cell_start;
+    u32* tile_start;
+    u32* tile_region;
     int B, N, L, A, P;
     u32 ap;                     // A*P records per bucket
     u32 cells_per_item;
 };
 
 size_t bucket_sort_lds_bytes(u32 ap) {
-    return ((size_t)ap + (size_t)kBucketWaves * kMaxDigits + kMaxDigits + 16) * 4;
+    return ((size_t)ap + (size_t)kBucketWaves * kMaxDigits + kMaxDigits + 32) * 4;
+}
+
+// Exclusive scan of v over the 1024 threads of a bucket-sort block (wave
+// sums in lds[0..15]); returns the thread's exclusive prefix and the total.
+__device__ __forceinline__ u32 bucket_block_scan(u32 v, u32* lds, u32* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    u32 x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const u32 t = __shfl_up(x, d, 64);
+        if (lane >= d) x += t;
+    }
+    if (lane == 63) lds[wave] = x;
+    __syncthreads();
+    u32 before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kBucketWaves; ++w) {
+        const u32 t = lds[w];
+        if (w < wave) before += t;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return before + x - v;
 }
 
 template <int E>
@@ -337,10 +364,40 @@ __global__ void __launch_bounds__(kBucketThreads) bucket_sort_kernel(BucketSortA
     u32* wcount = bsm + p.ap;                              // [waves][256]
     u32* dstart = wcount + kBucketWaves * kMaxDigits;      // [256]
     u32* lds16 = dstart + kMaxDigits;                      // [16] wave totals
+    u32* lds_scan = lds16 + 16;                            // [16] block scan
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const u32 k = blockIdx.x;
     const int NL = p.N * p.L;
     const int b = (int)(k / (u32)NL), r = (int)(k % (u32)NL);
+
+    // The region tables (NL <= 1024: one region per thread): the first cell
+    // of every region ((H+1)(W+1) bilinear cells and the outside cell each)
+    // -- this block's own, and block 0 writes them all -- and, over the
+    // processing slots (coarse levels first: slot o -> region
+    // (o % N) * L + (L - 1 - o / N)), the first tile and region of each slot.
+    {
+        u32 cells = 0, tiles = 0;
+        int rs = 0;
+        if (tid < NL) {
+            cells = (u32)(p.shapes[2 * tid] + 1) * (u32)(p.shapes[2 * tid + 1] + 1) + 1u;
+            rs = (tid % p.N) * p.L + (p.L - 1 - tid / p.N);
+            tiles = ((u32)(p.shapes[2 * rs] + kTileH - 1) / kTileH) *
+                    ((u32)(p.shapes[2 * rs + 1] + kTileW - 1) / kTileW);
+        }
+        u32 tc, tt;
+        const u32 cs = bucket_block_scan(cells, lds_scan, &tc);
+        const u32 ts = bucket_block_scan(tiles, lds_scan, &tt);
+        if (tid == r) dstart[0] = cs;                      // this bucket's region
+        if (k == 0 && tid < NL) {
+            p.cell_start[tid] = cs;
+            p.tile_start[tid] = ts;
+            p.tile_region[tid] = (u32)rs;
+            if (tid == NL - 1) p.tile_start[NL] = tt;
+        }
+        __syncthreads();
+    }
+    const u32 cstart = dstart[0];
+    __syncthreads();                                       // dstart is reused below
     const u32 H = (u32)p.shapes[2 * r], W = (u32)p.shapes[2 * r + 1];
     const u32 nkeys = (H + 1) * (W + 1) + 1;               // local keys, the outside cell last
     int kb = 1;
@@ -438,29 +495,30 @@ __global__ void __launch_bounds__(kBucketThreads) bucket_sort_kernel(BucketSortA
         // sample index of (b, a, pp, nr, lr)
         vals[i] = ((((u32)b * (u32)p.A + a) * (u32)p.P + pp) * n_ + nr) * L_ + lr;
     }
-    // first position of each local cell: the first composite >= cell << 15
-    u32* off = p.off + (size_t)b * p.cells_per_item + p.cell_start[r];
+    // first position of each local cell: element i starts the cells in
+    // (key[i-1], key[i]] (from 0 for the first), and the cells after the
+    // last key start at the bucket's end; every cell is written once
+    u32* off = p.off + (size_t)b * p.cells_per_item + cstart;
     const u32 base = k * ap;
-    for (u32 c = (u32)tid; c < nkeys; c += kBucketThreads) {
-        const u32 want = c << kBucketPosBits;
-        u32 lo = 0, hi = ap;
-        while (lo < hi) {
-            const u32 mid = (lo + hi) >> 1;
-            if (buf[mid] < want) lo = mid + 1; else hi = mid;
-        }
-        off[c] = base + lo;
+    for (u32 i = (u32)tid; i <= ap; i += kBucketThreads) {
+        const u32 c1 = i < ap ? buf[i] >> kBucketPosBits : nkeys - 1u;
+        const u32 c0 = i == 0 ? 0u : (buf[i - 1] >> kBucketPosBits) + 1u;
+        for (u32 c = c0; c <= c1; ++c) off[c] = base + i;
     }
     if (k + 1 == gridDim.x && tid == 0)
         p.off[(size_t)p.B * p.cells_per_item] = (u32)gridDim.x * ap;
 }
 
-hipError_t launch_bucket_sort(const u32* keys, const int32_t* shapes, const u32* cell_start,
-                              int32_t B, int32_t N, int32_t L, int32_t A, int32_t P,
-                              u32 cells_per_item, u32* vals, u32* off, hipStream_t s) {
+hipError_t launch_bucket_sort(const u32* keys, const int32_t* shapes, int32_t B, int32_t N,
+                              int32_t L, int32_t A, int32_t P, u32 cells_per_item, u32* vals,
+                              u32* off, u32* cell_start, u32* tile_start, u32* tile_region,
+                              hipStream_t s) {
     BucketSortArgs p;
     p.keys = keys;
     p.shapes = shapes;
     p.cell_start = cell_start;
+    p.tile_start = tile_start;
+    p.tile_region = tile_region;
     p.vals = vals;
     p.off = off;
     p.B = B;
