@@ -144,8 +144,10 @@ typedef struct msda_desc {
  * Forward (paper Sec. 3.1/3.2): out = sum over keypoints, cameras and levels
  * of weight * bilinear sample. All pointers device.
  * Requirements: every region [start, start + H*W) lies in [0, R); H, W >= 1;
- * R*C*sizeof(feat element) < 2^31 (one batch item is addressed with 32-bit
- * offsets; larger inputs are split by the caller); feat 16-byte aligned.
+ * R*C*sizeof(feat element) <= 4 GiB - 8 KiB (one batch item is addressed
+ * with 32-bit byte offsets; larger inputs are split by the caller) and
+ * C*sizeof(feat element) <= 4096 (UNSUPPORTED otherwise); feat 16-byte
+ * aligned.
  * Returns INVALID_ARGUMENT / UNSUPPORTED as listed above, else OK.
  */
 msda_status msda_forward(const void* feat, const int32_t* spatial_shapes,

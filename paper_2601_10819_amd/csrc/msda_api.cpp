@@ -123,10 +123,16 @@ msda_status check_regions(const msda_desc* d, int64_t* batch_bytes_out) {
                         "region %lld: rows [%lld, %lld) outside [0, R=%lld)", (long long)i,
                         (long long)s0, (long long)(s0 + H * W), (long long)d->rows);
     }
+    // one batch item is one buffer resource with 32-bit byte offsets, and
+    // the out-of-level marker offset msda::kOOB lies at or past its end
+    if ((int64_t)d->channels * eb > (int64_t)msda::kMaxRowBytes)
+        return fail(MSDA_ERR_UNSUPPORTED, "a feature row is %lld bytes (limit %u)",
+                    (long long)d->channels * eb, msda::kMaxRowBytes);
     const int64_t batch_bytes = d->rows * d->channels * (int64_t)eb;
-    if (batch_bytes > 0x7ffffff0LL)
-        return fail(MSDA_ERR_UNSUPPORTED, "one batch item of feat is %lld bytes (limit 2^31 - 16)",
-                    (long long)batch_bytes);
+    if (batch_bytes > (int64_t)msda::kOOB)
+        return fail(MSDA_ERR_UNSUPPORTED,
+                    "one batch item of feat is %lld bytes (limit %lld, 4 GiB - 8 KiB)",
+                    (long long)batch_bytes, (long long)msda::kOOB);
     if ((int64_t)d->batch * d->num_anchors > 0x7fffffffLL)
         return fail(MSDA_ERR_UNSUPPORTED, "batch * anchors exceeds 2^31 - 1");
     *batch_bytes_out = batch_bytes;

@@ -35,9 +35,6 @@ typedef u32 u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 
-// Offset used for a corner outside its level: beyond every resource (whose
-// size is < 2^31), so a buffer load returns zeros.
-constexpr u32 kOOB = 0x80000000u;
 
 // Word 3 of a raw (untyped, stride 0) buffer resource on gfx9-family GPUs.
 constexpr int kRsrcWord3 = 0x00020000;

@@ -11,6 +11,13 @@
 
 namespace msda {
 
+// Byte offset used for a corner outside its level: at or beyond the end of
+// every feature resource (a batch item is at most kOOB bytes, one buffer
+// resource with 32-bit offsets), so a buffer load returns zeros; a lane adds
+// at most one row (<= kMaxRowBytes) to it, which cannot wrap past 2^32.
+constexpr uint32_t kMaxRowBytes = 4096u;
+constexpr uint32_t kOOB = 0xFFFFE000u;
+
 // Everything one forward/backward launch needs. Pointers are device memory.
 struct OpArgs {
     const void* feat;             // [B][R][C], dtype below
@@ -35,7 +42,7 @@ struct OpArgs {
     int32_t w_bf16;               // forward: w holds bfloat16 bit patterns
     int32_t B, N, L, A, P, C, G;
     int64_t R;
-    uint32_t batch_bytes;         // R * C * sizeof(feat element) (< 2^31)
+    uint32_t batch_bytes;         // R * C * sizeof(feat element) (<= kOOB, under 4 GiB)
     int32_t lps_shift;            // log2(lanes per sample) = log2(C / chans_per_lane)
     int32_t pairs_per_chunk;      // (keypoint, camera) pairs staged per wave step
     // Bucketed records (dense single call): 0, or A*P -- the record of

@@ -210,7 +210,7 @@ hipError_t launch_quantize_fp8(const float* x, const int32_t* shapes, const int3
     // floats) of the largest region
     const size_t most = (size_t)max_region_rows * (size_t)C;
     const size_t per = (size_t)kQuantChunk * 4;
-    const size_t y = (most + per - 1) / per;   // <= 2^15: a batch item is < 2^31 bytes
+    const size_t y = (most + per - 1) / per;   // < 2^16: a batch item is under 4 GiB
     const dim3 grid((unsigned)(y < 1 ? 1 : y), (unsigned)(N * L), (unsigned)B);
     mark_begin("fp8_amax", s);
     if (vec)

@@ -136,9 +136,15 @@ def test_unsupported_requests(lib):
     expect(lib, fwd(lib, desc(Geo(), tile=(3, 0, 0, 0))), UNS, "waves_per_anchor")
     expect(lib, fwd(lib, desc(Geo(), tile=(0, 16, 0, 0))), UNS, "chans_per_lane")
     expect(lib, fwd(lib, desc(Geo(), tile=(0, 0, 5, 0))), UNS, "order")
-    # one batch item beyond 2^31 bytes of features
+    # one batch item beyond 4 GiB - 8 KiB of features (4096 x 4096 x 64 FP32)
     g = Geo(ncam=1, levels=((4096, 4096),))
     expect(lib, fwd(lib, desc(g, C=64, G=4)), UNS, "bytes")
+    # 2 GiB < one batch item <= 4 GiB - 8 KiB is accepted (validation only here)
+    g = Geo(ncam=2, levels=((1024, 2000),))
+    assert fwd(lib, desc(g, C=256, G=8, A=0)) == _lib.MSDA_OK
+    # a feature row above 4 KiB (its offset plus the out-of-level marker
+    # would pass 2^32; the lane layouts stop at 1 KiB rows anyway)
+    expect(lib, fwd(lib, desc(Geo(), C=2048, G=8)), UNS, "row")
 
 
 def test_backward_validation(lib):

@@ -4,8 +4,8 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import (FWD_F32_MAXREL, FWD_F32_TOL, anchor_subset, assert_close, host,
-                     oracle_forward_subset, to_device)
+from helpers import (FWD_F32_MAXREL, FWD_F32_TOL, GRAD_F32_MAXREL, GRAD_F32_TOL, anchor_subset,
+                     assert_close, host, oracle_forward_subset, to_device)
 from paper_2601_10819_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -114,36 +114,106 @@ def test_forward_pixel_centres_exact(ops):
     assert np.array_equal(got[0], feat[0, rows].double().numpy())
 
 
-def test_forward_max_batch_item(ops, oracle_mod):
-    """A batch item just under the 2^31-byte addressing limit, with samples in
-    its last rows: 32-bit offsets stay exact up to the limit."""
-    C, G = 256, 8
-    # 2 cameras x one 1024 x 1023 level: R*C*4 = 2,145,386,496 bytes < 2^31 - 16
-    levels = [(1024, 1023)]
-    shapes, starts, R = synth.layout([levels] * 2)
-    assert R * C * 4 < 2 ** 31 - 16
-    gen = torch.Generator().manual_seed(2)
-    A, P = 16, 4
-    feat = torch.empty(1, R, C, device="cuda")
-    feat.normal_(generator=torch.Generator(device="cuda").manual_seed(3))
-    loc = torch.rand(1, A, P, 2, 2, generator=gen) * 0.05 + 0.95   # bottom-right corner
+def _affine_feat(shapes, starts, R, C, gen, centre=30):
+    """FP32 features on the GPU, affine in each level's pixel coordinates:
+    F[start + y*W + x, c] = alpha_c + beta_c * (x - xc) + gamma_c * (y - yc)
+    with (xc, yc) = (W, H) - centre (small integers, exact in FP32), so every
+    interior bilinear sample is exact. Centred on the sampled corner of the
+    level, the values stay about 100 there, like a feature map's (the FP32
+    difference of neighbouring corners that grad_sampling_loc takes would
+    otherwise cancel digits)."""
+    alpha = torch.randint(-50, 50, (C,), generator=gen).float()
+    beta = torch.randint(-3, 4, (C,), generator=gen).float()
+    gamma = torch.randint(-3, 4, (C,), generator=gen).float()
+    feat = torch.zeros(1, R, C, device="cuda")
+    a, b, g = alpha.cuda(), beta.cuda(), gamma.cuda()
+    for n in range(shapes.shape[0]):
+        H, W = int(shapes[n, 0, 0]), int(shapes[n, 0, 1])
+        s0 = int(starts[n, 0])
+        ys = torch.arange(H, device="cuda", dtype=torch.float32) - (H - centre)
+        xs = torch.arange(W, device="cuda", dtype=torch.float32) - (W - centre)
+        for y0 in range(0, H, 256):                      # a band of rows at a time
+            yb = ys[y0:y0 + 256]
+            blk = a + b * xs[None, :, None] + g * yb[:, None, None]
+            feat[0, s0 + y0 * W:s0 + (y0 + len(yb)) * W] = blk.reshape(-1, C)
+    return feat, alpha.double(), beta.double(), gamma.double()
+
+
+def _interior_locs(shapes, A, P, gen, margin=60):
+    """(u, v) whose four corners lie inside the level, in its last `margin`
+    rows and columns (the highest offsets of each camera)."""
+    N = shapes.shape[0]
+    loc = torch.empty(1, A, P, N, 2)
+    for n in range(N):
+        H, W = int(shapes[n, 0, 0]), int(shapes[n, 0, 1])
+        x = W - margin + torch.rand(A, P, generator=gen) * (margin - 2)
+        y = H - margin + torch.rand(A, P, generator=gen) * (margin - 2)
+        loc[0, :, :, n, 0] = (x + 0.5) / W
+        loc[0, :, :, n, 1] = (y + 0.5) / H
+    return loc
+
+
+def test_forward_backward_beyond_2gib(ops):
+    """One batch item of 4.19 GB of FP32 features (2 cameras x one 1024 x 2000
+    level, C = 256), beyond 2^31 bytes and close to the 4 GiB limit, with
+    samples in each camera's last rows: the output, grad_weights and
+    grad_sampling_loc against closed forms (affine features are interpolated
+    exactly; d/dx of the sample is beta, d/dy gamma), and grad_feat by the
+    identity <grad_feat, feat> = <grad_out, out>."""
+    C, G, A, P = 256, 8, 24, 4
+    shapes, starts, R = synth.layout([[(1024, 2000)]] * 2)
+    assert 2 ** 31 < R * C * 4 <= 2 ** 32 - 8192
+    gen = torch.Generator().manual_seed(7)
+    feat, alpha, beta, gamma = _affine_feat(shapes, starts, R, C, gen)
+    loc = _interior_locs(shapes, A, P, gen)
+    w = torch.rand(1, A, P, 2, 1, G, generator=gen)
+    go = torch.randn(1, A, C, generator=gen)
+    layout = ops.Layout(shapes, starts)
+    print(f"beyond 2 GiB: R={R} bytes={R * C * 4}", flush=True)
+    out = ops.forward(feat, layout, loc.cuda(), w.cuda())
+    gf, gl, gw = ops.backward(feat, layout, loc.cuda(), w.cuda(), go.cuda())
+    torch.cuda.synchronize()
+    # closed forms in FP64
+    Wd = shapes[:, 0, 1].double()[None, None, :]
+    Hd = shapes[:, 0, 0].double()[None, None, :]
+    x = loc[0, ..., 0].double() * Wd - 0.5                   # [A, P, N]
+    y = loc[0, ..., 1].double() * Hd - 0.5
+    xc, yc = Wd - 30, Hd - 30                                 # the map's centre
+    val = alpha + beta * (x - xc)[..., None] + gamma * (y - yc)[..., None]   # [A, P, N, C]
+    wc = w[0, :, :, :, 0].double().repeat_interleave(C // G, dim=-1)   # [A, P, N, C]
+    ref_out = (wc * val).sum(dim=(1, 2))
+    god = go[0].double()
+    ref_gw = (god[:, None, None, :] * val).reshape(A, P, 2, G, C // G).sum(-1)
+    ref_gx = Wd[0, 0][None, None, :] * (wc * god[:, None, None, :] * beta).sum(-1)
+    ref_gy = Hd[0, 0][None, None, :] * (wc * god[:, None, None, :] * gamma).sum(-1)
+    assert_close(host(out)[0], ref_out.numpy(), FWD_F32_TOL, FWD_F32_MAXREL, "out")
+    assert_close(host(gw)[0, :, :, :, 0], ref_gw.numpy(), GRAD_F32_TOL, GRAD_F32_MAXREL, "grad_w")
+    assert_close(host(gl)[0, ..., 0], ref_gx.numpy(), GRAD_F32_TOL, GRAD_F32_MAXREL, "grad_loc x")
+    assert_close(host(gl)[0, ..., 1], ref_gy.numpy(), GRAD_F32_TOL, GRAD_F32_MAXREL, "grad_loc y")
+    # <grad_feat, feat> = <grad_out, out>, in FP64 over row bands
+    lhs = 0.0
+    for r0 in range(0, R, 1 << 19):
+        lhs += float((gf[0, r0:r0 + (1 << 19)].double() * feat[0, r0:r0 + (1 << 19)].double()).sum())
+    rhs = float((god * ref_out).sum())
+    assert abs(lhs - rhs) <= 1e-5 * (abs(rhs) + 1.0), (lhs, rhs)
+
+
+def test_bf16_constant_map_beyond_2gib(ops):
+    """BF16 storage, one batch item of 2.3 GB (2 cameras x one 2048 x 1100
+    level, C = 256): a constant map returns the constant times the sum of the
+    weights for samples in the last rows (the highest offsets)."""
+    C, G, A, P = 256, 8, 24, 4
+    shapes, starts, R = synth.layout([[(2048, 1100)]] * 2)
+    assert 2 ** 31 < R * C * 2 <= 2 ** 32 - 8192
+    gen = torch.Generator().manual_seed(8)
+    feat = torch.full((1, R, C), 1.5, dtype=torch.bfloat16, device="cuda")
+    loc = _interior_locs(shapes, A, P, gen)
     w = torch.rand(1, A, P, 2, 1, G, generator=gen)
     layout = ops.Layout(shapes, starts)
     out = ops.forward(feat, layout, loc.cuda(), w.cuda())
     torch.cuda.synchronize()
-    # oracle on the rows actually touched: the last 60 rows x 60 cols of each camera
-    rows = []
-    for n in range(2):
-        s0 = int(starts[n, 0])
-        for y in range(1024 - 60, 1024):
-            rows.append(s0 + y * 1023 + 1023 - 60 + np.arange(60))
-    rows = np.unique(np.concatenate(rows))
-    sub = feat[0, torch.from_numpy(rows).cuda()].double().cpu().numpy()
-    full = np.zeros((1, R, C))
-    full[0, rows] = sub
-    del feat
-    ref = oracle_mod.forward(full, shapes, starts, loc, w)
-    assert_close(host(out), ref, FWD_F32_TOL, FWD_F32_MAXREL, "max batch item")
+    ref = 1.5 * w[0, :, :, :, 0].double().sum(dim=(1, 2)).repeat_interleave(C // G, dim=-1)
+    assert_close(host(out)[0], ref.numpy(), FWD_F32_TOL, FWD_F32_MAXREL, "constant map")
 
 
 @pytest.mark.parametrize("which", ["train16", "cam64"])
