@@ -111,14 +111,21 @@ __device__ __forceinline__ BwdAnchor bwd_anchor_ctx(const OpArgs& a, int ba, con
 // group's first lane, sum of w * (sum over the group's channels of grad_out
 // * value) -- <grad_out, the anchor's feature in this view> -- for the
 // fused form's score gradient.
-template <class FT, int CPL, int LPG, int LPS>
+// FULL: grad_weights and grad_sampling_loc wanted, no float-atomic grad_feat
+// and no fusion dot product -- the common case, with those tests folded away.
+template <class FT, int CPL, int LPG, int LPS, bool FULL = false>
 __device__ __forceinline__ void bwd_chunk_w(const OpArgs& a, const StageSlot& st, int nj,
-                                            const Geo* geo, const Lanes& q, const BwdAnchor& x,
+                                            const Geo* geo, const Lanes& q, const BwdAnchor& x0,
                                             const float* go, float out_scale, float* dot) {
     using RowT = Row<FT, CPL>;
     const int L = a.L, G = a.G, LG = L * G;
     const int lpg = (a.C / a.G) / CPL;             // lanes of one group (a power of two)
-    const bool need_vals = x.gwout || x.glout || dot;
+    BwdAnchor x = x0;
+    if constexpr (FULL) {
+        x.gacc = nullptr;
+        dot = nullptr;
+    }
+    const bool need_vals = FULL || x.gwout || x.glout || dot;
     // byte offset of a row -> float offset in the FP32 accumulator
     constexpr int kOffToAcc = FT::kBytes == 4 ? 2 : FT::kBytes == 2 ? 1 : 0;
     for (int jj = q.sub; jj < nj; jj += q.spw) {
@@ -157,12 +164,12 @@ __device__ __forceinline__ void bwd_chunk_w(const OpArgs& a, const StageSlot& st
                 for (int i = 0; i < CPL; ++i) sum = fmaf(go[i], f[i], sum);
                 d[c] = sum;
             }
-            if (x.gwout || dot) {
+            if (FULL || x.gwout || dot) {
                 float tw = t.cw[0] * d[0] + t.cw[1] * d[1] + t.cw[2] * d[2] + t.cw[3] * d[3];
                 tw = group_sum_w<LPG>(tw, lpg);
                 if ((q.lane & (lpg - 1)) == 0) {
-                    if (x.gwout) x.gwout[(size_t)src * LG + l * G + q.g] = tw * out_scale;
-                    if (dot) *dot = fmaf(wl, tw, *dot);
+                    if (FULL || x.gwout) x.gwout[(size_t)src * LG + l * G + q.g] = tw * out_scale;
+                    if (!FULL && dot) *dot = fmaf(wl, tw, *dot);
                 }
             }
             // d val / dx = hy (F01 - F00) + ly (F11 - F10); x = u W - 0.5
@@ -172,7 +179,7 @@ __device__ __forceinline__ void bwd_chunk_w(const OpArgs& a, const StageSlot& st
             gx += (float)gm.W * wl * (hy * (d[1] - d[0]) + fr.y * (d[3] - d[2]));
             gy += (float)gm.H * wl * (hx * (d[2] - d[0]) + fr.x * (d[3] - d[1]));
         }
-        if (x.glout) {
+        if (FULL || x.glout) {
             gx = group_sum_w<LPS>(gx, q.lps);
             gy = group_sum_w<LPS>(gy, q.lps);
             if ((q.lane & (q.lps - 1)) == 0) {
@@ -193,7 +200,9 @@ __device__ __forceinline__ void bwd_chunk(const OpArgs& a, const StageSlot& st, 
                                           const float* go, float out_scale = 1.f,
                                           float* dot = nullptr) {
     const int lpg = (a.C / a.G) / CPL;
-    if (lpg == 4 && q.lps == 32)
+    if (lpg == 4 && q.lps == 32 && x.gwout && x.glout && !x.gacc && !dot)
+        bwd_chunk_w<FT, CPL, 4, 32, true>(a, st, nj, geo, q, x, go, out_scale, nullptr);
+    else if (lpg == 4 && q.lps == 32)
         bwd_chunk_w<FT, CPL, 4, 32>(a, st, nj, geo, q, x, go, out_scale, dot);
     else if (lpg == 8 && q.lps == 64)
         bwd_chunk_w<FT, CPL, 8, 64>(a, st, nj, geo, q, x, go, out_scale, dot);
