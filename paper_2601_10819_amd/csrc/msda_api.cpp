@@ -268,17 +268,15 @@ SortedWs sorted_layout(uint64_t nrec, uint64_t ncells, uint64_t nregions) {
     return w;
 }
 
-// Cells and 4x4 tiles of one batch item (from the host mirror of the shapes).
-// outside_cell: each region's cells are its (H+1)(W+1) bilinear cells and
-// one more for its samples outside the level (the single call's numbering,
-// region_tables_kernel); the batched form numbers (H+1)(W+1) per region.
-void cells_and_tiles(const msda_desc* d, uint64_t* cells, uint64_t* tiles,
-                     bool outside_cell = true) {
+// Cells and 4x4 tiles of one batch item (from the host mirror of the shapes):
+// each region's cells are its (H+1)(W+1) bilinear cells and one more for its
+// samples outside the level (region_tables_kernel, batch_tables_kernel).
+void cells_and_tiles(const msda_desc* d, uint64_t* cells, uint64_t* tiles) {
     *cells = *tiles = 0;
     const int64_t NL = (int64_t)d->num_cams * d->num_levels;
     for (int64_t i = 0; i < NL; ++i) {
         const uint64_t H = d->host_spatial_shapes[2 * i], W = d->host_spatial_shapes[2 * i + 1];
-        *cells += (H + 1) * (W + 1) + (outside_cell ? 1 : 0);
+        *cells += (H + 1) * (W + 1) + 1;
         *tiles += ((H + msda::kTileH - 1) / msda::kTileH) * ((W + msda::kTileW - 1) / msda::kTileW);
     }
 }
@@ -521,14 +519,8 @@ VisibleWs visible_layout(const msda_desc* d, size_t at) {
 // records per (batch item, region) bucket, every region's local keys within
 // the composite key, and the bucket's LDS within the device's per-block
 // limit (looked up once per device; no bucket sort if that fails).
-static bool bucket_sort_fits(const msda_desc* d) {
-    const uint64_t ap = (uint64_t)d->num_anchors * (uint64_t)d->num_points;
-    if (ap == 0 || ap > msda::kBucketMaxRecords) return false;
-    const int64_t NL = (int64_t)d->num_cams * d->num_levels;
-    for (int64_t i = 0; i < NL; ++i) {
-        const uint64_t H = d->host_spatial_shapes[2 * i], W = d->host_spatial_shapes[2 * i + 1];
-        if ((H + 1) * (W + 1) + 1 > msda::kBucketMaxKeys) return false;
-    }
+// Whether a bucket-sort block of ap records fits the current device's LDS.
+static bool bucket_lds_fits(uint64_t ap) {
     static int max_lds[64] = {0};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
@@ -540,6 +532,23 @@ static bool bucket_sort_fits(const msda_desc* d) {
         max_lds[dev] = v;
     }
     return max_lds[dev] > 0 && msda::bucket_sort_lds_bytes((uint32_t)ap) <= (size_t)max_lds[dev];
+}
+
+// Whether the region tables' cells of every region (bilinear cells and the
+// outside cell) fit the bucket sort's composite keys.
+static bool bucket_keys_fit(const int32_t* shapes, int64_t regions) {
+    for (int64_t i = 0; i < regions; ++i) {
+        const uint64_t H = shapes[2 * i], W = shapes[2 * i + 1];
+        if ((H + 1) * (W + 1) + 1 > msda::kBucketMaxKeys) return false;
+    }
+    return true;
+}
+
+static bool bucket_sort_fits(const msda_desc* d) {
+    const uint64_t ap = (uint64_t)d->num_anchors * (uint64_t)d->num_points;
+    if (ap == 0 || ap > msda::kBucketMaxRecords) return false;
+    return bucket_keys_fit(d->host_spatial_shapes, (int64_t)d->num_cams * d->num_levels) &&
+           bucket_lds_fits(ap);
 }
 
 // The backward's workspace without the weight flags' part.
@@ -1135,6 +1144,8 @@ struct BatchPlan {
     int view_cams;                // view order: cameras of a row at most
     int view_waves_fwd, view_waves_bwd;
     uint64_t part_bytes;          // view-order forward partials
+    uint64_t max_ap;              // the largest A_s * P
+    bool keys_fit;                // every region's cells fit the bucket sort's keys
 };
 
 // Validates the batch (every scene against its host mirrors) and sizes it.
@@ -1148,6 +1159,7 @@ msda_status plan_batch(const msda_batch* b, bool backward, BatchPlan* p) {
     if (b->flags & kWeightFlags)
         return fail(MSDA_ERR_UNSUPPORTED, "the batched form takes no weight flags");
     *p = BatchPlan{};
+    p->keys_fit = true;
     const int eb = elem_bytes(b->feat_dtype);
     for (int s = 0; s < b->num_scenes; ++s) {
         const msda_scene& sc = b->host_scenes[s];
@@ -1186,9 +1198,12 @@ msda_status plan_batch(const msda_batch* b, bool backward, BatchPlan* p) {
         p->max_cams = std::max(p->max_cams, sc.num_cams);
         p->max_batch_bytes = std::max<int64_t>(p->max_batch_bytes, bb);
         uint64_t cells = 0, tiles = 0;
-        cells_and_tiles(&d, &cells, &tiles, false);
+        cells_and_tiles(&d, &cells, &tiles);
         p->cells += cells;
         p->tiles += tiles;
+        p->max_ap = std::max<uint64_t>(p->max_ap, (uint64_t)sc.num_anchors * b->num_points);
+        if (!bucket_keys_fit(d.host_spatial_shapes, (int64_t)sc.num_cams * b->num_levels))
+            p->keys_fit = false;
         // heavy (scene, level): camera 0's area at most 1/16 of its largest level
         int64_t max_area = 0;
         for (int l = 0; l < b->num_levels; ++l)
@@ -1425,9 +1440,15 @@ msda_status msda_backward_batched(const msda_batch* b, void* workspace, size_t w
     const hipStream_t s = (hipStream_t)stream;
     hipError_t e = msda::launch_batch_tables(a, true, s);
     if (e != hipSuccess) return hip_fail(e, "batch tables");
+    // grad_feat records bucketed per (scene, region) when every bucket fits
+    // one bucket-sort block (sorted by launch_bucket_sort_batched), else in
+    // sample order with batch-global cells (the global radix sort)
+    const bool bucketed = gf && p.keys_fit && p.max_ap <= msda::kBucketMaxRecords &&
+                          bucket_lds_fits(p.max_ap);
     if (gf) {
         a.rec_key = reinterpret_cast<uint32_t*>(ws + w.keys_a);
         a.rec_frac = reinterpret_cast<float2*>(ws + w.frac);
+        a.rec_bucketed = bucketed ? 1 : 0;
         // rows outside every region are not visited by a tile
         for (int sc = 0; sc < b->num_scenes; ++sc) {
             msda_desc d = {};
@@ -1461,12 +1482,16 @@ msda_status msda_backward_batched(const msda_batch* b, void* workspace, size_t w
     if (!gf) return ok();
     uint32_t* sorted = nullptr;
     uint32_t* off = reinterpret_cast<uint32_t*>(ws + w.off);
-    e = msda::launch_sort_records(reinterpret_cast<uint32_t*>(ws + w.keys_a),
-                                  reinterpret_cast<uint32_t*>(ws + w.keys_b),
-                                  reinterpret_cast<uint32_t*>(ws + w.vals_a),
-                                  reinterpret_cast<uint32_t*>(ws + w.vals_b), (uint32_t)p.samples,
-                                  (uint32_t)p.cells, reinterpret_cast<uint32_t*>(ws + w.scratch),
-                                  off, &sorted, s);
+    if (bucketed)
+        e = msda::launch_bucket_sort_batched(a, (uint32_t)p.max_ap,
+                                             reinterpret_cast<uint32_t*>(ws + w.vals_a), off, s);
+    else
+        e = msda::launch_sort_records(reinterpret_cast<uint32_t*>(ws + w.keys_a),
+                                      reinterpret_cast<uint32_t*>(ws + w.keys_b),
+                                      reinterpret_cast<uint32_t*>(ws + w.vals_a),
+                                      reinterpret_cast<uint32_t*>(ws + w.vals_b),
+                                      (uint32_t)p.samples, (uint32_t)p.cells,
+                                      reinterpret_cast<uint32_t*>(ws + w.scratch), off, &sorted, s);
     if (e != hipSuccess) return hip_fail(e, "sort grad_feat records");
     a.vals = sorted ? sorted : reinterpret_cast<uint32_t*>(ws + w.vals_a);
     a.off = off;

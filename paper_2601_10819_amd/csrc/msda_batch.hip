@@ -81,19 +81,20 @@ __global__ void __launch_bounds__(256) batch_tables_kernel(BatchArgs b, int back
     }
     __syncthreads();
 
-    // first cell of every region: exclusive scan of (H+1)(W+1), regions in order
+    // first cell of every region: exclusive scan of (H+1)(W+1) + 1 (the
+    // bilinear cells and the region's outside cell), regions in order
     {
         const u32 per = (R + blockDim.x - 1) / blockDim.x;
         const u32 g0 = tid * per;
         u32 sum = 0;
         for (u32 k = 0; k < per; ++k)
-            if (g0 + k < R) sum += ((u32)sh_h[g0 + k] + 1u) * ((u32)sh_w[g0 + k] + 1u);
+            if (g0 + k < R) sum += ((u32)sh_h[g0 + k] + 1u) * ((u32)sh_w[g0 + k] + 1u) + 1u;
         u32 total;
         u32 run = block_inclusive_scan(sum, lds4, &total) - sum;
         for (u32 k = 0; k < per; ++k) {
             if (g0 + k < R) {
                 b.t.cell_start[g0 + k] = run;
-                run += ((u32)sh_h[g0 + k] + 1u) * ((u32)sh_w[g0 + k] + 1u);
+                run += ((u32)sh_h[g0 + k] + 1u) * ((u32)sh_w[g0 + k] + 1u) + 1u;
             }
         }
     }

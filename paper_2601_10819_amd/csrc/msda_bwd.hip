@@ -127,7 +127,8 @@ __global__ void __launch_bounds__(512) msda_bwd_view_kernel(OpArgs a) {
 }
 
 // Batched backward gather: persistent workgroups stride over the anchors of
-// all scenes; records go to the global (all-scene) cell and sample spaces.
+// all scenes; records go to the batch's sample space, per (scene, region)
+// bucket with local cells or at the sample index with batch-global cells.
 template <class FT, int CPL>
 __global__ void __launch_bounds__(512) msda_bwd_batched_kernel(BatchArgs b) {
     extern __shared__ __align__(16) unsigned char smem[];

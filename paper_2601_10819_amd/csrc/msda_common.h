@@ -589,6 +589,7 @@ __device__ __forceinline__ OpArgs scene_view(const BatchArgs& b, int s, int feat
     a.cell_offset = 0;
     a.no_cell = b.total_cells;
     a.sample_offset = b.rec_key ? b.t.sample_start[s] : 0u;
+    a.rec_bucket_ap = b.rec_key && b.rec_bucketed ? (u32)sc.num_anchors * (u32)b.P : 0u;
     a.B = 1;
     a.N = sc.num_cams;
     a.L = b.L;

@@ -90,7 +90,7 @@ __device__ __forceinline__ BwdAnchor bwd_anchor_ctx(const OpArgs& a, int ba, con
     x.rec.val = nullptr;
     x.rec.cbase = 0u;
     x.rec.bucket_ap = a.rec_bucket_ap;
-    x.rec.bucket_base = (u32)b * (u32)(a.N * a.L) * a.rec_bucket_ap +
+    x.rec.bucket_base = a.sample_offset + (u32)b * (u32)(a.N * a.L) * a.rec_bucket_ap +
                         (u32)(ba - b * a.A) * (u32)a.P;
     x.rec.N = (u32)a.N;
     x.feat = make_rsrc(static_cast<const char*>(a.feat) + (size_t)b * a.batch_bytes,

@@ -119,6 +119,7 @@ struct BatchArgs {
     int32_t view_cams;            // view order: cameras of a row at most (geometry slice)
     uint32_t* rec_key;            // backward, grad_feat records (or nullptr)
     float2* rec_frac;
+    int32_t rec_bucketed;         // records written per (scene, region) bucket (launch_bucket_sort_batched)
     // tiled reduction
     const uint32_t* vals;
     const uint32_t* off;
@@ -252,6 +253,15 @@ hipError_t launch_bucket_sort(const uint32_t* keys, const int32_t* shapes, int32
                               int32_t L, int32_t A, int32_t P, uint32_t cells_per_item,
                               uint32_t* vals, uint32_t* off, uint32_t* cell_start,
                               uint32_t* tile_start, uint32_t* tile_region, hipStream_t s);
+// The batched form's record sort: bucket k = the batch's region k (scene s,
+// region r of it), A_s*P records at sample_start[s] + r*A_s*P, keyed by
+// local cell; writes the sorted global sample indices to vals (bucket k's
+// part at the same place) and off[] of the batch's cells (cell_start of the
+// batch tables, (H+1)(W+1) + 1 per region), off[total_cells] = total
+// samples. max_ap: the largest A_s*P (<= kBucketMaxRecords; LDS
+// bucket_sort_lds_bytes(max_ap)).
+hipError_t launch_bucket_sort_batched(const BatchArgs& b, uint32_t max_ap, uint32_t* vals,
+                                      uint32_t* off, hipStream_t s);
 // In-place exclusive scan of n words; partial: scan_scratch_words(n) words.
 hipError_t launch_exclusive_scan(uint32_t* x, uint32_t n, uint32_t* partial, hipStream_t s);
 size_t scan_scratch_words(uint32_t n);

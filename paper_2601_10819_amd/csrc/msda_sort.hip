@@ -297,7 +297,8 @@ radix_scatter_kernel(const u32* __restrict__ keys_in, const u32* __restrict__ va
 //
 // The dense single call's records arrive bucketed (see RecordSink): bucket k
 // = (batch item b, region r) holds the A*P samples of region r in (anchor,
-// keypoint) order -- which is their sample order -- keyed by local cell.
+// keypoint) order -- which is their sample order -- keyed by local cell
+// (the batched form: bucket k = the batch's region k, A_s*P samples).
 // Every sample of a cell lies in one bucket, so sorting each bucket by key,
 // stably, gives exactly the order of the global sort (each cell's records in
 // sample order), in one launch and without leaving LDS.
@@ -357,57 +358,32 @@ __device__ __forceinline__ u32 bucket_block_scan(u32 v, u32* lds, u32* total) {
     return before + x - v;
 }
 
-template <int E>
-__global__ void __launch_bounds__(kBucketThreads) bucket_sort_kernel(BucketSortArgs p) {
-    extern __shared__ __align__(16) u32 bsm[];
-    u32* buf = bsm;                                        // [ap] composites
-    u32* wcount = bsm + p.ap;                              // [waves][256]
-    u32* dstart = wcount + kBucketWaves * kMaxDigits;      // [256]
-    u32* lds16 = dstart + kMaxDigits;                      // [16] wave totals
-    u32* lds_scan = lds16 + 16;                            // [16] block scan
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const u32 k = blockIdx.x;
-    const int NL = p.N * p.L;
-    const int b = (int)(k / (u32)NL), r = (int)(k % (u32)NL);
-
-    // The region tables (NL <= 1024: one region per thread): the first cell
-    // of every region ((H+1)(W+1) bilinear cells and the outside cell each)
-    // -- this block's own, and block 0 writes them all -- and, over the
-    // processing slots (coarse levels first: slot o -> region
-    // (o % N) * L + (L - 1 - o / N)), the first tile and region of each slot.
-    {
-        u32 cells = 0, tiles = 0;
-        int rs = 0;
-        if (tid < NL) {
-            cells = (u32)(p.shapes[2 * tid] + 1) * (u32)(p.shapes[2 * tid + 1] + 1) + 1u;
-            rs = (tid % p.N) * p.L + (p.L - 1 - tid / p.N);
-            tiles = ((u32)(p.shapes[2 * rs] + kTileH - 1) / kTileH) *
-                    ((u32)(p.shapes[2 * rs + 1] + kTileW - 1) / kTileW);
-        }
-        u32 tc, tt;
-        const u32 cs = bucket_block_scan(cells, lds_scan, &tc);
-        const u32 ts = bucket_block_scan(tiles, lds_scan, &tt);
-        if (tid == r) dstart[0] = cs;                      // this bucket's region
-        if (k == 0 && tid < NL) {
-            p.cell_start[tid] = cs;
-            p.tile_start[tid] = ts;
-            p.tile_region[tid] = (u32)rs;
-            if (tid == NL - 1) p.tile_start[NL] = tt;
-        }
-        __syncthreads();
+// LDS of a bucket-sort block: [ap] composites, per-wave digit counts,
+// digit starts, wave totals, block-scan scratch.
+struct BucketLds {
+    u32 *buf, *wcount, *dstart, *lds16, *lds_scan;
+    __device__ BucketLds(u32* bsm, u32 ap_max) {
+        buf = bsm;
+        wcount = bsm + ap_max;
+        dstart = wcount + kBucketWaves * kMaxDigits;
+        lds16 = dstart + kMaxDigits;
+        lds_scan = lds16 + 16;
     }
-    const u32 cstart = dstart[0];
-    __syncthreads();                                       // dstart is reused below
-    const u32 H = (u32)p.shapes[2 * r], W = (u32)p.shapes[2 * r + 1];
-    const u32 nkeys = (H + 1) * (W + 1) + 1;               // local keys, the outside cell last
+};
+
+// Sorts one bucket of ap <= 64*E*16 records by key (keys[j] < nkeys, larger
+// keys clamped to nkeys - 1), stably: leaves the composites key << 15 | j in
+// key order in m.buf[0, ap).
+template <int E>
+__device__ __forceinline__ void bucket_sort_core(const u32* __restrict__ keys, u32 ap, u32 nkeys,
+                                                 const BucketLds& m) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int kb = 1;
     while (kb < 32 && ((nkeys - 1) >> kb) != 0) ++kb;
     const int passes = (kb + kMaxDigitBits - 1) / kMaxDigitBits;
     const int bits = (kb + passes - 1) / passes;
     const int digits = 1 << bits;
     const u32 mask = (u32)digits - 1u;
-    const u32 ap = p.ap;
-    const u32* keys = p.keys + (size_t)k * ap;
 
     u32 v[E], rank[E];
     const u32 j0 = (u32)(wave * 64 * E + lane);
@@ -417,11 +393,11 @@ __global__ void __launch_bounds__(kBucketThreads) bucket_sort_kernel(BucketSortA
         v[e] = j < ap ? (min(keys[j], nkeys - 1u) << kBucketPosBits) | j : 0u;
     }
     const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    u32* const run = wcount + wave * kMaxDigits;
+    u32* const run = m.wcount + wave * kMaxDigits;
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = kBucketPosBits + pass * bits;
         for (int i = tid; i < kBucketWaves * digits; i += kBucketThreads)
-            wcount[(i / digits) * kMaxDigits + (i % digits)] = 0u;
+            m.wcount[(i / digits) * kMaxDigits + (i % digits)] = 0u;
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -447,8 +423,8 @@ __global__ void __launch_bounds__(kBucketThreads) bucket_sort_kernel(BucketSortA
         if (tid < digits) {
 #pragma unroll
             for (int w = 0; w < kBucketWaves; ++w) {
-                const u32 c = wcount[w * kMaxDigits + tid];
-                wcount[w * kMaxDigits + tid] = cnt;
+                const u32 c = m.wcount[w * kMaxDigits + tid];
+                m.wcount[w * kMaxDigits + tid] = cnt;
                 cnt += c;
             }
         }
@@ -459,54 +435,136 @@ __global__ void __launch_bounds__(kBucketThreads) bucket_sort_kernel(BucketSortA
             const u32 t = __shfl_up(x, dd, 64);
             if (lane >= dd) x += t;
         }
-        if (lane == 63 && wave < 4) lds16[wave] = x;
+        if (lane == 63 && wave < 4) m.lds16[wave] = x;
         __syncthreads();
         if (tid < digits) {
             u32 before = 0;
-            for (int w = 0; w < wave; ++w) before += lds16[w];
-            dstart[tid] = before + x - cnt;
+            for (int w = 0; w < wave; ++w) before += m.lds16[w];
+            m.dstart[tid] = before + x - cnt;
         }
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             if (j0 + (u32)(e * 64) < ap) {
                 const u32 d = (v[e] >> shift) & mask;
-                buf[dstart[d] + wcount[wave * kMaxDigits + d] + rank[e]] = v[e];
+                m.buf[m.dstart[d] + m.wcount[wave * kMaxDigits + d] + rank[e]] = v[e];
             }
         }
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const u32 j = j0 + (u32)(e * 64);
-            if (j < ap) v[e] = buf[j];
+            if (j < ap) v[e] = m.buf[j];
         }
         // the next pass clears wcount only after this barrier: every wave
         // has read its places
         __syncthreads();
     }
+}
 
-    // outputs: buf holds the bucket's composites in key order
-    const u32 n_ = (u32)p.N, L_ = (u32)p.L;
-    const u32 nr = (u32)r / L_, lr = (u32)r % L_;
-    u32* vals = p.vals + (size_t)k * ap;
-    for (u32 i = (u32)tid; i < ap; i += kBucketThreads) {
-        const u32 pos = buf[i] & ((1u << kBucketPosBits) - 1u);
-        const u32 a = pos / (u32)p.P, pp = pos - a * (u32)p.P;
-        // sample index of (b, a, pp, nr, lr)
-        vals[i] = ((((u32)b * (u32)p.A + a) * (u32)p.P + pp) * n_ + nr) * L_ + lr;
-    }
-    // first position of each local cell: element i starts the cells in
-    // (key[i-1], key[i]] (from 0 for the first), and the cells after the
-    // last key start at the bucket's end; every cell is written once
-    u32* off = p.off + (size_t)b * p.cells_per_item + cstart;
-    const u32 base = k * ap;
-    for (u32 i = (u32)tid; i <= ap; i += kBucketThreads) {
+// The first position of each of a bucket's nkeys local cells from its
+// sorted composites: element i starts the cells in (key[i-1], key[i]]
+// (from 0 for the first), and the cells after the last key start at the
+// bucket's end; every cell is written once. off: the bucket's first cell;
+// base: the bucket's first record.
+__device__ __forceinline__ void bucket_cell_starts(const u32* buf, u32 ap, u32 nkeys, u32 base,
+                                                   u32* __restrict__ off) {
+    for (u32 i = (u32)threadIdx.x; i <= ap; i += kBucketThreads) {
         const u32 c1 = i < ap ? buf[i] >> kBucketPosBits : nkeys - 1u;
         const u32 c0 = i == 0 ? 0u : (buf[i - 1] >> kBucketPosBits) + 1u;
         for (u32 c = c0; c <= c1; ++c) off[c] = base + i;
     }
+}
+
+template <int E>
+__global__ void __launch_bounds__(kBucketThreads) bucket_sort_kernel(BucketSortArgs p) {
+    extern __shared__ __align__(16) u32 bsm[];
+    const BucketLds m(bsm, p.ap);
+    const int tid = threadIdx.x;
+    const u32 k = blockIdx.x;
+    const int NL = p.N * p.L;
+    const int b = (int)(k / (u32)NL), r = (int)(k % (u32)NL);
+
+    // The region tables (NL <= 1024: one region per thread): the first cell
+    // of every region ((H+1)(W+1) bilinear cells and the outside cell each)
+    // -- this block's own, and block 0 writes them all -- and, over the
+    // processing slots (coarse levels first: slot o -> region
+    // (o % N) * L + (L - 1 - o / N)), the first tile and region of each slot.
+    {
+        u32 cells = 0, tiles = 0;
+        int rs = 0;
+        if (tid < NL) {
+            cells = (u32)(p.shapes[2 * tid] + 1) * (u32)(p.shapes[2 * tid + 1] + 1) + 1u;
+            rs = (tid % p.N) * p.L + (p.L - 1 - tid / p.N);
+            tiles = ((u32)(p.shapes[2 * rs] + kTileH - 1) / kTileH) *
+                    ((u32)(p.shapes[2 * rs + 1] + kTileW - 1) / kTileW);
+        }
+        u32 tc, tt;
+        const u32 cs = bucket_block_scan(cells, m.lds_scan, &tc);
+        const u32 ts = bucket_block_scan(tiles, m.lds_scan, &tt);
+        if (tid == r) m.dstart[0] = cs;                    // this bucket's region
+        if (k == 0 && tid < NL) {
+            p.cell_start[tid] = cs;
+            p.tile_start[tid] = ts;
+            p.tile_region[tid] = (u32)rs;
+            if (tid == NL - 1) p.tile_start[NL] = tt;
+        }
+        __syncthreads();
+    }
+    const u32 cstart = m.dstart[0];
+    __syncthreads();                                       // dstart is reused below
+    const u32 H = (u32)p.shapes[2 * r], W = (u32)p.shapes[2 * r + 1];
+    const u32 nkeys = (H + 1) * (W + 1) + 1;               // local keys, the outside cell last
+    const u32 ap = p.ap;
+    bucket_sort_core<E>(p.keys + (size_t)k * ap, ap, nkeys, m);
+
+    // outputs: m.buf holds the bucket's composites in key order
+    const u32 n_ = (u32)p.N, L_ = (u32)p.L;
+    const u32 nr = (u32)r / L_, lr = (u32)r % L_;
+    u32* vals = p.vals + (size_t)k * ap;
+    for (u32 i = (u32)tid; i < ap; i += kBucketThreads) {
+        const u32 pos = m.buf[i] & ((1u << kBucketPosBits) - 1u);
+        const u32 a = pos / (u32)p.P, pp = pos - a * (u32)p.P;
+        // sample index of (b, a, pp, nr, lr)
+        vals[i] = ((((u32)b * (u32)p.A + a) * (u32)p.P + pp) * n_ + nr) * L_ + lr;
+    }
+    bucket_cell_starts(m.buf, ap, nkeys, k * ap, p.off + (size_t)b * p.cells_per_item + cstart);
     if (k + 1 == gridDim.x && tid == 0)
         p.off[(size_t)p.B * p.cells_per_item] = (u32)gridDim.x * ap;
+}
+
+// The batched form: bucket k = the batch's region k, scene s (the last with
+// region_start[s] <= k), region r = k - region_start[s] = n*L + l of it,
+// holding the scene's A_s*P samples of that region in (anchor, keypoint)
+// order at sample_start[s] + r*A_s*P. Buckets, and the cells of the batch
+// tables, follow the regions in order, so the per-bucket results form the
+// global sorted order and off[] of the whole batch.
+template <int E>
+__global__ void __launch_bounds__(kBucketThreads) bucket_sort_batched_kernel(BatchArgs b,
+                                                                             u32 ap_max,
+                                                                             u32* __restrict__ vals,
+                                                                             u32* __restrict__ off) {
+    extern __shared__ __align__(16) u32 bsm[];
+    const BucketLds m(bsm, ap_max);
+    const u32 k = blockIdx.x;
+    const int s = scene_of(b.t.region_start, b.S, k);
+    const msda_scene& sc = b.scenes[s];
+    const u32 r = k - b.t.region_start[s];
+    const u32 N = (u32)sc.num_cams, L = (u32)b.L, P = (u32)b.P;
+    const u32 ap = (u32)sc.num_anchors * P;
+    const u32 base = b.t.sample_start[s] + r * ap;
+    const u32 H = (u32)sc.spatial_shapes[2 * r], W = (u32)sc.spatial_shapes[2 * r + 1];
+    const u32 nkeys = (H + 1) * (W + 1) + 1;               // local keys, the outside cell last
+    if (ap > 0) bucket_sort_core<E>(b.rec_key + base, ap, nkeys, m);
+
+    const u32 nr = r / L, lr = r % L;
+    for (u32 i = (u32)threadIdx.x; i < ap; i += kBucketThreads) {
+        const u32 pos = m.buf[i] & ((1u << kBucketPosBits) - 1u);
+        const u32 a = pos / P, pp = pos - a * P;
+        vals[base + i] = b.t.sample_start[s] + ((a * P + pp) * N + nr) * L + lr;
+    }
+    bucket_cell_starts(m.buf, ap, nkeys, base, off + b.t.cell_start[k]);
+    if (k + 1 == gridDim.x && threadIdx.x == 0) off[b.total_cells] = b.total_samples;
 }
 
 hipError_t launch_bucket_sort(const u32* keys, const int32_t* shapes, int32_t B, int32_t N,
@@ -544,6 +602,33 @@ hipError_t launch_bucket_sort(const u32* keys, const int32_t* shapes, int32_t B,
     else {
         mark_end(s);
         return hipErrorInvalidValue;               // ap > kBucketMaxRecords: the caller's check
+    }
+    mark_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_sort_batched(const BatchArgs& b, u32 max_ap, u32* vals, u32* off,
+                                      hipStream_t s) {
+    const unsigned grid = b.total_regions;
+    if (grid == 0) return hipSuccess;
+    const size_t lds = bucket_sort_lds_bytes(max_ap);
+    const u32 per_lane = (max_ap + kBucketThreads - 1) / kBucketThreads;
+    mark_begin("bucket_sort_batched", s);
+    if (per_lane <= 4)
+        hipLaunchKernelGGL(bucket_sort_batched_kernel<4>, dim3(grid), dim3(kBucketThreads), lds,
+                           s, b, max_ap, vals, off);
+    else if (per_lane <= 8)
+        hipLaunchKernelGGL(bucket_sort_batched_kernel<8>, dim3(grid), dim3(kBucketThreads), lds,
+                           s, b, max_ap, vals, off);
+    else if (per_lane <= 16)
+        hipLaunchKernelGGL(bucket_sort_batched_kernel<16>, dim3(grid), dim3(kBucketThreads), lds,
+                           s, b, max_ap, vals, off);
+    else if (per_lane <= 32)
+        hipLaunchKernelGGL(bucket_sort_batched_kernel<32>, dim3(grid), dim3(kBucketThreads), lds,
+                           s, b, max_ap, vals, off);
+    else {
+        mark_end(s);
+        return hipErrorInvalidValue;               // max_ap > kBucketMaxRecords: the caller's check
     }
     mark_end(s);
     return hipGetLastError();

@@ -221,6 +221,41 @@ def test_batched_view_order_tiny_scenes(ops):
         assert torch.equal(gw[0], batch.grad_w[s]), f"scene {s} grad_w"
 
 
+@pytest.mark.parametrize("big", ["anchors", "level"])
+def test_batched_record_sort_forms_bitwise(ops, big):
+    """The batched grad_feat records are sorted per (scene, region) bucket
+    when every scene's A*P fits one bucket-sort block (at most 2^15) and
+    every region's cells its keys (at most 2^17), else by the global radix
+    sort over the whole batch. Either way each cell's records end in sample
+    order: a batch with one scene beyond a limit (A*P = 33000, or a
+    400 x 400 level) still equals the single calls bit for bit, and so does
+    the same batch without that scene (bucketed)."""
+    if big == "anchors":
+        large = synth.small(seed=70, cams=2, A=11000, P=3, C=32, G=4,
+                            levels=((20, 30), (10, 15)))
+    else:
+        large = synth.small(seed=70, cams=2, A=40, P=3, C=32, G=4,
+                            levels=((400, 400), (10, 15)))
+    rest = [synth.small(seed=71, cams=3, A=7, P=3, C=32, G=4, levels=((12, 9), (6, 5))),
+            synth.small(seed=72, cams=1, A=1, P=3, C=32, G=4, levels=((3, 4), (2, 2)))]
+    for probs in ([large] + rest, rest):
+        print("case", big, [p.dims() for p in probs], flush=True)
+        scenes = to_scenes(ops, probs, torch.float32)
+        batch = ops.SceneBatch(scenes, tile=VIEW_TILE)
+        gen = torch.Generator(device="cuda").manual_seed(8)
+        for go in batch.grad_out:
+            go.normal_(generator=gen)
+        batch.forward()
+        batch.backward()
+        torch.cuda.synchronize()
+        for s, (feat, layout, loc, w) in enumerate(scenes):
+            gf, gl, gw = ops.backward(feat[None], layout, loc[None], w[None],
+                                      batch.grad_out[s][None], tile=VIEW_TILE)
+            torch.cuda.synchronize()
+            assert torch.equal(gf[0], batch.grad_feat[s]), f"scene {s} grad_feat"
+            assert torch.equal(gl[0], batch.grad_loc[s]), f"scene {s} grad_loc"
+            assert torch.equal(gw[0], batch.grad_w[s]), f"scene {s} grad_w"
+
 
 def test_batched_rejects_uneven_shared_sizes(ops):
     """Keypoints, levels, channels and groups are shared by a batch: a scene
