@@ -840,16 +840,11 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
     // Tiles of coarse levels collect many more samples per pixel: they come
     // first in slot order and get 4 waves each (partial sums added as a
     // tree); the rest get one wave each.
-    const uint32_t heavy = heavy_tiles(desc);
-    const uint32_t split[3] = {0u, heavy, (uint32_t)tiles};
-    for (int part = 0; part < 2; ++part) {
-        t.tile_begin = split[part];
-        t.tile_end = split[part + 1];
-        t.waves = part == 0 ? 4 : 1;
-        if (t.tile_end > t.tile_begin &&
-            (e = msda::launch_gfeat_tiles(t, desc->feat_dtype, rcpl, s)) != hipSuccess)
-            return hip_fail(e, "grad_feat tile reduction");
-    }
+    t.tile_begin = 0;
+    t.tile_split = heavy_tiles(desc);
+    t.tile_end = (uint32_t)tiles;
+    if ((e = msda::launch_gfeat_tiles(t, desc->feat_dtype, rcpl, s)) != hipSuccess)
+        return hip_fail(e, "grad_feat tile reduction");
     return finish();
 }
 
@@ -1497,15 +1492,11 @@ msda_status msda_backward_batched(const msda_batch* b, void* workspace, size_t w
     a.off = off;
     a.total_samples = (uint32_t)std::max<uint64_t>(p.samples, 1);
     a.lps_shift = log2i(b->channels / rcpl);
-    const uint32_t split[3] = {0u, (uint32_t)p.heavy_tiles, (uint32_t)p.tiles};
-    for (int part = 0; part < 2; ++part) {
-        a.tile_begin = split[part];
-        a.tile_end = split[part + 1];
-        a.waves = part == 0 ? 4 : 1;
-        if (a.tile_end > a.tile_begin &&
-            (e = msda::launch_gfeat_tiles_batched(a, b->feat_dtype, rcpl, s)) != hipSuccess)
-            return hip_fail(e, "batched grad_feat tile reduction");
-    }
+    a.tile_begin = 0;
+    a.tile_split = (uint32_t)p.heavy_tiles;
+    a.tile_end = (uint32_t)p.tiles;
+    if ((e = msda::launch_gfeat_tiles_batched(a, b->feat_dtype, rcpl, s)) != hipSuccess)
+        return hip_fail(e, "batched grad_feat tile reduction");
     return ok();
 }
 

@@ -73,13 +73,15 @@ struct TileArgs {
     const float* view_scale;      // [B*A][N] per-view weight factor (fused form), or nullptr
     int32_t N, L;                 // cameras and levels (to find a sample's view)
     uint32_t tiles_per_item;
-    uint32_t tile_begin, tile_end;  // this launch's tiles of each batch item (slot order)
+    // the tiles of each batch item (slot order) to reduce: [tile_begin,
+    // tile_split) coarse (4 waves each), [tile_split, tile_end) light
+    uint32_t tile_begin, tile_split, tile_end;
     uint32_t cells_per_item;
     uint32_t nrec;                // S (records, one per sample)
     int32_t NL, B, C, G;
     int64_t R;
     int32_t lps_shift;            // log2(C / chans_per_lane)
-    int32_t waves;                // waves sharing each tile's records (1, 2 or 4)
+    int32_t waves;                // narrower lane groups: waves sharing each tile's records (set by the launcher)
     uint64_t magic;               // sample -> anchor: s / (P*N*L) == (s * magic) >> magic_shift
     int32_t magic_shift;
 };
@@ -123,8 +125,8 @@ struct BatchArgs {
     // tiled reduction
     const uint32_t* vals;
     const uint32_t* off;
-    int32_t waves;
-    uint32_t tile_begin, tile_end;
+    int32_t waves;                // narrower lane groups: as TileArgs::waves
+    uint32_t tile_begin, tile_split, tile_end;  // as TileArgs
 };
 
 enum FeatType { kF32 = 0, kBF16 = 1, kFP8 = 2, kF16 = 3 };

@@ -216,8 +216,18 @@ struct TileView {
     bool w16;                   // G % 4 == 0 and w 16-byte aligned
 };
 
+// grad_out row of a whole-wave record: the anchor (a table entry every lane
+// reads at the same address) taken as uniform, so the row address is scalar
+// arithmetic and each lane adds only its channel offset.
+__device__ __forceinline__ const float* go_row(const TileView& v, float anchor_bits) {
+    const u32 an = (u32)uniform((int)__float_as_uint(anchor_bits));
+    return v.grad_out + (size_t)an * (u32)v.C;
+}
+
 // The reduction of one tile by a group of lps lanes (grp-th group of its
-// wave, lane sl within it); `waves` waves of the block share its records.
+// wave, lane sl within it); `waves` waves of the block share its records,
+// this wave being the wt-th of them (waves == 1: wt == 0, and the other
+// waves of the block reduce tiles of their own).
 // CELLS (whole-wave groups only): walk each chunk's records cell by cell in
 // a static loop over the tile's 5x5 cells, so every record's corner ->
 // pixel map is a compile-time constant (no per-record dispatch); records of
@@ -226,9 +236,11 @@ struct TileView {
 template <class OT, int CPL, bool WHOLE_WAVE, bool CELLS, int QB = 4>
 __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, const int spw,
                                             const int grp, const int sl, const int waves,
+                                            const int wt,
                                             u32* bnd_lds, float* work) {
     constexpr int TH = kTileH, TW = kTileW;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index is uniform: chunk bounds and cell runs below stay scalar
+    const int lane = threadIdx.x & 63, wave = uniform((int)(threadIdx.x >> 6));
     const int stride = tile_entry_floats(v.G);      // floats per record-table entry
     float* tab = work + (size_t)wave * 64 * stride + (size_t)(lane - sl) * stride;
     const bool active = v.active;
@@ -277,7 +289,7 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
     // The tile's records as one flat list, in chunks of lps; chunk k goes to
     // wave k % waves. Each lane of the group fills one table entry (all the
     // chunk's loads in flight together), then the group walks the chunk.
-    for (u32 base = (u32)(wave * lps); base < total; base += (u32)(waves * lps)) {
+    for (u32 base = (u32)(wt * lps); base < total; base += (u32)(waves * lps)) {
         const int n = (int)min((u32)lps, total - base);
         if (sl < n) {
             // flat index -> (row dy, sorted position e) -> cell position dx
@@ -349,9 +361,7 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
 #pragma unroll
                             for (int k = 0; k < QB; ++k) {
                                 const float* ent = tab + (qq + k) * stride;
-                                load_go<CPL>(v.grad_out +
-                                                 (size_t)__float_as_uint(ent[4]) * v.C + c0,
-                                             gv[k]);
+                                load_go<CPL>(go_row(v, ent[4]) + (u32)c0, gv[k]);
                             }
 #pragma unroll
                             for (int k = 0; k < QB; ++k) {
@@ -363,8 +373,7 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
                         for (; qq < qe; ++qq) {
                             const float* ent = tab + qq * stride;
                             float gv[CPL];
-                            load_go<CPL>(v.grad_out + (size_t)__float_as_uint(ent[4]) * v.C + c0,
-                                         gv);
+                            load_go<CPL>(go_row(v, ent[4]) + (u32)c0, gv);
                             cell_sample<DY, DX, CPL>(acc, *reinterpret_cast<const float4*>(ent),
                                                      ent[8 + g], gv);
                         }
@@ -411,30 +420,30 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
         float* part = work;
         __syncthreads();                             // record tables are dead from here on
         for (int h = waves >> 1; h >= 1; h >>= 1) {
-            if (wave >= h && wave < 2 * h) {
+            if (wt >= h && wt < 2 * h) {
 #pragma unroll
                 for (int py = 0; py < TH; ++py)
 #pragma unroll
                     for (int px = 0; px < TW; ++px)
 #pragma unroll
                         for (int i = 0; i < CPL; ++i)
-                            part[((wave - h) * E + (py * TW + px) * CPL + i) * 64 + lane] =
+                            part[((wt - h) * E + (py * TW + px) * CPL + i) * 64 + lane] =
                                 acc[py][px][i];
             }
             __syncthreads();
-            if (wave < h) {
+            if (wt < h) {
 #pragma unroll
                 for (int py = 0; py < TH; ++py)
 #pragma unroll
                     for (int px = 0; px < TW; ++px)
 #pragma unroll
                         for (int i = 0; i < CPL; ++i)
-                            acc[py][px][i] += part[(wave * E + (py * TW + px) * CPL + i) * 64 + lane];
+                            acc[py][px][i] += part[(wt * E + (py * TW + px) * CPL + i) * 64 + lane];
             }
             __syncthreads();
         }
     }
-    if (wave != 0 || !active) return;
+    if (wt != 0 || !active) return;
     const int start = v.start;
 #pragma unroll
     for (int py = 0; py < TH; ++py) {
@@ -449,8 +458,12 @@ __device__ __forceinline__ void tile_reduce(const TileView& v, const int lps, co
     }
 }
 
+// The tile of id gt (ids run over batch items first, then processing slots
+// within [tile_begin, tile_end)) by `waves` waves of the block, this wave the
+// wt-th of them.
 template <class OT, int CPL, bool WHOLE_WAVE, bool CELLS, int QB = 4>
-__device__ __forceinline__ void gfeat_tile_body(const TileArgs& t) {
+__device__ __forceinline__ void gfeat_tile_body(const TileArgs& t, const u32 gt, const int waves,
+                                                const int wt) {
     static_assert(kTileH == 4 && kTileW == 4, "the cell dispatch is written for 4x4 tiles");
     // LDS: per lane group its tile's cell boundaries; per wave a record table
     // (64 entries of bilinear factors, anchor, cell position and G weights);
@@ -464,13 +477,10 @@ __device__ __forceinline__ void gfeat_tile_body(const TileArgs& t) {
     const int grp = WHOLE_WAVE ? 0 : lane >> t.lps_shift;
     const int sl = WHOLE_WAVE ? lane : lane & (lps - 1);   // lane within its tile's group
     u32* bnd_lds = reinterpret_cast<u32*>(smem_raw);
-    float* work = reinterpret_cast<float*>(smem_raw + bnd_lds_bytes(t.waves, t.lps_shift));
+    float* work = reinterpret_cast<float*>(smem_raw +
+                                           bnd_lds_bytes((int)(blockDim.x >> 6), t.lps_shift));
 
-    // tiles of one block: spw consecutive ids, one per lane group; ids run
-    // over processing slots (within [tile_begin, tile_end)) first, batch
-    // items second
     const u32 span = t.tile_end - t.tile_begin;
-    const u32 gt = blockIdx.x * (u32)spw + (u32)grp;
     TileView v;
     v.active = gt < span * (u32)t.B;
     const u32 tt = t.tile_begin + (v.active ? gt / (u32)t.B : 0u);
@@ -507,7 +517,7 @@ __device__ __forceinline__ void gfeat_tile_body(const TileArgs& t) {
     v.vscale = t.view_scale;
     v.N = t.N;
     v.L = t.L;
-    tile_reduce<OT, CPL, WHOLE_WAVE, CELLS, QB>(v, lps, spw, grp, sl, t.waves, bnd_lds, work);
+    tile_reduce<OT, CPL, WHOLE_WAVE, CELLS, QB>(v, lps, spw, grp, sl, waves, wt, bnd_lds, work);
 }
 
 // Whole-wave lane groups (C = 64 * CPL): at most 128 VGPRs, i.e. 4 waves per
@@ -519,20 +529,36 @@ __device__ __forceinline__ void gfeat_tile_body(const TileArgs& t) {
 // for the one-wave light tiles (fewer registers: no spills at 128), 4 for
 // the coarse tiles (measured: light 0.248 -> 0.234 ms with 2, coarse 0.180
 // -> 0.191 ms).
-template <class OT, int CPL, int QB>
+//
+// One launch for both kinds of tiles: the coarse tiles (ids below
+// (tile_split - tile_begin) * B) first, a block of 4 waves each, then the
+// light ones, 4 per block, one wave each; the light blocks fill the CUs
+// around the long coarse ones instead of waiting for them to drain.
+template <class OT, int CPL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 gfeat_tile_kernel(TileArgs t) {
-    gfeat_tile_body<OT, CPL, true, true, QB>(t);
+    const u32 heavy = (t.tile_split - t.tile_begin) * (u32)t.B;
+    const int wave = uniform((int)(threadIdx.x >> 6));
+    if (blockIdx.x < heavy)
+        gfeat_tile_body<OT, CPL, true, true, 4>(t, blockIdx.x, 4, wave);
+    else
+        gfeat_tile_body<OT, CPL, true, true, 2>(t, heavy + (blockIdx.x - heavy) * 4u + (u32)wave,
+                                                1, 0);
 }
 
+// Narrower lane groups: spw tiles per wave, t.waves waves sharing them.
 template <class OT, int CPL>
 __global__ void __launch_bounds__(256) gfeat_tile_group_kernel(TileArgs t) {
-    gfeat_tile_body<OT, CPL, false, false>(t);
+    const int spw = 64 >> t.lps_shift;
+    const u32 gt = blockIdx.x * (u32)spw + (u32)((threadIdx.x & 63) >> t.lps_shift);
+    gfeat_tile_body<OT, CPL, false, false>(t, gt, t.waves, (int)(threadIdx.x >> 6));
 }
 
-// Batched tiled reduction: tiles of all scenes' regions in slot order.
+// Batched tiled reduction: tiles of all scenes' regions in slot order; the
+// tile of id gt (from tile_begin) by `waves` waves, this wave the wt-th.
 template <class OT, int CPL, bool WHOLE_WAVE, int QB = 4>
-__device__ __forceinline__ void gfeat_tile_batched_body(const BatchArgs& b) {
+__device__ __forceinline__ void gfeat_tile_batched_body(const BatchArgs& b, const u32 gt,
+                                                        const int waves, const int wt) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int TH = kTileH, TW = kTileW;
     const int lane = threadIdx.x & 63;
@@ -541,9 +567,9 @@ __device__ __forceinline__ void gfeat_tile_batched_body(const BatchArgs& b) {
     const int grp = WHOLE_WAVE ? 0 : lane >> b.lps_shift;
     const int sl = WHOLE_WAVE ? lane : lane & (lps - 1);
     u32* bnd_lds = reinterpret_cast<u32*>(smem_raw);
-    float* work = reinterpret_cast<float*>(smem_raw + bnd_lds_bytes(b.waves, b.lps_shift));
+    float* work = reinterpret_cast<float*>(smem_raw +
+                                           bnd_lds_bytes((int)(blockDim.x >> 6), b.lps_shift));
 
-    const u32 gt = blockIdx.x * (u32)spw + (u32)grp;
     TileView v;
     v.active = gt < b.tile_end - b.tile_begin;
     const u32 tt = b.tile_begin + (v.active ? gt : 0u);
@@ -577,69 +603,112 @@ __device__ __forceinline__ void gfeat_tile_batched_body(const BatchArgs& b) {
     v.vscale = nullptr;
     v.N = 1;
     v.L = 1;
-    tile_reduce<OT, CPL, WHOLE_WAVE, WHOLE_WAVE, QB>(v, lps, spw, grp, sl, b.waves, bnd_lds,
+    tile_reduce<OT, CPL, WHOLE_WAVE, WHOLE_WAVE, QB>(v, lps, spw, grp, sl, waves, wt, bnd_lds,
                                                      work);
 }
 
-// As gfeat_tile_kernel: 4 waves per SIMD, QB = 2 for the light tiles.
-template <class OT, int CPL, int QB>
+// As gfeat_tile_kernel: the heavy tiles ([tile_begin, tile_split)) 4 waves
+// each, then the light ones 4 per block, one wave each.
+template <class OT, int CPL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 gfeat_tile_batched_kernel(BatchArgs b) {
-    gfeat_tile_batched_body<OT, CPL, true, QB>(b);
+    const u32 heavy = b.tile_split - b.tile_begin;
+    const int wave = uniform((int)(threadIdx.x >> 6));
+    if (blockIdx.x < heavy)
+        gfeat_tile_batched_body<OT, CPL, true, 4>(b, blockIdx.x, 4, wave);
+    else
+        gfeat_tile_batched_body<OT, CPL, true, 2>(
+            b, heavy + (blockIdx.x - heavy) * 4u + (u32)wave, 1, 0);
 }
 
 template <class OT, int CPL>
 __global__ void __launch_bounds__(256) gfeat_tile_batched_group_kernel(BatchArgs b) {
-    gfeat_tile_batched_body<OT, CPL, false>(b);
+    const int spw = 64 >> b.lps_shift;
+    const u32 gt = blockIdx.x * (u32)spw + (u32)((threadIdx.x & 63) >> b.lps_shift);
+    gfeat_tile_batched_body<OT, CPL, false>(b, gt, b.waves, (int)(threadIdx.x >> 6));
 }
 
 // ---------------------------------------------------------------- launchers
 
+// LDS of a tile block of `waves` waves: the cell boundaries, then the larger
+// of the record tables and the partial sums (coarse tiles: waves/2 halves of
+// a tile's accumulators).
+template <int CPL>
+static size_t tile_lds_bytes(int waves, int lps_shift, int G, bool coarse) {
+    const size_t part = coarse ? (size_t)(waves / 2) * kTileH * kTileW * CPL * 64 * 4 : 0;
+    const size_t tables = (size_t)waves * 64 * tile_entry_floats(G) * sizeof(float);
+    return bnd_lds_bytes(waves, lps_shift) + (part > tables ? part : tables);
+}
+
+// Whole-wave groups: one launch of gfeat_tile_kernel over [tile_begin,
+// tile_end) (coarse up to tile_split). Narrower groups: two launches of the
+// group kernel, 4 waves per coarse tile group, 1 per light one.
 template <class OT, int CPL>
-static hipError_t tile_launch(const TileArgs& t, hipStream_t s) {
-    const u32 spw = 64u >> t.lps_shift;
-    const u32 ntiles = (t.tile_end - t.tile_begin) * (u32)t.B;
-    const u32 blocks = (ntiles + spw - 1) / spw;
-    if (blocks == 0) return hipSuccess;
-    const size_t part = t.waves > 1 ? (size_t)(t.waves / 2) * kTileH * kTileW * CPL * 64 * 4 : 0;
-    const size_t tables = (size_t)t.waves * 64 * tile_entry_floats(t.G) * sizeof(float);
-    const size_t lds = bnd_lds_bytes(t.waves, t.lps_shift) + (part > tables ? part : tables);
-    mark_begin(t.waves > 1 ? "gfeat_tile_kernel_coarse" : "gfeat_tile_kernel", s);
-    // whole-wave groups walk each chunk cell by cell
-    if (t.lps_shift == 6 && t.waves > 1)
-        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL, 4>), dim3(blocks),
-                           dim3(64 * t.waves), lds, s, t);
-    else if (t.lps_shift == 6)
-        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL, 2>), dim3(blocks),
-                           dim3(64 * t.waves), lds, s, t);
-    else
+static hipError_t tile_launch(const TileArgs& t0, hipStream_t s) {
+    const u32 B = (u32)t0.B;
+    if (t0.lps_shift == 6) {
+        const u32 heavy = (t0.tile_split - t0.tile_begin) * B;
+        const u32 light = (t0.tile_end - t0.tile_split) * B;
+        const u32 blocks = heavy + (light + 3) / 4;
+        if (blocks == 0) return hipSuccess;
+        const size_t lds = tile_lds_bytes<CPL>(4, 6, t0.G, heavy > 0);
+        mark_begin("gfeat_tile_kernel", s);
+        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL>), dim3(blocks), dim3(256), lds, s, t0);
+        mark_end(s);
+        return hipGetLastError();
+    }
+    const u32 split[3] = {t0.tile_begin, t0.tile_split, t0.tile_end};
+    for (int part = 0; part < 2; ++part) {
+        TileArgs t = t0;
+        t.tile_begin = split[part];
+        t.tile_end = split[part + 1];
+        t.waves = part == 0 ? 4 : 1;
+        const u32 spw = 64u >> t.lps_shift;
+        const u32 blocks = ((t.tile_end - t.tile_begin) * B + spw - 1) / spw;
+        if (blocks == 0) continue;
+        const size_t lds = tile_lds_bytes<CPL>(t.waves, t.lps_shift, t.G, t.waves > 1);
+        mark_begin(t.waves > 1 ? "gfeat_tile_kernel_coarse" : "gfeat_tile_kernel", s);
         hipLaunchKernelGGL((gfeat_tile_group_kernel<OT, CPL>), dim3(blocks),
                            dim3(64 * t.waves), lds, s, t);
-    mark_end(s);
-    return hipGetLastError();
+        mark_end(s);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <class OT, int CPL>
-static hipError_t tile_batched_launch(const BatchArgs& b, hipStream_t s) {
-    const u32 spw = 64u >> b.lps_shift;
-    const u32 ntiles = b.tile_end - b.tile_begin;
-    const u32 blocks = (ntiles + spw - 1) / spw;
-    if (blocks == 0) return hipSuccess;
-    const size_t part = b.waves > 1 ? (size_t)(b.waves / 2) * kTileH * kTileW * CPL * 64 * 4 : 0;
-    const size_t tables = (size_t)b.waves * 64 * tile_entry_floats(b.G) * sizeof(float);
-    const size_t lds = bnd_lds_bytes(b.waves, b.lps_shift) + (part > tables ? part : tables);
-    mark_begin(b.waves > 1 ? "gfeat_tile_batched_coarse" : "gfeat_tile_batched", s);
-    if (b.lps_shift == 6 && b.waves > 1)
-        hipLaunchKernelGGL((gfeat_tile_batched_kernel<OT, CPL, 4>), dim3(blocks),
-                           dim3(64 * b.waves), lds, s, b);
-    else if (b.lps_shift == 6)
-        hipLaunchKernelGGL((gfeat_tile_batched_kernel<OT, CPL, 2>), dim3(blocks),
-                           dim3(64 * b.waves), lds, s, b);
-    else
+static hipError_t tile_batched_launch(const BatchArgs& b0, hipStream_t s) {
+    if (b0.lps_shift == 6) {
+        const u32 heavy = b0.tile_split - b0.tile_begin;
+        const u32 light = b0.tile_end - b0.tile_split;
+        const u32 blocks = heavy + (light + 3) / 4;
+        if (blocks == 0) return hipSuccess;
+        const size_t lds = tile_lds_bytes<CPL>(4, 6, b0.G, heavy > 0);
+        mark_begin("gfeat_tile_batched", s);
+        hipLaunchKernelGGL((gfeat_tile_batched_kernel<OT, CPL>), dim3(blocks), dim3(256), lds, s,
+                           b0);
+        mark_end(s);
+        return hipGetLastError();
+    }
+    const u32 split[3] = {b0.tile_begin, b0.tile_split, b0.tile_end};
+    for (int part = 0; part < 2; ++part) {
+        BatchArgs b = b0;
+        b.tile_begin = split[part];
+        b.tile_end = split[part + 1];
+        b.waves = part == 0 ? 4 : 1;
+        const u32 spw = 64u >> b.lps_shift;
+        const u32 blocks = (b.tile_end - b.tile_begin + spw - 1) / spw;
+        if (blocks == 0) continue;
+        const size_t lds = tile_lds_bytes<CPL>(b.waves, b.lps_shift, b.G, b.waves > 1);
+        mark_begin(b.waves > 1 ? "gfeat_tile_batched_coarse" : "gfeat_tile_batched", s);
         hipLaunchKernelGGL((gfeat_tile_batched_group_kernel<OT, CPL>), dim3(blocks),
                            dim3(64 * b.waves), lds, s, b);
-    mark_end(s);
-    return hipGetLastError();
+        mark_end(s);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_gfeat_tiles_batched(const BatchArgs& b, int out_dtype, int cpl, hipStream_t s) {
