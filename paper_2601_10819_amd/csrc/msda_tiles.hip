@@ -534,16 +534,19 @@ __device__ __forceinline__ void gfeat_tile_body(const TileArgs& t, const u32 gt,
 // (tile_split - tile_begin) * B) first, a block of 4 waves each, then the
 // light ones, 4 per block, one wave each; the light blocks fill the CUs
 // around the long coarse ones instead of waiting for them to drain.
+constexpr int kTileBlockWaves = 4;
+
 template <class OT, int CPL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(64 * kTileBlockWaves) __attribute__((amdgpu_waves_per_eu(4, 8)))
 gfeat_tile_kernel(TileArgs t) {
+    constexpr int BW = kTileBlockWaves;
     const u32 heavy = (t.tile_split - t.tile_begin) * (u32)t.B;
     const int wave = uniform((int)(threadIdx.x >> 6));
     if (blockIdx.x < heavy)
-        gfeat_tile_body<OT, CPL, true, true, 4>(t, blockIdx.x, 4, wave);
+        gfeat_tile_body<OT, CPL, true, true, 4>(t, blockIdx.x, BW, wave);
     else
-        gfeat_tile_body<OT, CPL, true, true, 2>(t, heavy + (blockIdx.x - heavy) * 4u + (u32)wave,
-                                                1, 0);
+        gfeat_tile_body<OT, CPL, true, true, 2>(
+            t, heavy + (blockIdx.x - heavy) * (u32)BW + (u32)wave, 1, 0);
 }
 
 // Narrower lane groups: spw tiles per wave, t.waves waves sharing them.
@@ -610,15 +613,16 @@ __device__ __forceinline__ void gfeat_tile_batched_body(const BatchArgs& b, cons
 // As gfeat_tile_kernel: the heavy tiles ([tile_begin, tile_split)) 4 waves
 // each, then the light ones 4 per block, one wave each.
 template <class OT, int CPL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(64 * kTileBlockWaves) __attribute__((amdgpu_waves_per_eu(4, 8)))
 gfeat_tile_batched_kernel(BatchArgs b) {
+    constexpr int BW = kTileBlockWaves;
     const u32 heavy = b.tile_split - b.tile_begin;
     const int wave = uniform((int)(threadIdx.x >> 6));
     if (blockIdx.x < heavy)
-        gfeat_tile_batched_body<OT, CPL, true, 4>(b, blockIdx.x, 4, wave);
+        gfeat_tile_batched_body<OT, CPL, true, 4>(b, blockIdx.x, BW, wave);
     else
         gfeat_tile_batched_body<OT, CPL, true, 2>(
-            b, heavy + (blockIdx.x - heavy) * 4u + (u32)wave, 1, 0);
+            b, heavy + (blockIdx.x - heavy) * (u32)BW + (u32)wave, 1, 0);
 }
 
 template <class OT, int CPL>
@@ -649,11 +653,13 @@ static hipError_t tile_launch(const TileArgs& t0, hipStream_t s) {
     if (t0.lps_shift == 6) {
         const u32 heavy = (t0.tile_split - t0.tile_begin) * B;
         const u32 light = (t0.tile_end - t0.tile_split) * B;
-        const u32 blocks = heavy + (light + 3) / 4;
+        constexpr int BW = kTileBlockWaves;
+        const u32 blocks = heavy + (light + BW - 1) / BW;
         if (blocks == 0) return hipSuccess;
-        const size_t lds = tile_lds_bytes<CPL>(4, 6, t0.G, heavy > 0);
+        const size_t lds = tile_lds_bytes<CPL>(BW, 6, t0.G, heavy > 0);
         mark_begin("gfeat_tile_kernel", s);
-        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL>), dim3(blocks), dim3(256), lds, s, t0);
+        hipLaunchKernelGGL((gfeat_tile_kernel<OT, CPL>), dim3(blocks), dim3(64 * BW), lds, s,
+                           t0);
         mark_end(s);
         return hipGetLastError();
     }
@@ -682,12 +688,13 @@ static hipError_t tile_batched_launch(const BatchArgs& b0, hipStream_t s) {
     if (b0.lps_shift == 6) {
         const u32 heavy = b0.tile_split - b0.tile_begin;
         const u32 light = b0.tile_end - b0.tile_split;
-        const u32 blocks = heavy + (light + 3) / 4;
+        constexpr int BW = kTileBlockWaves;
+        const u32 blocks = heavy + (light + BW - 1) / BW;
         if (blocks == 0) return hipSuccess;
-        const size_t lds = tile_lds_bytes<CPL>(4, 6, b0.G, heavy > 0);
+        const size_t lds = tile_lds_bytes<CPL>(BW, 6, b0.G, heavy > 0);
         mark_begin("gfeat_tile_batched", s);
-        hipLaunchKernelGGL((gfeat_tile_batched_kernel<OT, CPL>), dim3(blocks), dim3(256), lds, s,
-                           b0);
+        hipLaunchKernelGGL((gfeat_tile_batched_kernel<OT, CPL>), dim3(blocks), dim3(64 * BW), lds,
+                           s, b0);
         mark_end(s);
         return hipGetLastError();
     }
