@@ -149,6 +149,22 @@ int resolve_order(const msda_desc* d, bool can_view) {
     return can_view && views >= msda::kSlots ? MSDA_ORDER_VIEW : MSDA_ORDER_ANCHOR;
 }
 
+// LDS one workgroup may use on the current device (160 KB on gfx950), the
+// attribute read once per device; 0 if it cannot be read.
+size_t device_lds_limit() {
+    static int max_lds[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (max_lds[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess || v <= 0)
+            v = -1;
+        max_lds[dev] = v;
+    }
+    return max_lds[dev] > 0 ? (size_t)max_lds[dev] : 0;
+}
+
 // Validates everything and chooses the launch shape for the given order;
 // fills `a` except pointers.
 msda_status prepare(const msda_desc* d, int order, msda::OpArgs* a, int* cpl_out,
@@ -208,11 +224,14 @@ msda_status prepare(const msda_desc* d, int order, msda::OpArgs* a, int* cpl_out
         return order == MSDA_ORDER_VIEW ? msda::lds_bytes_view(*a, w) : msda::lds_bytes_for(*a, w);
     };
     // a chosen (not requested) wave count shrinks until the staging fits
+    // 64 KiB (a quarter of the CU's LDS or less: 4 workgroups per CU); a
+    // requested one may use what the device allows a workgroup
     if (!(d->tile && d->tile->waves_per_anchor))
         while (waves > 1 && lds_of(waves) > 65536) waves /= 2;
-    const size_t lds = lds_of(waves);
-    if (lds > 65536)
-        return fail(MSDA_ERR_UNSUPPORTED, "launch needs %zu bytes of LDS (limit 65536)", lds);
+    // (64 KiB, every gfx9 device's minimum, if the device cannot be asked)
+    const size_t lds = lds_of(waves), limit = device_lds_limit() ? device_lds_limit() : 65536;
+    if (lds > limit)
+        return fail(MSDA_ERR_UNSUPPORTED, "launch needs %zu bytes of LDS (limit %zu)", lds, limit);
     *cpl_out = cpl;
     *waves_out = waves;
     return MSDA_OK;
@@ -521,17 +540,7 @@ VisibleWs visible_layout(const msda_desc* d, size_t at) {
 // limit (looked up once per device; no bucket sort if that fails).
 // Whether a bucket-sort block of ap records fits the current device's LDS.
 static bool bucket_lds_fits(uint64_t ap) {
-    static int max_lds[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
-    if (max_lds[dev] == 0) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
-                hipSuccess || v <= 0)
-            v = -1;
-        max_lds[dev] = v;
-    }
-    return max_lds[dev] > 0 && msda::bucket_sort_lds_bytes((uint32_t)ap) <= (size_t)max_lds[dev];
+    return msda::bucket_sort_lds_bytes((uint32_t)ap) <= device_lds_limit();
 }
 
 // Whether the region tables' cells of every region (bilinear cells and the

@@ -314,14 +314,16 @@ __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(siz
 
 // One wave's LDS staging slot for a chunk of up to J (keypoint, camera)
 // pairs of one anchor: per pair its index p*N + n among the anchor's pairs
-// and its camera, its L*G weights, and the taps and bilinear fractions of
-// its L samples.
+// and its camera, its L*G weights, and the taps of its L samples; for the
+// backward also each sample's location-derivative factors
+// (W(1-ly), W ly, H(1-lx), H lx): d(blend)/dx = W((1-ly)(F01-F00) +
+// ly(F11-F10)) and d(blend)/dy = H((1-lx)(F10-F00) + lx(F11-F01)).
 struct StageSlot {
     u32* src;
     u32* cam;
     float* w;
     Taps* taps;
-    float2* frac;
+    float4* dk;
 };
 
 // Levels per pair in the staged taps: L rounded up to a multiple of 4, so the
@@ -334,7 +336,7 @@ __host__ __device__ constexpr int padded_levels(int L) { return (L + 3) & ~3; }
 __host__ __device__ constexpr size_t wave_stage_bytes(int J, int L, int G) {
     return align16((size_t)J * 8) + align16((size_t)J * L * G * 4) +
            (size_t)J * padded_levels(L) * sizeof(Taps) +
-           align16((size_t)J * padded_levels(L) * sizeof(float2));
+           (size_t)J * padded_levels(L) * sizeof(float4);
 }
 
 __device__ __forceinline__ StageSlot stage_slot(unsigned char* work, int wave, int J, int L,
@@ -347,7 +349,7 @@ __device__ __forceinline__ StageSlot stage_slot(unsigned char* work, int wave, i
     s.w = reinterpret_cast<float*>(p);
     p += align16((size_t)J * L * G * 4);
     s.taps = reinterpret_cast<Taps*>(p);
-    s.frac = reinterpret_cast<float2*>(s.taps + (size_t)J * padded_levels(L));
+    s.dk = reinterpret_cast<float4*>(s.taps + (size_t)J * padded_levels(L));
     return s;
 }
 
@@ -479,7 +481,7 @@ __device__ __forceinline__ void stage_chunk(const StageSlot& s, const Order& ord
                 t.cw[c] = 0.f;
             }
             s.taps[i] = t;
-            if constexpr (FRACS) s.frac[i] = make_float2(0.f, 0.f);
+            if constexpr (FRACS) s.dk[i] = make_float4(0.f, 0.f, 0.f, 0.f);
             continue;
         }
         const u32 src = s.src[jj];
@@ -492,7 +494,8 @@ __device__ __forceinline__ void stage_chunk(const StageSlot& s, const Order& ord
         }
         s.taps[i] = t;
         if constexpr (FRACS) {
-            s.frac[i] = make_float2(cr.lx, cr.ly);
+            const float fw = (float)gm.W, fh = (float)gm.H;
+            s.dk[i] = make_float4(fw * (1.f - cr.ly), fw * cr.ly, fh * (1.f - cr.lx), fh * cr.lx);
             if (rec.key) {
                 const u32 smp = rec.base + src * (u32)L + (u32)l;
                 const u32 local = cr.valid ? (u32)(cr.y0 + 1) * (u32)(gm.W + 1) + (u32)(cr.x0 + 1)

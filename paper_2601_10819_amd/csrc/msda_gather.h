@@ -130,10 +130,9 @@ __device__ __forceinline__ void bwd_chunk_w(const OpArgs& a, const StageSlot& st
     constexpr int kOffToAcc = FT::kBytes == 4 ? 2 : FT::kBytes == 2 ? 1 : 0;
     for (int jj = q.sub; jj < nj; jj += q.spw) {
         const u32 src = st.src[jj];
-        const int n = (int)st.cam[jj];
         const float* wj = st.w + jj * LG + q.g;
         const Taps* tj = st.taps + jj * padded_levels(L);
-        const float2* fj = st.frac + jj * padded_levels(L);
+        const float4* kj = st.dk + jj * padded_levels(L);
         float gx = 0.f, gy = 0.f;
         for (int l = 0; l < L; ++l) {
             const Taps t = tj[l];
@@ -172,12 +171,11 @@ __device__ __forceinline__ void bwd_chunk_w(const OpArgs& a, const StageSlot& st
                     if (!FULL && dot) *dot = fmaf(wl, tw, *dot);
                 }
             }
-            // d val / dx = hy (F01 - F00) + ly (F11 - F10); x = u W - 0.5
-            const Geo gm = geo[n * L + l];
-            const float2 fr = fj[l];
-            const float hx = 1.f - fr.x, hy = 1.f - fr.y;
-            gx += (float)gm.W * wl * (hy * (d[1] - d[0]) + fr.y * (d[3] - d[2]));
-            gy += (float)gm.H * wl * (hx * (d[2] - d[0]) + fr.x * (d[3] - d[1]));
+            // d val / dx = W ((1-ly)(F01 - F00) + ly (F11 - F10)) (x = u W - 0.5),
+            // and d val / dy alike, the factors staged per sample
+            const float4 k = kj[l];
+            gx = fmaf(wl, k.x * (d[1] - d[0]) + k.y * (d[3] - d[2]), gx);
+            gy = fmaf(wl, k.z * (d[2] - d[0]) + k.w * (d[3] - d[1]), gy);
         }
         if (FULL || x.glout) {
             gx = group_sum_w<LPS>(gx, q.lps);
