@@ -330,6 +330,21 @@ struct BucketSortArgs {
     u32 cells_per_item;
 };
 
+// n / d for n < 2^15 and 1 <= d <= 2^15 as (n * m) >> k, with k = 15 +
+// ceil(log2 d) and m = ceil(2^k / d): m < 2^16 + 1, so n * m fits 32 bits,
+// and the error term stays below 1/d, so the quotient is exact.
+struct Div15 {
+    u32 m;
+    int k;
+    __device__ explicit Div15(u32 d) {
+        int l = 0;
+        while ((1u << l) < d) ++l;
+        k = 15 + l;
+        m = (u32)(((1ull << k) + d - 1) / d);
+    }
+    __device__ u32 operator()(u32 n) const { return (n * m) >> k; }
+};
+
 size_t bucket_sort_lds_bytes(u32 ap) {
     return ((size_t)ap + (size_t)kBucketWaves * kMaxDigits + kMaxDigits + 32) * 4;
 }
@@ -397,7 +412,7 @@ __device__ __forceinline__ void bucket_sort_core(const u32* __restrict__ keys, u
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = kBucketPosBits + pass * bits;
         for (int i = tid; i < kBucketWaves * digits; i += kBucketThreads)
-            m.wcount[(i / digits) * kMaxDigits + (i % digits)] = 0u;
+            m.wcount[(i >> bits) * kMaxDigits + (i & (digits - 1))] = 0u;
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -522,9 +537,10 @@ __global__ void __launch_bounds__(kBucketThreads) bucket_sort_kernel(BucketSortA
     const u32 n_ = (u32)p.N, L_ = (u32)p.L;
     const u32 nr = (u32)r / L_, lr = (u32)r % L_;
     u32* vals = p.vals + (size_t)k * ap;
+    const Div15 by_p((u32)p.P);
     for (u32 i = (u32)tid; i < ap; i += kBucketThreads) {
         const u32 pos = m.buf[i] & ((1u << kBucketPosBits) - 1u);
-        const u32 a = pos / (u32)p.P, pp = pos - a * (u32)p.P;
+        const u32 a = by_p(pos), pp = pos - a * (u32)p.P;
         // sample index of (b, a, pp, nr, lr)
         vals[i] = ((((u32)b * (u32)p.A + a) * (u32)p.P + pp) * n_ + nr) * L_ + lr;
     }
@@ -558,9 +574,10 @@ __global__ void __launch_bounds__(kBucketThreads) bucket_sort_batched_kernel(Bat
     if (ap > 0) bucket_sort_core<E>(b.rec_key + base, ap, nkeys, m);
 
     const u32 nr = r / L, lr = r % L;
+    const Div15 by_p(P);
     for (u32 i = (u32)threadIdx.x; i < ap; i += kBucketThreads) {
         const u32 pos = m.buf[i] & ((1u << kBucketPosBits) - 1u);
-        const u32 a = pos / P, pp = pos - a * P;
+        const u32 a = by_p(pos), pp = pos - a * P;
         vals[base + i] = b.t.sample_start[s] + ((a * P + pp) * N + nr) * L + lr;
     }
     bucket_cell_starts(m.buf, ap, nkeys, base, off + b.t.cell_start[k]);
