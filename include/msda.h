@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define MSDA_ABI_VERSION 7
+#define MSDA_ABI_VERSION 8
 
 typedef enum msda_status {
     MSDA_OK = 0,
@@ -96,6 +96,10 @@ typedef enum msda_dtype {
                                  summing in sample order: deterministic, no atomics   */
 #define MSDA_SCATTER_ATOMIC 2 /* FP32 float atomics into an accumulator: run-to-run
                                  differences in the last bits                        */
+#define MSDA_SCATTER_SORTED_GLOBAL 3 /* SORTED, with the records always grouped by one
+                                 global radix sort instead of per-region buckets in
+                                 LDS: the same grad_feat bit for bit (a reference for
+                                 tests and a fallback)                               */
 
 /* msda_tile.order: how the gathers split the work */
 #define MSDA_ORDER_AUTO 0   /* the library's choice                                    */

@@ -28,7 +28,7 @@ MSDA_DETERMINISTIC = 1
 MSDA_WEIGHT_LOGITS = 2
 MSDA_WEIGHTS_BF16 = 4
 
-ABI_VERSION = 7
+ABI_VERSION = 8
 
 # Every symbol include/msda.h declares.
 EXPORTS = (
@@ -48,6 +48,7 @@ EXPORTS = (
 MSDA_SCATTER_AUTO = 0
 MSDA_SCATTER_SORTED = 1
 MSDA_SCATTER_ATOMIC = 2
+MSDA_SCATTER_SORTED_GLOBAL = 3
 
 MSDA_ORDER_AUTO = 0
 MSDA_ORDER_ANCHOR = 1

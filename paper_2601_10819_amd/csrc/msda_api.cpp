@@ -618,9 +618,10 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
     if (desc->feat_dtype == MSDA_FP8_E4M3)
         return fail(MSDA_ERR_UNSUPPORTED, "the backward takes FP32 or BF16 features (not FP8)");
     const int mode = scatter_mode(desc);
-    if (mode != MSDA_SCATTER_SORTED && mode != MSDA_SCATTER_ATOMIC)
+    if (mode != MSDA_SCATTER_SORTED && mode != MSDA_SCATTER_SORTED_GLOBAL &&
+        mode != MSDA_SCATTER_ATOMIC)
         return fail(MSDA_ERR_UNSUPPORTED, "unknown scatter mode %d", mode);
-    if (visible && mode != MSDA_SCATTER_SORTED)
+    if (visible && mode == MSDA_SCATTER_ATOMIC)
         return fail(MSDA_ERR_UNSUPPORTED, "the visible-view backward has the sorted form only");
     if (visible && desc->tile && desc->tile->order == MSDA_ORDER_ANCHOR)
         return fail(MSDA_ERR_UNSUPPORTED, "the visible-view form runs in view order only");
@@ -635,7 +636,7 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
     for (int c : {4, 2, 1})
         if (cpl_fits(c, a.C, a.G)) { rcpl = c; break; }
     bool cover = true;
-    if (grad_feat && mode == MSDA_SCATTER_SORTED) {
+    if (grad_feat && mode != MSDA_SCATTER_ATOMIC) {
         if (!regions_disjoint(desc, &cover))
             return fail(MSDA_ERR_UNSUPPORTED,
                         "sorted grad_feat needs disjoint regions (use MSDA_SCATTER_ATOMIC)");
@@ -738,10 +739,11 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
         cell_start = reinterpret_cast<uint32_t*>(ws + W.cell_start);
         tile_start = reinterpret_cast<uint32_t*>(ws + W.tile_start);
         tile_region = reinterpret_cast<uint32_t*>(ws + W.tile_region);
-        // dense records sorted per (batch item, region) bucket in LDS when
-        // the buckets fit (that launch also writes the region tables), else
-        // the global radix sort
-        if (!visible && bucket_sort_fits(desc)) a.rec_bucket_ap = (uint32_t)(a.A * a.P);
+        // records sorted per (batch item, region) bucket in LDS when the
+        // buckets fit (that launch also writes the region tables), else, or
+        // when asked, by the global radix sort
+        if (mode != MSDA_SCATTER_SORTED_GLOBAL && bucket_sort_fits(desc))
+            a.rec_bucket_ap = (uint32_t)(a.A * a.P);
         if (!a.rec_bucket_ap &&
             (e = msda::launch_region_tables(spatial_shapes, a.N, a.L, cell_start, tile_start,
                                             tile_region, s)) != hipSuccess)
@@ -760,6 +762,8 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
     }
     uint32_t* rec_count = nullptr;
     float* vt = nullptr;
+    uint32_t* vis_place = nullptr;
+    uint32_t* vis_items = nullptr;
     if (visible) {
         // invisible pairs take no part: their gradients are zero
         if (a.A > 0 && grad_weights &&
@@ -773,8 +777,8 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
             return hip_fail(e, "zero grad_sampling_loc");
         float* grad_score = fuse ? fuse->grad_score : nullptr;   // written whole below
         if (a.A > 0 && (grad_feat || grad_sampling_loc || grad_weights || grad_score)) {
-            uint32_t* place = reinterpret_cast<uint32_t*>(ws + VW.place);
-            uint32_t* items = reinterpret_cast<uint32_t*>(ws + VW.items);
+            uint32_t* place = vis_place = reinterpret_cast<uint32_t*>(ws + VW.place);
+            uint32_t* items = vis_items = reinterpret_cast<uint32_t*>(ws + VW.items);
             rec_count = reinterpret_cast<uint32_t*>(ws + VW.rec_count);
             const size_t V = (size_t)a.B * a.N * a.A;
             if (fuse) {
@@ -790,8 +794,9 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
                                                 s)) != hipSuccess ||
                 (e = msda::launch_backward_visible(
                      a, desc->feat_dtype, cpl, waves, msda::lds_bytes_view(a, waves), items,
-                     place + V, grad_feat ? reinterpret_cast<uint32_t*>(ws + W.vals_a) : nullptr,
-                     vt, item_dot, s)) != hipSuccess)
+                     place, place + V,
+                     grad_feat ? reinterpret_cast<uint32_t*>(ws + W.vals_a) : nullptr, vt,
+                     item_dot, s)) != hipSuccess)
                 return hip_fail(e, "msda_backward_visible launch");
             if (grad_score &&
                 (e = msda::launch_grad_score(grad_out, fuse->out, visible, fuse->score, place,
@@ -811,7 +816,8 @@ static msda_status backward_impl(const void* feat, const int32_t* spatial_shapes
         sorted = reinterpret_cast<uint32_t*>(ws + W.vals_a);
         e = msda::launch_bucket_sort(reinterpret_cast<uint32_t*>(ws + W.keys_a), spatial_shapes,
                                      a.B, a.N, a.L, a.A, a.P, (uint32_t)cells, sorted, off,
-                                     cell_start, tile_start, tile_region, s);
+                                     cell_start, tile_start, tile_region, vis_place, vis_items,
+                                     s);
     } else {
         e = msda::launch_sort_records(reinterpret_cast<uint32_t*>(ws + W.keys_a),
                                       reinterpret_cast<uint32_t*>(ws + W.keys_b),
@@ -1448,7 +1454,8 @@ msda_status msda_backward_batched(const msda_batch* b, void* workspace, size_t w
     // one bucket-sort block (sorted by launch_bucket_sort_batched), else in
     // sample order with batch-global cells (the global radix sort)
     const bool bucketed = gf && p.keys_fit && p.max_ap <= msda::kBucketMaxRecords &&
-                          bucket_lds_fits(p.max_ap);
+                          bucket_lds_fits(p.max_ap) &&
+                          !(b->tile && b->tile->scatter == MSDA_SCATTER_SORTED_GLOBAL);
     if (gf) {
         a.rec_key = reinterpret_cast<uint32_t*>(ws + w.keys_a);
         a.rec_frac = reinterpret_cast<float2*>(ws + w.frac);

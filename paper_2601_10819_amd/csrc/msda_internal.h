@@ -247,14 +247,21 @@ size_t sort_scratch_words(uint32_t n);
 // = B*N*L*ap. Also writes the region tables of launch_region_tables
 // (cell_start, tile_start, tile_region). Requires ap <= kBucketMaxRecords,
 // (H+1)(W+1) + 1 <= kBucketMaxKeys for every region, N*L <= 1024, and
-// bucket_sort_lds_bytes(ap) of LDS.
+// bucket_sort_lds_bytes(ap) of LDS. The visible-view form (place, items
+// non-null: the exclusive scan of the visible flags over the view-major items
+// (b*N + n)*A + a and the compacted item list): bucket (b, n, l) holds the
+// cnt*P records of the cnt visible anchors of (b, n), at s0*P*L + l*cnt*P
+// with s0 = place[(b*N + n)*A], in (anchor, keypoint) order, ap = A*P
+// bounding cnt*P; vals and off as above, off[B*cells_per_item] = the number
+// of visible records.
 constexpr uint32_t kBucketMaxRecords = 1u << 15;
 constexpr uint32_t kBucketMaxKeys = 1u << 17;
 size_t bucket_sort_lds_bytes(uint32_t ap);
 hipError_t launch_bucket_sort(const uint32_t* keys, const int32_t* shapes, int32_t B, int32_t N,
                               int32_t L, int32_t A, int32_t P, uint32_t cells_per_item,
                               uint32_t* vals, uint32_t* off, uint32_t* cell_start,
-                              uint32_t* tile_start, uint32_t* tile_region, hipStream_t s);
+                              uint32_t* tile_start, uint32_t* tile_region, const uint32_t* place,
+                              const uint32_t* items, hipStream_t s);
 // The batched form's record sort: bucket k = the batch's region k (scene s,
 // region r of it), A_s*P records at sample_start[s] + r*A_s*P, keyed by
 // local cell; writes the sorted global sample indices to vals (bucket k's
@@ -283,9 +290,9 @@ hipError_t launch_forward_visible(const OpArgs& a, int dtype, int cpl, int waves
                                   float* part, hipStream_t s);
 // item_dot (or nullptr): per item, <grad_out, the anchor's feature in the view>.
 hipError_t launch_backward_visible(const OpArgs& a, int dtype, int cpl, int waves, size_t lds,
-                                   const uint32_t* items, const uint32_t* count,
-                                   uint32_t* rec_val, const float* vt, float* item_dot,
-                                   hipStream_t s);
+                                   const uint32_t* items, const uint32_t* place,
+                                   const uint32_t* count, uint32_t* rec_val, const float* vt,
+                                   float* item_dot, hipStream_t s);
 // Fused weight generation (per-group softmax of logits, BF16 weights).
 // stats[(b*A + a)*G + g] = (max, 1 / sum of exp(logit - max)) over the
 // anchor's P*N*L logits of group g; logits FP32 or bfloat16 bit patterns.

@@ -294,6 +294,7 @@ __global__ void __launch_bounds__(256) fwd_visible_reduce(const float* __restric
 
 template <class FT, int CPL>
 __global__ void __launch_bounds__(512) msda_bwd_visible_kernel(OpArgs a, const u32* items,
+                                                               const u32* place,
                                                                const u32* count,
                                                                u32* rec_val, const float* vt,
                                                                float* item_dot) {
@@ -309,8 +310,20 @@ __global__ void __launch_bounds__(512) msda_bwd_visible_kernel(OpArgs a, const u
     for_each_visible_item(a, items, count, [&](u32 i, int b, int an, int n) {
         float go[CPL];
         BwdAnchor x = bwd_anchor_ctx<FT, CPL>(a, b * a.A + an, q, go);
-        x.rec.val = rec_val;
-        x.rec.cbase = i * (u32)(a.P * a.L);
+        if (a.rec_bucket_ap) {
+            // records per (b, n, l) bucket (launch_bucket_sort's visible-view
+            // layout): the cnt visible anchors of (b, n) from item s0 on,
+            // level-major; stage_chunk adds (n*L + l)*bucket_ap + p, so the
+            // base drops n*L*bucket_ap (modulo 2^32)
+            const u32 bn = (u32)(b * a.N + n), P = (u32)a.P, L = (u32)a.L;
+            const u32 s0 = place[(size_t)bn * a.A];
+            x.rec.bucket_ap = (place[(size_t)(bn + 1) * a.A] - s0) * P;
+            x.rec.bucket_base = s0 * P * L + (i - s0) * P - (u32)n * L * x.rec.bucket_ap;
+            x.rec.val = nullptr;
+        } else {
+            x.rec.val = rec_val;
+            x.rec.cbase = i * (u32)(a.P * a.L);
+        }
         const ViewOrder order{a.N, a.P, n};
         const float scale = vt ? vt[((size_t)b * a.A + an) * a.N + n] : 1.f;
         float dot = 0.f;
@@ -355,11 +368,11 @@ static hipError_t fwd_visible_launch(const OpArgs& a, int waves, size_t lds, con
 
 template <class FT, int CPL>
 static hipError_t bwd_visible_launch(const OpArgs& a, int waves, size_t lds, const u32* items,
-                                     const u32* count, u32* rec_val, const float* vt,
-                                     float* item_dot, hipStream_t s) {
+                                     const u32* place, const u32* count, u32* rec_val,
+                                     const float* vt, float* item_dot, hipStream_t s) {
     mark_begin("msda_bwd_visible_kernel", s);
     hipLaunchKernelGGL((msda_bwd_visible_kernel<FT, CPL>), dim3(visible_blocks(waves)),
-                       dim3(64 * waves), lds, s, a, items, count, rec_val, vt, item_dot);
+                       dim3(64 * waves), lds, s, a, items, place, count, rec_val, vt, item_dot);
     mark_end(s);
     return hipGetLastError();
 }
@@ -401,12 +414,13 @@ hipError_t launch_forward_visible(const OpArgs& a, int dtype, int cpl, int waves
 }
 
 hipError_t launch_backward_visible(const OpArgs& a, int dtype, int cpl, int waves, size_t lds,
-                                   const u32* items, const u32* count, u32* rec_val,
-                                   const float* vt, float* item_dot, hipStream_t s) {
+                                   const u32* items, const u32* place, const u32* count,
+                                   u32* rec_val, const float* vt, float* item_dot, hipStream_t s) {
     switch (dtype * 100 + cpl) {
 #define MSDA_CASE(D, T, K) \
         case D * 100 + K: \
-            return bwd_visible_launch<T, K>(a, waves, lds, items, count, rec_val, vt, item_dot, s);
+            return bwd_visible_launch<T, K>(a, waves, lds, items, place, count, rec_val, vt, \
+                                            item_dot, s);
         MSDA_CASE(kF32, TF32, 1) MSDA_CASE(kF32, TF32, 2) MSDA_CASE(kF32, TF32, 4)
         MSDA_CASE(kBF16, TBF16, 2) MSDA_CASE(kBF16, TBF16, 4) MSDA_CASE(kBF16, TBF16, 8)
         MSDA_CASE(kF16, TF16, 2) MSDA_CASE(kF16, TF16, 4) MSDA_CASE(kF16, TF16, 8)

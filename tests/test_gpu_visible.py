@@ -9,7 +9,7 @@ import torch
 
 from helpers import (FWD_F32_MAXREL, FWD_F32_TOL, GRAD_F32_MAXREL, GRAD_F32_TOL, anchor_subset,
                      assert_close, host, normwise, to_device)
-from paper_2601_10819_amd import synth
+from paper_2601_10819_amd import _lib, synth
 
 pytestmark = pytest.mark.gpu
 
@@ -135,11 +135,12 @@ def test_all_visible_equals_dense(ops, dtype):
 
 @pytest.mark.parametrize("which", ["cam64", "train16"])
 def test_bucket_sort_equals_global_sort(ops, which):
-    """The dense backward sorts its records per (batch item, region) bucket
-    in LDS; the visible-view form, with every pair visible, sorts the same
-    records with the global radix sort. Every cell must list the same
-    records in the same order, so grad_feat is bitwise the same -- at the
-    64-camera scene (11,700 records per bucket) and the 16-camera training
+    """The backward sorts its records per (batch item, region) bucket in LDS;
+    MSDA_SCATTER_SORTED_GLOBAL sorts the same records with the global radix
+    sort instead. Every cell must list the same records in the same order,
+    so grad_feat is bitwise the same -- dense, and in the visible-view form
+    with every pair visible (which equals the dense form) -- at the
+    64-camera scene's bucket size (11,700 records) and the 16-camera training
     workload (2 batch items, 23,400 per bucket, a quarter of them outside
     every level), BF16."""
     p = synth.cam64(seed=2, anchors=900, cams=16) if which == "cam64" else synth.train16(seed=2)
@@ -147,11 +148,49 @@ def test_bucket_sort_equals_global_sort(ops, which):
     feat, layout, loc, w = to_device(p, torch.bfloat16)
     v = torch.ones(p.batch, p.num_anchors, p.num_cams, dtype=torch.uint8, device="cuda")
     go = synth.grad_out_like(p, seed=5).cuda()
+    glob = {"scatter": _lib.MSDA_SCATTER_SORTED_GLOBAL}
     gf_v, _, _ = ops.backward_visible(feat, layout, loc, w, v, go)
+    gf_vg, _, _ = ops.backward_visible(feat, layout, loc, w, v, go, tile=glob)
     gf_d, _, _ = ops.backward(feat, layout, loc, w, go, need_loc=False, need_w=False,
                               tile={"order": "view"})
+    gf_dg, _, _ = ops.backward(feat, layout, loc, w, go, need_loc=False, need_w=False,
+                               tile=dict(glob, order="view"))
     torch.cuda.synchronize()
-    assert torch.equal(gf_v, gf_d)
+    assert torch.equal(gf_d, gf_dg), "dense: bucket vs global"
+    assert torch.equal(gf_v, gf_vg), "visible: bucket vs global"
+    assert torch.equal(gf_v, gf_d), "visible (all) vs dense"
+
+
+@pytest.mark.parametrize("fused", [False, True], ids=["visible", "fused"])
+def test_visible_buckets_equal_global_sort(ops, fused):
+    """Visible-view records bucketed per (batch item, camera, level) from the
+    visible-item scan: regions receive uneven record counts (a camera sees
+    none, one sees every anchor, the rest about a quarter), and the bucketed
+    sort must give every output bitwise equal to the global radix sort's --
+    for the visible-view and the fused form, B = 2, BF16."""
+    p = synth.small(seed=81, B=2, cams=12, levels=((24, 40), (12, 20), (6, 10), (3, 5)),
+                    C=256, G=8, A=300, P=13)
+    print(f"visible buckets: {p.dims()} fused={fused}", flush=True)
+    feat, layout, loc, w = to_device(p, torch.bfloat16)
+    gen = torch.Generator().manual_seed(82)
+    v = (torch.rand(p.batch, p.num_anchors, p.num_cams, generator=gen) < 0.25).to(torch.uint8)
+    v[:, :, 3] = 0
+    v[:, :, 7] = 1
+    v = v.cuda()
+    go = synth.grad_out_like(p, seed=83).cuda()
+    glob = {"scatter": _lib.MSDA_SCATTER_SORTED_GLOBAL}
+    if fused:
+        score = torch.rand(p.batch, p.num_anchors, p.num_cams, generator=gen).cuda()
+        out = ops.forward_fused(feat, layout, loc, w, v, score)
+        g_b = ops.backward_fused(feat, layout, loc, w, v, score, out, go)
+        g_g = ops.backward_fused(feat, layout, loc, w, v, score, out, go, tile=glob)
+    else:
+        g_b = ops.backward_visible(feat, layout, loc, w, v, go)
+        g_g = ops.backward_visible(feat, layout, loc, w, v, go, tile=glob)
+    torch.cuda.synchronize()
+    assert len(g_b) == len(g_g)
+    for i, (a, b) in enumerate(zip(g_b, g_g)):
+        assert torch.equal(a, b), f"output {i}"
 
 
 def test_nothing_visible(ops):
