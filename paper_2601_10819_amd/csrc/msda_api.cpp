@@ -1111,13 +1111,20 @@ namespace {
 struct BatchWs {
     size_t anchor_start, sample_start, region_start, cell_start, slot_scene, slot_region,
         tile_start, magic, magic_shift, keys_a, keys_b, vals_a, vals_b, frac, off, scratch, part,
-        total;
+        wstats, wscratch, w32, total;
+};
+
+// Weight-flag buffers of a batch: softmax statistics per anchor of every
+// scene, one softmax scratch (the per-scene launches run in stream order and
+// share it), and for the backward the FP32 weights of every sample.
+struct BatchWeights {
+    uint64_t stats_bytes, scratch_bytes, w32_bytes;
 };
 
 // part_bytes: the view-order forward's per-slot partial sums (always part of
 // the forward's workspace, so that the order can change without resizing).
 BatchWs batch_layout(uint64_t S, uint64_t regions, uint64_t nsamp, uint64_t ncells, bool records,
-                     uint64_t part_bytes = 0) {
+                     uint64_t part_bytes = 0, const BatchWeights& wb = BatchWeights{}) {
     BatchWs w = {};
     size_t at = 0;
     auto take = [&](size_t bytes) { const size_t here = at; at += align256(bytes); return here; };
@@ -1140,6 +1147,9 @@ BatchWs batch_layout(uint64_t S, uint64_t regions, uint64_t nsamp, uint64_t ncel
         w.scratch = take(msda::sort_scratch_words((uint32_t)nsamp) * 4);
     }
     if (part_bytes) w.part = take(part_bytes);
+    if (wb.stats_bytes) w.wstats = take(wb.stats_bytes);
+    if (wb.scratch_bytes) w.wscratch = take(wb.scratch_bytes);
+    if (wb.w32_bytes) w.w32 = take(wb.w32_bytes);
     w.total = at;
     return w;
 }
@@ -1166,8 +1176,8 @@ msda_status plan_batch(const msda_batch* b, bool backward, BatchPlan* p) {
                     msda::kMaxBatchScenes);
     if (!b->scenes || !b->host_scenes || !b->host_spatial_shapes || !b->host_level_start_index)
         return fail(MSDA_ERR_INVALID_ARGUMENT, "scene table or host mirrors are NULL");
-    if (b->flags & kWeightFlags)
-        return fail(MSDA_ERR_UNSUPPORTED, "the batched form takes no weight flags");
+    if (b->flags & ~(MSDA_DETERMINISTIC | kWeightFlags))
+        return fail(MSDA_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", (unsigned)b->flags);
     *p = BatchPlan{};
     p->keys_fit = true;
     const int eb = elem_bytes(b->feat_dtype);
@@ -1311,6 +1321,84 @@ void fill_batch_args(const msda_batch* b, const BatchPlan& p, char* ws, const Ba
     a->view_cams = p.view_cams;
 }
 
+// The weight-flag buffers of a batch (all zero without a weight flag).
+BatchWeights batch_weights(const msda_batch* b, const BatchPlan& p, bool backward) {
+    BatchWeights w{};
+    if (b->flags & MSDA_WEIGHT_LOGITS) {
+        w.stats_bytes = p.anchors * (uint64_t)b->groups * sizeof(float2);
+        for (int sc = 0; sc < b->num_scenes; ++sc) {
+            const msda_scene& h = b->host_scenes[sc];
+            if (h.num_anchors > 0)
+                w.scratch_bytes = std::max<uint64_t>(
+                    w.scratch_bytes,
+                    msda::softmax_scratch_bytes(h.num_anchors,
+                                                b->num_points * h.num_cams * b->num_levels,
+                                                b->groups));
+        }
+    }
+    if (backward && (b->flags & kWeightFlags)) w.w32_bytes = p.samples * (uint64_t)b->groups * 4;
+    return w;
+}
+
+// Under a weight flag, per scene with anchors (in stream order): the softmax
+// statistics of its logits, and for the backward its FP32 weights (softmax
+// weights, or BF16 weights widened) at its samples' place, which the
+// batched kernels then read in place of the scene's weights.
+msda_status batch_weight_prep(const msda_batch* b, char* ws, const BatchWs& w, bool backward,
+                              msda::BatchArgs* a, hipStream_t s) {
+    const bool logits = b->flags & MSDA_WEIGHT_LOGITS, wbf16 = b->flags & MSDA_WEIGHTS_BF16;
+    if (!logits && !wbf16) return MSDA_OK;
+    float2* stats = logits ? reinterpret_cast<float2*>(ws + w.wstats) : nullptr;
+    float2* part = logits ? reinterpret_cast<float2*>(ws + w.wscratch) : nullptr;
+    float* w32 = backward ? reinterpret_cast<float*>(ws + w.w32) : nullptr;
+    const int G = b->groups;
+    uint64_t a0 = 0, s0 = 0;
+    for (int sc = 0; sc < b->num_scenes; ++sc) {
+        const msda_scene& h = b->host_scenes[sc];
+        const int A = h.num_anchors, PNL = b->num_points * h.num_cams * b->num_levels;
+        if (A > 0) {
+            float2* st = logits ? stats + a0 * G : nullptr;
+            hipError_t e = hipSuccess;
+            if (logits && (e = msda::launch_softmax_stats(h.weights, wbf16, A, PNL, G, part, st,
+                                                          s)) != hipSuccess)
+                return hip_fail(e, "batched softmax statistics");
+            if (w32 && (e = msda::launch_weights_f32(h.weights, wbf16, st, A, PNL, G,
+                                                     w32 + s0 * G, s)) != hipSuccess)
+                return hip_fail(e, "batched FP32 weights");
+        }
+        a0 += (uint64_t)(A > 0 ? A : 0);
+        s0 += (uint64_t)(A > 0 ? A : 0) * (uint64_t)PNL;
+    }
+    if (backward) {
+        a->w32 = w32;
+    } else {
+        a->wstats = stats;
+        a->w_bf16 = wbf16 ? 1 : 0;
+    }
+    return MSDA_OK;
+}
+
+// With logits, grad_weights as the gather leaves it (with respect to the
+// softmax weights) mapped in place to the logits' gradient, per scene.
+msda_status batch_softmax_grad(const msda_batch* b, char* ws, const BatchWs& w, hipStream_t s) {
+    if (!(b->flags & MSDA_WEIGHT_LOGITS)) return MSDA_OK;
+    const float* w32 = reinterpret_cast<const float*>(ws + w.w32);
+    float* part = reinterpret_cast<float*>(ws + w.wscratch);
+    const int G = b->groups;
+    uint64_t s0 = 0;
+    for (int sc = 0; sc < b->num_scenes; ++sc) {
+        const msda_scene& h = b->host_scenes[sc];
+        const int A = h.num_anchors, PNL = b->num_points * h.num_cams * b->num_levels;
+        if (A > 0 && h.grad_weights) {
+            const hipError_t e = msda::launch_softmax_grad(w32 + s0 * G, h.grad_weights, A, PNL, G,
+                                                           part, s);
+            if (e != hipSuccess) return hip_fail(e, "batched gradient through the softmax");
+        }
+        s0 += (uint64_t)(A > 0 ? A : 0) * (uint64_t)PNL;
+    }
+    return MSDA_OK;
+}
+
 size_t batch_lds(const msda_batch* b, const BatchPlan& p) {
     msda::OpArgs o = {};
     o.N = p.max_cams;
@@ -1360,7 +1448,8 @@ size_t msda_batched_workspace_size(const msda_batch* b, int32_t backward) {
     bool gf = false, gl = false, gw = false;
     if (backward && batch_grads(b, &gf, &gl, &gw) != MSDA_OK) return 0;
     return batch_layout(b->num_scenes, p.regions, p.samples, p.cells, backward && gf,
-                        backward ? 0 : p.part_bytes).total;
+                        backward ? 0 : p.part_bytes, batch_weights(b, p, backward != 0))
+        .total;
 }
 
 msda_status msda_forward_batched(const msda_batch* b, void* workspace, size_t workspace_bytes,
@@ -1369,7 +1458,7 @@ msda_status msda_forward_batched(const msda_batch* b, void* workspace, size_t wo
     msda_status st = plan_batch(b, false, &p);
     if (st != MSDA_OK) return st;
     const BatchWs w = batch_layout(b->num_scenes, p.regions, p.samples, p.cells, false,
-                                   p.part_bytes);
+                                   p.part_bytes, batch_weights(b, p, false));
     if (!workspace || workspace_bytes < w.total)
         return fail(MSDA_ERR_WORKSPACE, "workspace of %zu bytes needed", w.total);
     if (!aligned(workspace, 256)) return fail(MSDA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
@@ -1381,6 +1470,8 @@ msda_status msda_forward_batched(const msda_batch* b, void* workspace, size_t wo
     hipError_t e = msda::launch_batch_tables(a, false, s);
     if (e != hipSuccess) return hip_fail(e, "batch tables");
     if (p.anchors == 0) return ok();
+    if ((st = batch_weight_prep(b, static_cast<char*>(workspace), w, false, &a, s)) != MSDA_OK)
+        return st;
     if (p.order == MSDA_ORDER_VIEW) {
         const size_t vlds = msda::batch_view_lds(p.view_cams, b->num_levels, a.pairs_per_chunk,
                                                  b->groups, p.view_waves_fwd);
@@ -1437,7 +1528,8 @@ msda_status msda_backward_batched(const msda_batch* b, void* workspace, size_t w
                 return fail(MSDA_ERR_UNSUPPORTED, "scene %d: grad_feat needs disjoint regions", s);
         }
     }
-    const BatchWs w = batch_layout(b->num_scenes, p.regions, p.samples, p.cells, gf);
+    const BatchWs w = batch_layout(b->num_scenes, p.regions, p.samples, p.cells, gf, 0,
+                                   batch_weights(b, p, true));
     if (!workspace || workspace_bytes < w.total)
         return fail(MSDA_ERR_WORKSPACE, "workspace of %zu bytes needed", w.total);
     if (!aligned(workspace, 256)) return fail(MSDA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
@@ -1450,6 +1542,7 @@ msda_status msda_backward_batched(const msda_batch* b, void* workspace, size_t w
     const hipStream_t s = (hipStream_t)stream;
     hipError_t e = msda::launch_batch_tables(a, true, s);
     if (e != hipSuccess) return hip_fail(e, "batch tables");
+    if (p.anchors > 0 && (st = batch_weight_prep(b, ws, w, true, &a, s)) != MSDA_OK) return st;
     // grad_feat records bucketed per (scene, region) when every bucket fits
     // one bucket-sort block (sorted by launch_bucket_sort_batched), else in
     // sample order with batch-global cells (the global radix sort)
@@ -1490,7 +1583,7 @@ msda_status msda_backward_batched(const msda_batch* b, void* workspace, size_t w
         }
         if (e != hipSuccess) return hip_fail(e, "msda_backward_batched launch");
     }
-    if (!gf) return ok();
+    if (!gf) return p.anchors > 0 ? batch_softmax_grad(b, ws, w, s) : ok();
     uint32_t* sorted = nullptr;
     uint32_t* off = reinterpret_cast<uint32_t*>(ws + w.off);
     if (bucketed)
@@ -1513,7 +1606,7 @@ msda_status msda_backward_batched(const msda_batch* b, void* workspace, size_t w
     a.tile_end = (uint32_t)p.tiles;
     if ((e = msda::launch_gfeat_tiles_batched(a, b->feat_dtype, rcpl, s)) != hipSuccess)
         return hip_fail(e, "batched grad_feat tile reduction");
-    return ok();
+    return p.anchors > 0 ? batch_softmax_grad(b, ws, w, s) : ok();
 }
 
 namespace {

@@ -579,7 +579,11 @@ __device__ __forceinline__ OpArgs scene_view(const BatchArgs& b, int s, int feat
     a.shapes = sc.spatial_shapes;
     a.starts = sc.level_start_index;
     a.loc = sc.sampling_loc;
-    a.w = sc.weights;
+    // under a weight flag: the FP32 weights (backward), or the scene's
+    // logits / BF16 weights with its anchors' softmax statistics (forward)
+    a.w = b.w32 ? b.w32 + (size_t)b.t.sample_start[s] * (size_t)b.G : sc.weights;
+    a.w_bf16 = b.w32 ? 0 : b.w_bf16;
+    a.wstats = (b.w32 || !b.wstats) ? nullptr : b.wstats + (size_t)b.t.anchor_start[s] * (size_t)b.G;
     a.level_scale = b.level_scale;
     a.grad_out = sc.grad_out;
     a.out = sc.out;

@@ -122,6 +122,12 @@ struct BatchArgs {
     uint32_t* rec_key;            // backward, grad_feat records (or nullptr)
     float2* rec_frac;
     int32_t rec_bucketed;         // records written per (scene, region) bucket (launch_bucket_sort_batched)
+    // weight flags: forward, softmax statistics of every anchor (scenes in
+    // order; w holds logits) and BF16 weights; backward, FP32 weights of
+    // every sample (scenes in order), read in place of each scene's weights
+    const float2* wstats;
+    int32_t w_bf16;
+    const float* w32;
     // tiled reduction
     const uint32_t* vals;
     const uint32_t* off;

@@ -592,8 +592,8 @@ __device__ __forceinline__ void gfeat_tile_batched_body(const BatchArgs& b, cons
     v.vals = b.vals;
     v.off = b.off;
     v.frac = b.rec_frac;
-    v.w = sc.weights;
-    v.w16 = (b.G & 3) == 0 && ((uintptr_t)sc.weights & 15) == 0;
+    v.w = b.w32 ? b.w32 + (size_t)b.t.sample_start[s] * (size_t)b.G : sc.weights;
+    v.w16 = (b.G & 3) == 0 && ((uintptr_t)v.w & 15) == 0;
     v.grad_out = sc.grad_out;
     v.grad_feat = sc.grad_feat;
     v.nrec = b.total_samples;

@@ -494,11 +494,14 @@ class SceneBatch:
     upstream gradient into ``grad_out[s]`` before backward().
 
     scenes: list of (feat [R, C], Layout, sampling_loc [A, P, Ncam, 2],
-    weights [A, P, Ncam, L, G]) on the device.
+    weights [A, P, Ncam, L, G]) on the device; weights FP32 or BF16 (the same
+    in every scene). logits: the weights are per-group logits, turned into
+    the softmax over each anchor's (keypoint, camera, level) entries inside,
+    and grad_w is the logits' gradient (FP32).
     """
 
     def __init__(self, scenes, level_scale=None, need_feat=True, need_loc=True, need_w=True,
-                 tile=None, deterministic=False):
+                 tile=None, deterministic=False, logits: bool = False):
         lib = _lib.load()
         if not scenes:
             raise ValueError("empty batch")
@@ -508,6 +511,7 @@ class SceneBatch:
         self.L, self.G = w0.shape[-2], w0.shape[-1]
         self.P = loc0.shape[1]
         self.dtype = feat0.dtype
+        self.w_dtype = w0.dtype
         self.scenes = scenes
         self.level_scale = level_scale
         self.out, self.grad_out, self.grad_feat, self.grad_loc, self.grad_w = [], [], [], [], []
@@ -522,6 +526,8 @@ class SceneBatch:
                 raise ValueError("scene tensors: feat [R,C], loc [A,P,Ncam,2], w [A,P,Ncam,L,G]")
             if feat.dtype != self.dtype or feat.shape[1] != self.C:
                 raise ValueError(f"scene {s}: feat dtype / channels differ from scene 0")
+            if w.dtype != self.w_dtype or w.dtype not in (torch.float32, torch.bfloat16):
+                raise ValueError(f"scene {s}: weights must be FP32 or BF16, as scene 0's")
             A = loc.shape[0]
             # keypoints, levels and groups are shared by the batch (the kernels
             # read every scene's locations and weights with scene 0's sizes)
@@ -535,7 +541,7 @@ class SceneBatch:
             go = torch.zeros(A, self.C, device=self.device, dtype=torch.float32)
             gf = torch.empty_like(feat) if need_feat else None
             gl = torch.empty_like(loc) if need_loc else None
-            gw = torch.empty_like(w) if need_w else None
+            gw = torch.empty(w.shape, dtype=torch.float32, device=w.device) if need_w else None
             self.out.append(out)
             self.grad_out.append(go)
             self.grad_feat.append(gf)
@@ -565,7 +571,9 @@ class SceneBatch:
         b.host_spatial_shapes = ctypes.cast(self._host_shapes, ctypes.POINTER(ctypes.c_void_p))
         b.host_level_start_index = ctypes.cast(self._host_starts, ctypes.POINTER(ctypes.c_void_p))
         b.level_scale = level_scale.data_ptr() if level_scale is not None else None
-        b.flags = _lib.MSDA_DETERMINISTIC if deterministic else 0
+        b.flags = ((_lib.MSDA_DETERMINISTIC if deterministic else 0) |
+                   (_lib.MSDA_WEIGHT_LOGITS if logits else 0) |
+                   (_lib.MSDA_WEIGHTS_BF16 if self.w_dtype == torch.bfloat16 else 0))
         self._batch = b
         self._tile = _lib.MsdaTile()
         if tile == "auto":

@@ -291,10 +291,19 @@ def test_batched_validation(lib):
     t = _lib.MsdaTile(0, 0, 0, _lib.MSDA_SCATTER_ATOMIC)
     b.tile = ctypes.pointer(t)
     expect(lib, lib.msda_backward_batched(ctypes.byref(b), FAKE, 1 << 30, None), UNS, "sorted")
-    # the batched form takes no weight flags
+    # unknown flags are rejected; the weight flags are taken, and grow the
+    # workspace by the softmax statistics (and, backward, FP32 weights)
     b = batch_desc(geos, [4, 7])
+    b.flags = 1 << 20
+    expect(lib, lib.msda_forward_batched(ctypes.byref(b), FAKE, 1 << 30, None), INV, "flags")
+    b = batch_desc(geos, [4, 7])
+    plain = [lib.msda_batched_workspace_size(ctypes.byref(b), k) for k in (0, 1)]
     b.flags = _lib.MSDA_WEIGHT_LOGITS
-    expect(lib, lib.msda_forward_batched(ctypes.byref(b), FAKE, 1 << 30, None), UNS, "weight flags")
+    logit = [lib.msda_batched_workspace_size(ctypes.byref(b), k) for k in (0, 1)]
+    b.flags = _lib.MSDA_WEIGHTS_BF16
+    bf16 = [lib.msda_batched_workspace_size(ctypes.byref(b), k) for k in (0, 1)]
+    assert 0 < plain[0] < logit[0] and plain[1] < logit[1], (plain, logit)
+    assert bf16[0] == plain[0] and bf16[1] > plain[1], (plain, bf16)
     # an order the batched form does not know
     b = batch_desc(geos, [4, 7])
     t = _lib.MsdaTile(0, 0, 7, 0)

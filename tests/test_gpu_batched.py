@@ -257,6 +257,38 @@ def test_batched_record_sort_forms_bitwise(ops, big):
             assert torch.equal(gw[0], batch.grad_w[s]), f"scene {s} grad_w"
 
 
+@pytest.mark.parametrize("tile", [TILE, VIEW_TILE], ids=["anchor", "view"])
+@pytest.mark.parametrize("wkind", ["logits_f32", "logits_bf16", "weights_bf16"])
+def test_batched_weight_flags_equal_single_calls(ops, wkind, tile):
+    """Weight flags in the batched form: per-group softmax of logits (FP32 or
+    BF16), or BF16 weights. Per scene the statistics, the FP32 weights of the
+    backward and the gradient through the softmax are the single call's, so
+    every output is bitwise equal to per-scene calls with the same flag (one
+    scene has no anchors)."""
+    probs = small_batch(seed=9, scenes=5, max_cams=9)
+    logits = wkind.startswith("logits")
+    wdt = torch.float32 if wkind == "logits_f32" else torch.bfloat16
+    print("case", wkind, tile, [p.dims() for p in probs], flush=True)
+    scenes = [(f, lay, loc, (w * 3.0 if logits else w).to(wdt).contiguous())
+              for f, lay, loc, w in to_scenes(ops, probs, torch.bfloat16)]
+    batch = ops.SceneBatch(scenes, tile=tile, logits=logits)
+    gen = torch.Generator(device="cuda").manual_seed(10)
+    for go in batch.grad_out:
+        go.normal_(generator=gen)
+    batch.forward()
+    batch.backward()
+    torch.cuda.synchronize()
+    for s, (feat, layout, loc, w) in enumerate(scenes):
+        out = ops.forward(feat[None], layout, loc[None], w[None], tile=tile, logits=logits)
+        gf, gl, gw = ops.backward(feat[None], layout, loc[None], w[None], batch.grad_out[s][None],
+                                  tile=tile, logits=logits)
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], batch.out[s]), f"scene {s} out"
+        assert torch.equal(gf[0], batch.grad_feat[s]), f"scene {s} grad_feat"
+        assert torch.equal(gl[0], batch.grad_loc[s]), f"scene {s} grad_loc"
+        assert torch.equal(gw[0], batch.grad_w[s]), f"scene {s} grad_w"
+
+
 def test_batched_rejects_uneven_shared_sizes(ops):
     """Keypoints, levels, channels and groups are shared by a batch: a scene
     that differs is rejected before anything runs."""
