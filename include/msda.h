@@ -88,7 +88,10 @@ typedef enum msda_dtype {
 /* The visible-view and fused forms take both flags (their workspaces grow
  * accordingly; with logits, the softmax runs over every camera's entries,
  * visible or not, and the logits' gradient reaches invisible entries through
- * its normalisation); the batched form takes neither (UNSUPPORTED). */
+ * its normalisation). The batched form takes both too (msda_batch.flags,
+ * the same for every scene): its workspace then also holds the softmax
+ * statistics of every anchor and, for the backward, FP32 weights of every
+ * sample; each scene's grad_weights is FP32. */
 
 /* msda_tile.scatter: how the backward forms grad_feat */
 #define MSDA_SCATTER_AUTO 0   /* the library's choice (currently SORTED)                */
@@ -386,7 +389,8 @@ typedef struct msda_batch {
     const int32_t* const* host_spatial_shapes;     /* per scene, host mirror            */
     const int32_t* const* host_level_start_index;  /* per scene, host mirror            */
     const float* level_scale;         /* device [L], FP8 only                            */
-    uint32_t flags;                   /* MSDA_DETERMINISTIC ...                          */
+    uint32_t flags;                   /* MSDA_DETERMINISTIC, MSDA_WEIGHT_LOGITS,
+                                         MSDA_WEIGHTS_BF16 (all scenes alike)            */
     const msda_tile* tile;            /* NULL = built-in choice                          */
 } msda_batch;
 
