@@ -611,7 +611,10 @@ __device__ __forceinline__ void gfeat_tile_batched_body(const BatchArgs& b, cons
 }
 
 // As gfeat_tile_kernel: the heavy tiles ([tile_begin, tile_split)) 4 waves
-// each, then the light ones 4 per block, one wave each.
+// each, then the light ones 4 per block, one wave each. Both walk with 2
+// grad_out rows in flight: with the batch's scene lookups, 4 for the heavy
+// tiles spilled 64 bytes under the 128-VGPR cap (the 12-scene batch's step:
+// 9.37 ms with 4, 9.22 ms with 2).
 template <class OT, int CPL>
 __global__ void __launch_bounds__(64 * kTileBlockWaves) __attribute__((amdgpu_waves_per_eu(4, 8)))
 gfeat_tile_batched_kernel(BatchArgs b) {
@@ -619,7 +622,7 @@ gfeat_tile_batched_kernel(BatchArgs b) {
     const u32 heavy = b.tile_split - b.tile_begin;
     const int wave = uniform((int)(threadIdx.x >> 6));
     if (blockIdx.x < heavy)
-        gfeat_tile_batched_body<OT, CPL, true, 4>(b, blockIdx.x, BW, wave);
+        gfeat_tile_batched_body<OT, CPL, true, 2>(b, blockIdx.x, BW, wave);
     else
         gfeat_tile_batched_body<OT, CPL, true, 2>(
             b, heavy + (blockIdx.x - heavy) * (u32)BW + (u32)wave, 1, 0);
