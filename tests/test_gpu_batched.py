@@ -8,7 +8,7 @@ import torch
 
 from helpers import (BF16_TOL, FWD_F32_MAXREL, FWD_F32_TOL, GRAD_F32_MAXREL, GRAD_F32_TOL,
                      anchor_subset, assert_close, host, normwise, oracle_backward_subset)
-from paper_2601_10819_amd import synth
+from paper_2601_10819_amd import _lib, synth
 
 pytestmark = pytest.mark.gpu
 
@@ -255,6 +255,30 @@ def test_batched_record_sort_forms_bitwise(ops, big):
             assert torch.equal(gf[0], batch.grad_feat[s]), f"scene {s} grad_feat"
             assert torch.equal(gl[0], batch.grad_loc[s]), f"scene {s} grad_loc"
             assert torch.equal(gw[0], batch.grad_w[s]), f"scene {s} grad_w"
+
+
+def test_batched_global_sort_on_request_bitwise(ops):
+    """MSDA_SCATTER_SORTED_GLOBAL sends the batch's records through the
+    global radix sort instead of the per-(scene, region) buckets: every
+    output bitwise the same (BF16, view order, one scene without anchors)."""
+    probs = small_batch(seed=11, scenes=5, max_cams=9)
+    print("case", [p.dims() for p in probs], flush=True)
+    scenes = to_scenes(ops, probs, torch.bfloat16)
+    res = []
+    for scatter in (0, _lib.MSDA_SCATTER_SORTED_GLOBAL):
+        batch = ops.SceneBatch(scenes, tile=dict(VIEW_TILE, scatter=scatter))
+        gen = torch.Generator(device="cuda").manual_seed(12)
+        for go in batch.grad_out:
+            go.normal_(generator=gen)
+        batch.forward()
+        batch.backward()
+        torch.cuda.synchronize()
+        res.append(batch)
+    a, b = res
+    for s in range(len(scenes)):
+        assert torch.equal(a.grad_feat[s], b.grad_feat[s]), f"scene {s} grad_feat"
+        assert torch.equal(a.grad_loc[s], b.grad_loc[s]), f"scene {s} grad_loc"
+        assert torch.equal(a.grad_w[s], b.grad_w[s]), f"scene {s} grad_w"
 
 
 @pytest.mark.parametrize("tile", [TILE, VIEW_TILE], ids=["anchor", "view"])
